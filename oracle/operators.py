@@ -1,0 +1,199 @@
+"""Assembled (CSR) operators of the MADP hierarchy (oracle; test infrastructure).
+
+Grid convention: a level holds nx*ny vertex-centred nodes including the
+boundary nodes (Sec. 2.1); node (i, j) has index j*nx + i (x fastest).
+All matrices are scipy.sparse CSR in complex128.
+
+Readings of the paper this module fixes (listed with reasons in the design notes):
+  * Sommerfeld ghost point (Sec. 2.1, eq. ghost_sommerfeld): the ghost behind a
+    boundary node b, mirrored from the interior neighbour m, is
+    u_ghost = u_m + 2 i H k_b u_b, with H the spacing of the grid concerned.
+    Boundary rows are not rescaled (reading R2).
+  * CSLP (Sec. 3.1, eq. CSLP def): sigma = beta1 + i beta2 multiplies only the
+    k^2 term; the Sommerfeld ghost keeps the unshifted k (reading R9).
+  * Coarse levels l >= 2 (Sec. 3.3): interior and near-boundary rows use the
+    Galerkin-derived stencils with the wavenumber read at each stencil point,
+    (K u)_I = sum K[a,b] k^2_{I+(a,b)} u_{I+(a,b)} (reading R6).  A stencil
+    point one step outside the grid in exactly one direction is a ghost point
+    with the Sommerfeld value above at spacing h_l and zero wavenumber; points
+    further out, or outside in both directions, are zero (reading R8).
+    Boundary-node rows are s_l times the standard 5-point operator at spacing
+    h_l (reading R7), s_l = 4^(l-1).
+  * Deflation vectors: Z = p (x) p, p = [1,4,6,4,1]/8, truncated at the
+    boundary; Z^T is its exact transpose (readings R3, R4).
+  * Multigrid transfers: full weighting (1/16)[1 2 1; 2 4 2; 1 2 1] with
+    out-of-grid fine values zero, bilinear interpolation, wavenumber by
+    injection (reading R10).
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from . import stencils
+
+_NEIGHBOURS = ((-1, 0), (1, 0), (0, -1), (0, 1))
+
+
+def coarse_size(n, factor):
+    """Nodes of a grid with (n-1) intervals coarsened by `factor` (must divide)."""
+    assert (n - 1) % factor == 0
+    return (n - 1) // factor + 1
+
+
+def inject(field, nx, ny):
+    """Injection of a nodal field onto the next coarser grid: f_c(J) = f(2J)."""
+    f = np.asarray(field).reshape(ny, nx)
+    return np.ascontiguousarray(f[::2, ::2]).ravel()
+
+
+def five_point(nx, ny, H, k, sigma, scale=1.0):
+    """scale * ( H^-2 (4u - sum of 4 neighbours) - sigma k^2 u ) with a Sommerfeld
+    ghost point behind every boundary side (Sec. 2.1, eqs. helm operator h and
+    ghost_sommerfeld; with sigma = beta1 + i beta2 it is the CSLP, Sec. 3.1).
+
+    `k` is the nodal wavenumber (not squared).  Rows of corner nodes receive a
+    ghost from both directions.
+    """
+    k = np.asarray(k, dtype=np.float64).reshape(ny, nx)
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    idx = jj * nx + ii
+    rows, cols, vals = [], [], []
+    off = -scale / H**2
+    diag = scale * (4.0 / H**2 - sigma * k**2) + 0j
+    for di, dj in _NEIGHBOURS:
+        ni, nj = ii + di, jj + dj
+        inside = (ni >= 0) & (ni < nx) & (nj >= 0) & (nj < ny)
+        rows.append(idx[inside]); cols.append((nj * nx + ni)[inside])
+        vals.append(np.full(inside.sum(), off, dtype=np.complex128))
+        out = ~inside
+        # ghost u_g = u_mirror + 2 i H k_b u_b ; mirror is the opposite neighbour
+        mi, mj = ii - di, jj - dj
+        rows.append(idx[out]); cols.append((mj * nx + mi)[out])
+        vals.append(np.full(out.sum(), off, dtype=np.complex128))
+        diag = diag + np.where(out, off * 2j * H * k, 0.0)
+    rows.append(idx.ravel()); cols.append(idx.ravel()); vals.append(diag.ravel())
+    N = nx * ny
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(N, N)).tocsr()
+
+
+def wide_stencil(nx, ny, h, level, k, sigma):
+    """Re-discretised coarse operator of deflation level `level` >= 2 (Sec. 3.3).
+
+    h is the FINEST spacing (the printed stencils are in units of h^-2); the
+    level spacing is h_l = 2^(l-1) h.  Interior/near-boundary rows:
+        sum_{a,b} ( h^-2 L[b,a] - sigma K[b,a] k^2_{I+(a,b)} ) u_{I+(a,b)}
+    with the ghost/zero rule for points outside the grid; boundary rows are
+    s_l * five_point at spacing h_l.
+    """
+    L, K = stencils.stencils_2d_float(level)
+    r = L.shape[0] // 2
+    hl = h * 2 ** (level - 1)
+    sl = float(stencils.level_scale(level))
+    k2d = np.asarray(k, dtype=np.float64).reshape(ny, nx)
+    N = nx * ny
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    interior = (ii > 0) & (ii < nx - 1) & (jj > 0) & (jj < ny - 1)
+    ii_in, jj_in = ii[interior], jj[interior]
+    I_in = jj_in * nx + ii_in
+    rows, cols, vals = [], [], []
+    for b in range(-r, r + 1):
+        for a in range(-r, r + 1):
+            lap = L[b + r, a + r] / h**2
+            wav = K[b + r, a + r]
+            if lap == 0.0 and wav == 0.0:
+                continue
+            pi, pj = ii_in + a, jj_in + b
+            xin = (pi >= 0) & (pi < nx)
+            yin = (pj >= 0) & (pj < ny)
+            inside = xin & yin
+            P = pj * nx + pi
+            kp = np.where(inside, k2d[np.clip(pj, 0, ny - 1), np.clip(pi, 0, nx - 1)], 0.0)
+            rows.append(I_in[inside]); cols.append(P[inside])
+            vals.append((lap - sigma * wav * kp[inside] ** 2).astype(np.complex128))
+            # ghost: one step outside in x only
+            for side_x, bnd_i, mir_i in ((-1, 0, 1), (nx, nx - 1, nx - 2)):
+                g = (pi == side_x) & yin
+                if g.any():
+                    pjg = pj[g]
+                    kb = k2d[pjg, bnd_i]
+                    rows.append(I_in[g]); cols.append(pjg * nx + mir_i)
+                    vals.append(np.full(g.sum(), lap, dtype=np.complex128))
+                    rows.append(I_in[g]); cols.append(pjg * nx + bnd_i)
+                    vals.append(lap * 2j * hl * kb)
+            # ghost: one step outside in y only
+            for side_y, bnd_j, mir_j in ((-1, 0, 1), (ny, ny - 1, ny - 2)):
+                g = (pj == side_y) & xin
+                if g.any():
+                    pig = pi[g]
+                    kb = k2d[bnd_j, pig]
+                    rows.append(I_in[g]); cols.append(mir_j * nx + pig)
+                    vals.append(np.full(g.sum(), lap, dtype=np.complex128))
+                    rows.append(I_in[g]); cols.append(bnd_j * nx + pig)
+                    vals.append(lap * 2j * hl * kb)
+    W = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(N, N)).tocsr()
+    B = five_point(nx, ny, hl, k, sigma, scale=sl)
+    bmask = (~interior).ravel()
+    D = sp.diags(bmask.astype(np.float64))
+    Dc = sp.diags((~bmask).astype(np.float64))
+    return (Dc @ W + D @ B).tocsr()
+
+
+def level_operator(nx, ny, h, level, k, sigma):
+    """Operator of deflation level `level`: the 5-point operator on the finest
+    level, the Galerkin-derived wide stencil on coarser levels."""
+    if level == 1:
+        return five_point(nx, ny, h, k, sigma, 1.0)
+    return wide_stencil(nx, ny, h, level, k, sigma)
+
+
+def _bezier_1d(nc):
+    """1-D quadratic-Bezier deflation interpolation, fine (2nc-1) x coarse nc."""
+    nf = 2 * (nc - 1) + 1
+    p = [1 / 8, 4 / 8, 6 / 8, 4 / 8, 1 / 8]
+    rows, cols, vals = [], [], []
+    for J in range(nc):
+        for s in range(-2, 3):
+            i = 2 * J + s
+            if 0 <= i < nf:
+                rows.append(i); cols.append(J); vals.append(p[s + 2])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+
+
+def deflation_z(nxc, nyc):
+    """Z from the coarse grid (nxc x nyc) to the fine grid: p (x) p, truncated."""
+    return sp.kron(_bezier_1d(nyc), _bezier_1d(nxc)).tocsr().astype(np.complex128)
+
+
+def _bilinear_1d(nc):
+    nf = 2 * (nc - 1) + 1
+    rows, cols, vals = [], [], []
+    for J in range(nc):
+        rows.append(2 * J); cols.append(J); vals.append(1.0)
+        if 2 * J - 1 >= 0:
+            rows.append(2 * J - 1); cols.append(J); vals.append(0.5)
+        if 2 * J + 1 < nf:
+            rows.append(2 * J + 1); cols.append(J); vals.append(0.5)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+
+
+def bilinear_prolongation(nxc, nyc):
+    """Bilinear interpolation coarse -> fine (multigrid prolongation)."""
+    return sp.kron(_bilinear_1d(nyc), _bilinear_1d(nxc)).tocsr().astype(np.complex128)
+
+
+def _full_weighting_1d(nf):
+    nc = coarse_size(nf, 2)
+    rows, cols, vals = [], [], []
+    for J in range(nc):
+        for a, w in ((-1, 0.25), (0, 0.5), (1, 0.25)):
+            if 0 <= 2 * J + a < nf:
+                rows.append(J); cols.append(2 * J + a); vals.append(w)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nc, nf))
+
+
+def full_weighting(nxf, nyf):
+    """Full-weighting restriction fine -> coarse with weights (1/16)[1 2 1;2 4 2;1 2 1]
+    centred at fine node 2J; fine nodes outside the grid contribute zero.  The
+    2-D weights are the outer product of the 1-D weights [1, 2, 1]/4."""
+    return sp.kron(_full_weighting_1d(nyf), _full_weighting_1d(nxf)).tocsr().astype(np.complex128)
