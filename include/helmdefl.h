@@ -1,0 +1,176 @@
+/*
+ * helmdefl.h -- C ABI of the MI355X (gfx950) implementation of the matrix-free
+ * multilevel deflation preconditioner (MADP) inside flexible GMRES for the
+ * heterogeneous 2-D Helmholtz equation  -Lap u - k(x,y)^2 u = b
+ * (Chen, Dwarka, Vuik, arXiv 2412.04980).
+ *
+ * Problem statement (Sec. 2 and 2.1 of the paper): rectangle, vertex-centred
+ * uniform grid of nx*ny nodes INCLUDING the boundary nodes, spacing h, 5-point
+ * second-order finite differences, first-order Sommerfeld radiation condition on
+ * all four sides imposed through the ghost point u_ghost = u_mirror + 2 i h k u_b
+ * (eq. ghost_sommerfeld).  The outer solver is FGMRES from a zero initial guess
+ * stopping at ||b - A u||_2 / ||b||_2 <= tol_outer (Sec. 4); the preconditioner
+ * is MADP (Sec. 4.3): Algorithm 1 applied recursively over `levels` levels with
+ * the CSLP  M = -Lap - (beta1 + i beta2) k^2  (eq. CSLP def) approximated by one
+ * multigrid V-cycle on levels 1-2 and by GMRES on coarser levels, the
+ * Galerkin-derived re-discretised coarse stencils of Sec. 3.3 and the
+ * higher-order (quadratic Bezier) deflation vectors.
+ *
+ * Conventions for every entry point
+ *   Layout     node (i, j), 0 <= i < nx (x), 0 <= j < ny (y), index j*nx + i
+ *              (x fastest).  Complex vectors are interleaved (re, im) pairs of
+ *              double (complex128) -- the layout of torch.complex128.
+ *   Ownership  the caller allocates and owns every device buffer (wavenumber
+ *              field, right-hand side, solution, workspace).  The library never
+ *              allocates or frees device memory.  It allocates a small host
+ *              object (hm_problem) and pinned host staging memory, released by
+ *              hm_destroy_problem.  The workspace must outlive the problem.
+ *   Streams    every call takes a hipStream_t (as void*; NULL = default stream)
+ *              and enqueues its work there.  Calls whose control flow depends on
+ *              device results (Krylov stopping tests) synchronise that stream;
+ *              all others are asynchronous.  A problem must be used from one
+ *              stream at a time.
+ *   Errors     return codes only.  < 0: nothing was written to the output;
+ *              > 0: output written with a warning (e.g. not converged).
+ *              hm_last_error() returns a message for the calling thread.
+ */
+#ifndef HELMDEFL_H
+#define HELMDEFL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hm_problem hm_problem;
+
+typedef enum {
+  HM_OK = 0,
+  HM_NOT_CONVERGED = 1,   /* output written; tolerance not met within maxit       */
+  HM_ERR_ARG = -1,        /* invalid argument (size, pointer, parameter)          */
+  HM_ERR_NOMEM = -2,      /* workspace smaller than hm_workspace_bytes()          */
+  HM_ERR_HIP = -3,        /* a HIP runtime call or kernel launch failed           */
+  HM_ERR_STATE = -4       /* call not valid in the problem's current state        */
+} hm_status;
+
+typedef enum { HM_BC_SOMMERFELD = 0 } hm_bc;   /* all four sides (Sec. 2.1) */
+
+typedef enum {
+  HM_FP64 = 0,        /* every step in complex128                                     */
+  HM_MIXED_FP32 = 1   /* preconditioner levels 1-2 in complex64 with FP32 arithmetic;
+                         outer FGMRES (Arnoldi/MGS, Givens, true residual) and the
+                         coarsest-level solve in complex128                           */
+} hm_precision;
+
+typedef struct {
+  int nx, ny;            /* nodes incl. boundary; (n-1) divisible by 2^(levels-1)   */
+  double h;              /* mesh width                                              */
+  int bc;                /* hm_bc                                                   */
+  double beta1, beta2;   /* CSLP shift (Sec. 3.1); MADP uses (1, 0.5) (Sec. 4.3)     */
+  int levels;            /* deflation levels, >= 2 (MADP default 3)                 */
+  double tol_outer;      /* outer relative residual (Sec. 4: 1e-6)                  */
+  double tol_level2;     /* level-2 FGMRES relative tolerance (Sec. 4.3: 0.3)       */
+  double tol_cslp;       /* Krylov CSLP relative tolerance (Sec. 4.2: 0.1)          */
+  double maxit_coef;     /* Krylov CSLP step cap floor(coef * N^(1/4)) (Sec. 4.2: 6) */
+  int outer_restart;     /* outer FGMRES restart length (30)                        */
+  int outer_maxit;       /* outer FGMRES total step cap (300)                       */
+  int level2_maxit;      /* level-2 FGMRES step cap (100)                           */
+  int mg_nu_pre, mg_nu_post;  /* Jacobi sweeps of the CSLP V-cycle (1, 1)           */
+  int precision;         /* hm_precision                                            */
+  int reserved[8];       /* must be zero                                            */
+} hm_config;
+
+typedef struct {
+  int outer_iters;             /* outer FGMRES steps                                 */
+  int level2_iters_total;      /* level-2 FGMRES steps summed over the solve         */
+  int cslp_iters_total;        /* Krylov CSLP steps on the coarsest level, summed     */
+  int mg_coarse_iters_total;   /* GMRES steps of multigrid coarsest solves, summed    */
+  double rel_res_estimate;     /* last Givens estimate |g_{m+1}| / ||b||             */
+  double rel_res_true;         /* ||b - A u|| / ||b|| recomputed in FP64             */
+  double seconds;              /* wall time of the call (host clock)                 */
+} hm_solve_info;
+
+/* Fills *cfg with the MADP configuration of Sec. 4.3 for an nx x ny grid of
+ * spacing h: 3 levels, beta = (1, 0.5), tolerances 1e-6 / 0.3 / 0.1, cap
+ * coefficient 6, restart 30, outer cap 300, level-2 cap 100, V(1,1), FP64. */
+void hm_default_config(hm_config* cfg, int nx, int ny, double h);
+
+/* Device workspace bytes a problem with this configuration needs (256-byte
+ * aligned start required).  Returns 0 if the configuration is invalid. */
+size_t hm_workspace_bytes(const hm_config* cfg);
+
+/* Builds the level hierarchy (Sec. 3.3: sizes n_l = (n-1)/2^(l-1)+1, spacings
+ * 2^(l-1) h, wavenumber injected to coarse grids) and the multigrid
+ * sub-hierarchies of levels 1-2 inside `workspace`.
+ *   k_dev: device, nx*ny doubles, the nodal wavenumber k = 2 pi f / c >= 0
+ *          (Sec. 2, eq. wavenum); read during the call only.
+ *   workspace: device, >= hm_workspace_bytes(cfg) bytes, 256-byte aligned.
+ * Errors: HM_ERR_ARG for invalid cfg or pointers or a non-finite/negative k
+ * (checked on the device), HM_ERR_NOMEM for a short workspace.
+ * Synchronises `stream`. */
+hm_status hm_create_problem(const hm_config* cfg, const double* k_dev, void* workspace,
+                            size_t workspace_bytes, void* stream, hm_problem** out);
+
+/* One application of the finest-level MADP preconditioner x = P v (Algorithm 1
+ * loop body at level 1: Z^T, recursive coarse FGMRES, Z, A, CSLP V-cycle, x=r+t).
+ *   v_dev, x_dev: device, nx*ny complex128, must not alias.
+ * Synchronises `stream` (inner Krylov stopping tests). */
+hm_status hm_precond_apply(hm_problem* p, const void* v_dev, void* x_dev, void* stream);
+
+/* Solves A u = b by MADP-preconditioned FGMRES (Algorithm 1 at level 1 with
+ * restarts), zero initial guess.  b_dev, u_dev: device, nx*ny complex128, no
+ * aliasing.  info may be NULL.  Returns HM_NOT_CONVERGED (u written) when the
+ * tolerance is not met within outer_maxit steps. */
+hm_status hm_fgmres_solve(hm_problem* p, const void* b_dev, void* u_dev, hm_solve_info* info,
+                          void* stream);
+
+/* Component access for parity tests.  Applies one building block in the
+ * problem's precision, reading and writing complex128 device vectors:
+ *   HM_OP_A        level operator: 5-point Helmholtz A (level 1, eq. helm
+ *                  operator h) or re-discretised E_l (l >= 2, Sec. 3.3)  N_l -> N_l
+ *   HM_OP_M        CSLP of the level (same stencils, shifted k^2 term)    N_l -> N_l
+ *   HM_OP_ZT       deflation restriction Z^T, level -> level+1           N_l -> N_{l+1}
+ *   HM_OP_Z        deflation interpolation Z, level+1 -> level           N_{l+1} -> N_l
+ *   HM_OP_VCYCLE   one multigrid V-cycle for M_l (levels 1-2)             N_l -> N_l
+ *   HM_OP_CSLP     the level's CSLP approximation (V-cycle or GMRES)      N_l -> N_l
+ *   HM_OP_PRECOND  the level-l MADP preconditioner (Algorithm 1 body)     N_l -> N_l
+ *   HM_OP_MG_M     multigrid-level operator of M_l at multigrid level sub
+ *   HM_OP_MG_JACOBI  one damped-Jacobi sweep from zero at multigrid level sub
+ *   HM_OP_MG_RESTRICT full weighting, multigrid level sub -> sub+1
+ *   HM_OP_MG_PROLONG  bilinear interpolation, multigrid level sub+1 -> sub
+ * `level` is 1-based; `sub` selects the multigrid level (0 = top) for the
+ * HM_OP_MG_* operations and is ignored otherwise.  Synchronises `stream` for the
+ * Krylov-based operations. */
+enum {
+  HM_OP_A = 0, HM_OP_M = 1, HM_OP_ZT = 2, HM_OP_Z = 3, HM_OP_VCYCLE = 4, HM_OP_CSLP = 5,
+  HM_OP_PRECOND = 6, HM_OP_MG_M = 7, HM_OP_MG_JACOBI = 8, HM_OP_MG_RESTRICT = 9,
+  HM_OP_MG_PROLONG = 10
+};
+hm_status hm_apply_operator(hm_problem* p, int level, int sub, int which, const void* in_dev,
+                            void* out_dev, void* stream);
+
+/* Grid shape of deflation level `level` (1-based) and multigrid level `sub`
+ * below it (sub = 0: the deflation level itself).  HM_ERR_ARG if absent. */
+hm_status hm_level_shape(const hm_problem* p, int level, int sub, int* nx, int* ny);
+
+/* Fixed-count (replay) mode for parity tests.  kind: 0 = level-2 FGMRES,
+ * 1 = coarsest-level Krylov CSLP, 2 = multigrid coarsest GMRES, 3 = outer
+ * FGMRES cycles.  After hm_set_replay, each inner solve of that kind takes
+ * exactly the next count (tolerance test off), making the preconditioner a
+ * fixed map; n = 0 switches replay off.  hm_get_counts copies the counts
+ * recorded since the last hm_reset_counts (at most cap) and stores the total
+ * number recorded in *n. */
+hm_status hm_set_replay(hm_problem* p, int kind, const int* counts, int n);
+hm_status hm_get_counts(const hm_problem* p, int kind, int* counts, int cap, int* n);
+hm_status hm_reset_counts(hm_problem* p);
+
+hm_status hm_destroy_problem(hm_problem* p);
+
+const char* hm_status_string(hm_status s);
+const char* hm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELMDEFL_H */

@@ -1,0 +1,259 @@
+"""Python binding of libhelmdefl, the MI355X (gfx950) implementation of the
+matrix-free multilevel deflation preconditioner (MADP) inside FGMRES for the
+heterogeneous 2-D Helmholtz equation (Chen, Dwarka, Vuik, arXiv 2412.04980).
+
+This module only marshals arguments: every step of the preconditioner and the
+solver runs in the library's HIP kernels.  PyTorch provides device memory and
+the stream.  The entry points carry the names of the C ABI in include/helmdefl.h:
+
+    cfg = default_config(nx, ny, h)
+    prob = create_problem(cfg, k)            # k: torch.float64 on the GPU, nx*ny
+    x = precond_apply(prob, v)               # complex128
+    u, info = fgmres_solve(prob, b)
+    y = apply_operator(prob, level, which, x, sub=0)
+    destroy_problem(prob)
+
+The library is loaded from libhelmdefl.so next to this file (built by
+paper_2412_04980_amd.build); importing this module fails loudly when it is
+missing.  There is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch  # loads the HIP runtime first, so the library binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelmdefl.so")
+
+HM_OK, HM_NOT_CONVERGED = 0, 1
+HM_ERR_ARG, HM_ERR_NOMEM, HM_ERR_HIP, HM_ERR_STATE = -1, -2, -3, -4
+HM_FP64, HM_MIXED_FP32 = 0, 1
+HM_BC_SOMMERFELD = 0
+
+HM_OP_A, HM_OP_M, HM_OP_ZT, HM_OP_Z, HM_OP_VCYCLE, HM_OP_CSLP, HM_OP_PRECOND = range(7)
+HM_OP_MG_M, HM_OP_MG_JACOBI, HM_OP_MG_RESTRICT, HM_OP_MG_PROLONG = 7, 8, 9, 10
+
+KIND_LEVEL2, KIND_CSLP, KIND_MG_COARSE, KIND_OUTER = 0, 1, 2, 3
+
+EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_precond_apply",
+            "hm_fgmres_solve", "hm_apply_operator", "hm_level_shape", "hm_set_replay",
+            "hm_get_counts", "hm_reset_counts", "hm_destroy_problem", "hm_status_string",
+            "hm_last_error"]
+
+
+class HmConfig(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("h", ctypes.c_double),
+                ("bc", ctypes.c_int), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("levels", ctypes.c_int), ("tol_outer", ctypes.c_double),
+                ("tol_level2", ctypes.c_double), ("tol_cslp", ctypes.c_double),
+                ("maxit_coef", ctypes.c_double), ("outer_restart", ctypes.c_int),
+                ("outer_maxit", ctypes.c_int), ("level2_maxit", ctypes.c_int),
+                ("mg_nu_pre", ctypes.c_int), ("mg_nu_post", ctypes.c_int),
+                ("precision", ctypes.c_int), ("reserved", ctypes.c_int * 8)]
+
+    def replace(self, **kw):
+        c = HmConfig()
+        ctypes.pointer(c)[0] = self
+        for key, val in kw.items():
+            setattr(c, key, val)
+        return c
+
+
+class HmSolveInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("level2_iters_total", ctypes.c_int),
+                ("cslp_iters_total", ctypes.c_int), ("mg_coarse_iters_total", ctypes.c_int),
+                ("rel_res_estimate", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class HelmDeflError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("helmdefl status %d: %s" % (status, message))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhelmdefl.so is not built (expected at %s); run "
+                          "`python -m paper_2412_04980_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V, I, D = ctypes.c_void_p, None, ctypes.c_int, ctypes.c_double
+    sig = {
+        "hm_default_config": (V, [ctypes.POINTER(HmConfig), I, I, D]),
+        "hm_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(HmConfig)]),
+        "hm_create_problem": (I, [ctypes.POINTER(HmConfig), P, P, ctypes.c_size_t, P,
+                                  ctypes.POINTER(P)]),
+        "hm_precond_apply": (I, [P, P, P, P]),
+        "hm_fgmres_solve": (I, [P, P, P, ctypes.POINTER(HmSolveInfo), P]),
+        "hm_apply_operator": (I, [P, I, I, I, P, P, P]),
+        "hm_level_shape": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "hm_set_replay": (I, [P, I, ctypes.POINTER(I), I]),
+        "hm_get_counts": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
+        "hm_reset_counts": (I, [P]),
+        "hm_destroy_problem": (I, [P]),
+        "hm_status_string": (ctypes.c_char_p, [I]),
+        "hm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status):
+    if status < 0:
+        raise HelmDeflError(status, _lib.hm_last_error().decode())
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_config(nx, ny, h, **overrides):
+    c = HmConfig()
+    _lib.hm_default_config(ctypes.byref(c), int(nx), int(ny), float(h))
+    for key, val in overrides.items():
+        setattr(c, key, val)
+    return c
+
+
+def workspace_bytes(cfg):
+    n = _lib.hm_workspace_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise HelmDeflError(HM_ERR_ARG, _lib.hm_last_error().decode())
+    return n
+
+
+class Problem:
+    """A problem hierarchy resident in a caller-owned (torch) workspace."""
+
+    def __init__(self, handle, cfg, workspace, device):
+        self.handle = handle
+        self.cfg = cfg
+        self.workspace = workspace
+        self.device = device
+        self.N = cfg.nx * cfg.ny
+
+    def close(self):
+        if self.handle:
+            _lib.hm_destroy_problem(self.handle)
+            self.handle = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_problem(cfg, k, stream=None, workspace=None):
+    """k: nodal wavenumber, torch.float64 CUDA tensor with nx*ny entries."""
+    if not (k.is_cuda and k.dtype == torch.float64 and k.numel() == cfg.nx * cfg.ny):
+        raise ValueError("k must be a float64 GPU tensor with nx*ny entries")
+    k = k.contiguous()
+    nbytes = workspace_bytes(cfg)
+    if workspace is None:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=k.device)
+    base = workspace.data_ptr()
+    off = (-base) % 256
+    handle = ctypes.c_void_p()
+    _check(_lib.hm_create_problem(ctypes.byref(cfg), _ptr(k), ctypes.c_void_p(base + off),
+                                  ctypes.c_size_t(workspace.numel() - off), _stream(stream),
+                                  ctypes.byref(handle)))
+    return Problem(handle, cfg, workspace, k.device)
+
+
+def _c128(x, n, name):
+    if not (x.is_cuda and x.dtype == torch.complex128 and x.numel() == n and x.is_contiguous()):
+        raise ValueError("%s must be a contiguous complex128 GPU tensor with %d entries" % (name, n))
+    return x
+
+
+def precond_apply(prob, v, out=None, stream=None):
+    _c128(v, prob.N, "v")
+    x = torch.empty_like(v) if out is None else _c128(out, prob.N, "out")
+    _check(_lib.hm_precond_apply(prob.handle, _ptr(v), _ptr(x), _stream(stream)))
+    return x
+
+
+def fgmres_solve(prob, b, out=None, stream=None):
+    _c128(b, prob.N, "b")
+    u = torch.empty_like(b) if out is None else _c128(out, prob.N, "out")
+    info = HmSolveInfo()
+    st = _check(_lib.hm_fgmres_solve(prob.handle, _ptr(b), _ptr(u), ctypes.byref(info),
+                                     _stream(stream)))
+    d = info.as_dict()
+    d["status"] = st
+    return u, d
+
+
+def level_shape(prob, level, sub=0):
+    nx, ny = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.hm_level_shape(prob.handle, level, sub, ctypes.byref(nx), ctypes.byref(ny)))
+    return nx.value, ny.value
+
+
+def apply_operator(prob, level, which, x, sub=0, stream=None):
+    """Applies one building block (HM_OP_*) to the complex128 vector x."""
+    nin = nout = None
+    if which in (HM_OP_A, HM_OP_M, HM_OP_VCYCLE, HM_OP_CSLP, HM_OP_PRECOND):
+        nx, ny = level_shape(prob, level)
+        nin = nout = nx * ny
+    elif which in (HM_OP_ZT, HM_OP_Z):
+        f = level_shape(prob, level)
+        c = level_shape(prob, level + 1)
+        nin, nout = (f[0] * f[1], c[0] * c[1]) if which == HM_OP_ZT else (c[0] * c[1], f[0] * f[1])
+    else:
+        f = level_shape(prob, level, sub)
+        nin = nout = f[0] * f[1]
+        if which in (HM_OP_MG_RESTRICT, HM_OP_MG_PROLONG):
+            c = level_shape(prob, level, sub + 1)
+            if which == HM_OP_MG_RESTRICT:
+                nout = c[0] * c[1]
+            else:
+                nin = c[0] * c[1]
+    _c128(x, nin, "x")
+    out = torch.empty(nout, dtype=torch.complex128, device=x.device)
+    _check(_lib.hm_apply_operator(prob.handle, level, sub, which, _ptr(x), _ptr(out),
+                                  _stream(stream)))
+    return out
+
+
+def set_replay(prob, kind, counts):
+    arr = (ctypes.c_int * max(1, len(counts)))(*counts)
+    _check(_lib.hm_set_replay(prob.handle, kind, arr, len(counts)))
+
+
+def get_counts(prob, kind):
+    n = ctypes.c_int()
+    _check(_lib.hm_get_counts(prob.handle, kind, None, 0, ctypes.byref(n)))
+    arr = (ctypes.c_int * max(1, n.value))()
+    _check(_lib.hm_get_counts(prob.handle, kind, arr, n.value, ctypes.byref(n)))
+    return list(arr[: n.value])
+
+
+def reset_counts(prob):
+    _check(_lib.hm_reset_counts(prob.handle))
+
+
+def destroy_problem(prob):
+    prob.close()
+
+
+def status_string(status):
+    return _lib.hm_status_string(status).decode()

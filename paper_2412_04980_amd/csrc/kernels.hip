@@ -1,0 +1,807 @@
+// HIP kernels of the MADP library for gfx950 (wave64).
+//
+// Stencils (Sec. 2.1 and Sec. 3.3 of the paper), deflation transfers Z^T / Z
+// (higher-order deflation vectors), multigrid transfers for the CSLP V-cycle,
+// vector updates and reductions of the Krylov methods (Algorithm 1).
+// All grid arrays are row-major with x fastest; complex values interleaved.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace hm {
+
+namespace {
+
+constexpr int BX = 64;   // one wavefront along x
+constexpr int BY = 4;    // four wavefronts per block
+constexpr int NT = 256;
+
+inline dim3 grid2d(int nx, int ny) { return dim3((nx + BX - 1) / BX, (ny + BY - 1) / BY); }
+inline unsigned blocks1d(size_t n) {
+  size_t b = (n + NT - 1) / NT;
+  return (unsigned)(b > 0 ? b : 1);
+}
+
+// Ghost-extended value at grid position (x, y), which may lie outside:
+// inside -> u, k^2;  one step out in exactly one direction -> Sommerfeld ghost
+// u_m + i (2H) k_b u_b with k^2 = 0;  otherwise 0.
+template <typename T>
+__device__ __forceinline__ void ext_val(const OpDesc<T>& d, const cx<T>* __restrict__ u,
+                                        const T* __restrict__ k, int x, int y, cx<T>& uv, T& k2) {
+  const int nx = d.nx, ny = d.ny;
+  const bool xin = (unsigned)x < (unsigned)nx;
+  const bool yin = (unsigned)y < (unsigned)ny;
+  if (xin && yin) {
+    const size_t p = (size_t)y * nx + x;
+    uv = u[p];
+    const T kk = k[p];
+    k2 = kk * kk;
+    return;
+  }
+  k2 = T(0);
+  if (yin && (x == -1 || x == nx)) {
+    const int xb = x < 0 ? 0 : nx - 1;
+    const int xm = x < 0 ? 1 : nx - 2;
+    const size_t row = (size_t)y * nx;
+    const cx<T> ub = u[row + xb], um = u[row + xm];
+    const T c = d.two_H * k[row + xb];
+    uv = mk(um.re - c * ub.im, um.im + c * ub.re);
+    return;
+  }
+  if (xin && (y == -1 || y == ny)) {
+    const int yb = y < 0 ? 0 : ny - 1;
+    const int ym = y < 0 ? 1 : ny - 2;
+    const cx<T> ub = u[(size_t)yb * nx + x], um = u[(size_t)ym * nx + x];
+    const T c = d.two_H * k[(size_t)yb * nx + x];
+    uv = mk(um.re - c * ub.im, um.im + c * ub.re);
+    return;
+  }
+  uv = mk(T(0), T(0));
+}
+
+// Five-point row at (x, y): scale*(inv_H2 (4u - sum nbrs) - sigma k^2 u).
+template <typename T>
+__device__ __forceinline__ cx<T> five_point_row(const OpDesc<T>& d, const cx<T>* __restrict__ u,
+                                                const T* __restrict__ k, int x, int y) {
+  cx<T> uc, un;
+  T k2, kd;
+  ext_val(d, u, k, x, y, uc, k2);
+  cx<T> s = mk(T(4) * uc.re, T(4) * uc.im);
+  ext_val(d, u, k, x - 1, y, un, kd); s = s - un;
+  ext_val(d, u, k, x + 1, y, un, kd); s = s - un;
+  ext_val(d, u, k, x, y - 1, un, kd); s = s - un;
+  ext_val(d, u, k, x, y + 1, un, kd); s = s - un;
+  // sigma k^2 u
+  const cx<T> sk = mk(d.sig_re * k2, d.sig_im * k2) * uc;
+  return d.scale * (d.inv_H2 * s - sk);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> five_point_diag(const OpDesc<T>& d, const T* __restrict__ k, int x,
+                                                 int y) {
+  const T kk = k[(size_t)y * d.nx + x];
+  const T k2 = kk * kk;
+  const int nout = (x == 0) + (x == d.nx - 1) + (y == 0) + (y == d.ny - 1);
+  // scale*(4/H^2 - sigma k^2) - i scale/H^2 * 2H k * nout
+  return mk(d.scale * (T(4) * d.inv_H2 - d.sig_re * k2),
+            d.scale * (-d.sig_im * k2 - d.inv_H2 * d.two_H * kk * T(nout)));
+}
+
+template <typename T, int R>
+__device__ __forceinline__ cx<T> wide_row(const OpDesc<T>& d, const cx<T>* __restrict__ u,
+                                          const T* __restrict__ k, int x, int y) {
+  constexpr int W = 2 * R + 1;
+  T acc_re = 0, acc_im = 0;
+#pragma unroll
+  for (int b = -R; b <= R; ++b) {
+#pragma unroll
+    for (int a = -R; a <= R; ++a) {
+      cx<T> uv;
+      T k2;
+      ext_val(d, u, k, x + a, y + b, uv, k2);
+      const T lc = d.L[(b + R) * W + (a + R)];
+      const T kc = d.K[(b + R) * W + (a + R)] * k2;
+      const T cre = lc - d.sig_re * kc;
+      const T cim = -d.sig_im * kc;
+      acc_re += cre * uv.re - cim * uv.im;
+      acc_im += cre * uv.im + cim * uv.re;
+    }
+  }
+  return mk(acc_re, acc_im);
+}
+
+template <typename T, int R>
+__device__ __forceinline__ cx<T> wide_diag(const OpDesc<T>& d, const T* __restrict__ k, int x, int y) {
+  constexpr int W = 2 * R + 1;
+  const T kk = k[(size_t)y * d.nx + x];
+  const T k2 = kk * kk;
+  // centre entry plus the ghost reflections that land on the node itself:
+  // offset +-2 along x at x == 1 / nx-2 and along y at y == 1 / ny-2
+  const T lx2 = d.L[R * W + (R + 2)];
+  const T ly2 = d.L[(R + 2) * W + R];
+  T re = d.L[R * W + R] - d.sig_re * d.K[R * W + R] * k2;
+  const T im = -d.sig_im * d.K[R * W + R] * k2;
+  re += lx2 * T((x == 1) + (x == d.nx - 2)) + ly2 * T((y == 1) + (y == d.ny - 2));
+  return mk(re, im);
+}
+
+template <typename T, int R>
+__device__ __forceinline__ bool is_boundary(const OpDesc<T>& d, int x, int y) {
+  return x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1;
+}
+
+template <typename T, int R, int MODE>
+__global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __restrict__ u,
+                                                const T* __restrict__ k,
+                                                const cx<T>* __restrict__ b,
+                                                cx<T>* __restrict__ out, T omega) {
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int y = blockIdx.y * BY + threadIdx.y;
+  if (x >= d.nx || y >= d.ny) return;
+  const size_t p = (size_t)y * d.nx + x;
+  cx<T> au;
+  bool bnd = true;
+  if constexpr (R == 1) {
+    au = five_point_row(d, u, k, x, y);
+  } else {
+    bnd = is_boundary<T, R>(d, x, y);
+    au = bnd ? five_point_row(d, u, k, x, y) : wide_row<T, R>(d, u, k, x, y);
+  }
+  if constexpr (MODE == ST_APPLY) {
+    out[p] = au;
+  } else if constexpr (MODE == ST_RESID) {
+    out[p] = b[p] - au;
+  } else {
+    cx<T> dg;
+    if constexpr (R == 1) {
+      dg = five_point_diag(d, k, x, y);
+    } else {
+      dg = bnd ? five_point_diag(d, k, x, y) : wide_diag<T, R>(d, k, x, y);
+    }
+    const cx<T> r = b[p] - au;
+    out[p] = u[p] + omega * cdiv(r, dg);
+  }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(NT) k_jacobi0(OpDesc<T> d, const T* __restrict__ k,
+                                                const cx<T>* __restrict__ b, cx<T>* __restrict__ x_out,
+                                                T omega) {
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int y = blockIdx.y * BY + threadIdx.y;
+  if (x >= d.nx || y >= d.ny) return;
+  const size_t p = (size_t)y * d.nx + x;
+  cx<T> dg;
+  if constexpr (R == 1) {
+    dg = five_point_diag(d, k, x, y);
+  } else {
+    dg = is_boundary<T, R>(d, x, y) ? five_point_diag(d, k, x, y) : wide_diag<T, R>(d, k, x, y);
+  }
+  x_out[p] = omega * cdiv(b[p], dg);
+}
+
+// ---- transfers -------------------------------------------------------------
+
+__device__ __constant__ double kPz[5] = {0.125, 0.5, 0.75, 0.5, 0.125};
+
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(NT) k_restrict_z(const cx<Ti>* __restrict__ f, int nxf, int nyf,
+                                                   cx<To>* __restrict__ c, int nxc, int nyc) {
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int J = blockIdx.y * BY + threadIdx.y;
+  if (I >= nxc || J >= nyc) return;
+  To re = 0, im = 0;
+#pragma unroll
+  for (int t = -2; t <= 2; ++t) {
+    const int y = 2 * J + t;
+    if ((unsigned)y >= (unsigned)nyf) continue;
+    To rr = 0, ri = 0;
+#pragma unroll
+    for (int s = -2; s <= 2; ++s) {
+      const int x = 2 * I + s;
+      if ((unsigned)x >= (unsigned)nxf) continue;
+      const cx<Ti> v = f[(size_t)y * nxf + x];
+      rr += (To)kPz[s + 2] * (To)v.re;
+      ri += (To)kPz[s + 2] * (To)v.im;
+    }
+    re += (To)kPz[t + 2] * rr;
+    im += (To)kPz[t + 2] * ri;
+  }
+  c[(size_t)J * nxc + I] = mk(re, im);
+}
+
+// 1-D interpolation weights of Z for fine index i: coarse J0..J0+cnt-1
+__device__ __forceinline__ int z_weights(int i, int nc, int* js, double* ws) {
+  int cnt = 0;
+  if ((i & 1) == 0) {
+    const int I = i >> 1;
+    if (I - 1 >= 0) { js[cnt] = I - 1; ws[cnt++] = 0.125; }
+    js[cnt] = I; ws[cnt++] = 0.75;
+    if (I + 1 < nc) { js[cnt] = I + 1; ws[cnt++] = 0.125; }
+  } else {
+    const int I = i >> 1;
+    js[cnt] = I; ws[cnt++] = 0.5;
+    if (I + 1 < nc) { js[cnt] = I + 1; ws[cnt++] = 0.5; }
+  }
+  return cnt;
+}
+
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(NT) k_prolong_z(const cx<Ti>* __restrict__ c, int nxc, int nyc,
+                                                  cx<To>* __restrict__ f, int nxf, int nyf) {
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int y = blockIdx.y * BY + threadIdx.y;
+  if (x >= nxf || y >= nyf) return;
+  int jx[3], jy[3];
+  double wx[3], wy[3];
+  const int cxn = z_weights(x, nxc, jx, wx);
+  const int cyn = z_weights(y, nyc, jy, wy);
+  To re = 0, im = 0;
+  for (int b = 0; b < cyn; ++b) {
+    To rr = 0, ri = 0;
+    for (int a = 0; a < cxn; ++a) {
+      const cx<Ti> v = c[(size_t)jy[b] * nxc + jx[a]];
+      rr += (To)wx[a] * (To)v.re;
+      ri += (To)wx[a] * (To)v.im;
+    }
+    re += (To)wy[b] * rr;
+    im += (To)wy[b] * ri;
+  }
+  f[(size_t)y * nxf + x] = mk(re, im);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_restrict_fw(const cx<T>* __restrict__ f, int nxf, int nyf,
+                                                    cx<T>* __restrict__ c, int nxc, int nyc) {
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int J = blockIdx.y * BY + threadIdx.y;
+  if (I >= nxc || J >= nyc) return;
+  const T w[3] = {T(0.25), T(0.5), T(0.25)};
+  T re = 0, im = 0;
+#pragma unroll
+  for (int b = -1; b <= 1; ++b) {
+    const int y = 2 * J + b;
+    if ((unsigned)y >= (unsigned)nyf) continue;
+    T rr = 0, ri = 0;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a) {
+      const int x = 2 * I + a;
+      if ((unsigned)x >= (unsigned)nxf) continue;
+      const cx<T> v = f[(size_t)y * nxf + x];
+      rr += w[a + 1] * v.re;
+      ri += w[a + 1] * v.im;
+    }
+    re += w[b + 1] * rr;
+    im += w[b + 1] * ri;
+  }
+  c[(size_t)J * nxc + I] = mk(re, im);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_prolong_bilinear_add(const cx<T>* __restrict__ c, int nxc,
+                                                             int nyc, cx<T>* __restrict__ f, int nxf,
+                                                             int nyf) {
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int y = blockIdx.y * BY + threadIdx.y;
+  if (x >= nxf || y >= nyf) return;
+  const int I = x >> 1, J = y >> 1;
+  const bool ox = x & 1, oy = y & 1;
+  cx<T> e;
+  if (!ox && !oy) {
+    e = c[(size_t)J * nxc + I];
+  } else if (ox && !oy) {
+    e = T(0.5) * (c[(size_t)J * nxc + I] + c[(size_t)J * nxc + I + 1]);
+  } else if (!ox && oy) {
+    e = T(0.5) * (c[(size_t)J * nxc + I] + c[(size_t)(J + 1) * nxc + I]);
+  } else {
+    e = T(0.25) * ((c[(size_t)J * nxc + I] + c[(size_t)J * nxc + I + 1]) +
+                   (c[(size_t)(J + 1) * nxc + I] + c[(size_t)(J + 1) * nxc + I + 1]));
+  }
+  const size_t p = (size_t)y * nxf + x;
+  f[p] = f[p] + e;
+}
+
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(NT) k_inject(const Ti* __restrict__ f, int nxf, To* __restrict__ c,
+                                               int nxc, int nyc) {
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int J = blockIdx.y * BY + threadIdx.y;
+  if (I >= nxc || J >= nyc) return;
+  c[(size_t)J * nxc + I] = (To)f[(size_t)(2 * J) * nxf + 2 * I];
+}
+
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(NT) k_convert_real(const Ti* __restrict__ a, To* __restrict__ b,
+                                                     size_t n) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) b[i] = (To)a[i];
+}
+
+// ---- vector kernels ----------------------------------------------------------
+
+template <typename Ti, typename To>
+__global__ void __launch_bounds__(NT) k_convert(const cx<Ti>* __restrict__ a, cx<To>* __restrict__ b,
+                                                size_t n) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) b[i] = cvt<To>(a[i]);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_add(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b,
+                                            cx<T>* __restrict__ out, size_t n) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_scale_dev(const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                  const c128* __restrict__ scal, int inv, size_t n) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const c128 sc = scal[0];
+  if (inv) {
+    const T s = (T)(1.0 / sc.re);
+    y[i] = s * x[i];
+  } else {
+    y[i] = cvt<T>(sc) * x[i];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_zero(cx<T>* __restrict__ x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) x[i] = mk(T(0), T(0));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_combine(const cx<T>* __restrict__ V, size_t ldv, int m,
+                                                const c128* __restrict__ coef, double sign,
+                                                cx<T>* __restrict__ out, int accumulate, size_t n) {
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  double re = 0, im = 0;
+  for (int j = 0; j < m; ++j) {
+    const c128 c = coef[j];
+    const cx<T> v = V[(size_t)j * ldv + i];
+    re += c.re * (double)v.re - c.im * (double)v.im;
+    im += c.re * (double)v.im + c.im * (double)v.re;
+  }
+  re *= sign;
+  im *= sign;
+  if (accumulate) {
+    const cx<T> o = out[i];
+    re += (double)o.re;
+    im += (double)o.im;
+  }
+  out[i] = mk((T)re, (T)im);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_dense_matvec(const cx<T>* __restrict__ A, int n,
+                                                     const cx<T>* __restrict__ x, cx<T>* __restrict__ y) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  double re = 0, im = 0;
+  for (int j = 0; j < n; ++j) {
+    const cx<T> a = A[(size_t)i * n + j];
+    const cx<T> v = x[j];
+    re += (double)a.re * (double)v.re - (double)a.im * (double)v.im;
+    im += (double)a.re * (double)v.im + (double)a.im * (double)v.re;
+  }
+  y[i] = mk((T)re, (T)im);
+}
+
+__global__ void __launch_bounds__(NT) k_identity(c128* __restrict__ out, int n) {
+  const size_t idx = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const size_t i = idx % n, j = idx / n;
+  out[idx] = mk(i == j ? 1.0 : 0.0, 0.0);
+}
+
+// ---- reductions ----------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum of (re, im) over a 256-thread block; valid in thread 0.
+__device__ __forceinline__ c128 block_sum(double re, double im, double* sh) {
+  re = wave_sum(re);
+  im = wave_sum(im);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[2 * wid] = re;
+    sh[2 * wid + 1] = im;
+  }
+  __syncthreads();
+  c128 r = mk(0.0, 0.0);
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < NT / 64; ++w) {
+      r.re += sh[2 * w];
+      r.im += sh[2 * w + 1];
+    }
+  }
+  return r;
+}
+
+inline size_t chunk_len(size_t n, int nchunks) { return (n + nchunks - 1) / nchunks; }
+
+constexpr int G = 8;   // dot products per block in the multi-dot
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, size_t ldv, int m,
+                                                 const cx<T>* __restrict__ w, size_t n, size_t clen,
+                                                 c128* __restrict__ partials, int nchunks) {
+  __shared__ double sh[2 * NT / 64];
+  const int chunk = blockIdx.x;
+  const int i0 = blockIdx.y * G;
+  const size_t lo = (size_t)chunk * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  double re[G], im[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) { re[g] = 0; im[g] = 0; }
+  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
+    const cx<T> wv = w[i];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (i0 + g < m) {
+        const cx<T> v = V[(size_t)(i0 + g) * ldv + i];
+        // conj(v) * w
+        re[g] += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
+        im[g] += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    if (i0 + g < m) {
+      const c128 s = block_sum(re[g], im[g], sh);
+      if (threadIdx.x == 0) partials[(size_t)(i0 + g) * nchunks + chunk] = s;
+    }
+  }
+}
+
+// out[i] = sum_c partials[i*nchunks + c]; sqrt_re: out = sqrt(re)
+__global__ void __launch_bounds__(NT) k_final(const c128* __restrict__ partials, int nchunks,
+                                              c128* __restrict__ out, int sqrt_re) {
+  __shared__ double sh[2 * NT / 64];
+  const int i = blockIdx.x;
+  double re = 0, im = 0;
+  for (int c = threadIdx.x; c < nchunks; c += NT) {
+    const c128 v = partials[(size_t)i * nchunks + c];
+    re += v.re;
+    im += v.im;
+  }
+  const c128 s = block_sum(re, im, sh);
+  if (threadIdx.x == 0) out[i] = sqrt_re ? mk(sqrt(s.re), 0.0) : s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_mgs_step(cx<T>* __restrict__ w, const cx<T>* __restrict__ prev,
+                                                 const c128* __restrict__ hprev,
+                                                 const cx<T>* __restrict__ next, size_t n, size_t clen,
+                                                 c128* __restrict__ partials) {
+  __shared__ double sh[2 * NT / 64];
+  const size_t lo = (size_t)blockIdx.x * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  double re = 0, im = 0;
+  cx<T> h = mk(T(0), T(0));
+  if (prev) h = cvt<T>(hprev[0]);
+  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
+    cx<T> wv = w[i];
+    if (prev) {
+      wv = wv - h * prev[i];
+      w[i] = wv;
+    }
+    if (next) {
+      const cx<T> v = next[i];
+      re += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
+      im += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
+    } else {
+      re += (double)wv.re * (double)wv.re + (double)wv.im * (double)wv.im;
+    }
+  }
+  const c128 s = block_sum(re, im, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, const cx<T>* __restrict__ V,
+                                                        size_t ldv, int m, const c128* __restrict__ h,
+                                                        size_t n, size_t clen,
+                                                        c128* __restrict__ partials) {
+  __shared__ double sh[2 * NT / 64];
+  const size_t lo = (size_t)blockIdx.x * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  double acc = 0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
+    const cx<T> w0 = w[i];
+    double re = 0, im = 0;
+    for (int j = 0; j < m; ++j) {
+      const c128 c = h[j];
+      const cx<T> v = V[(size_t)j * ldv + i];
+      re += c.re * (double)v.re - c.im * (double)v.im;
+      im += c.re * (double)v.im + c.im * (double)v.re;
+    }
+    const cx<T> wn = mk((T)((double)w0.re - re), (T)((double)w0.im - im));
+    w[i] = wn;
+    acc += (double)wn.re * (double)wn.re + (double)wn.im * (double)wn.im;
+  }
+  const c128 s = block_sum(acc, 0.0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_norm2(const cx<T>* __restrict__ x, size_t n, size_t clen,
+                                              c128* __restrict__ partials) {
+  __shared__ double sh[2 * NT / 64];
+  const size_t lo = (size_t)blockIdx.x * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  double acc = 0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
+    const cx<T> v = x[i];
+    acc += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+  }
+  const c128 s = block_sum(acc, 0.0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(NT) k_check_k(const double* __restrict__ k, size_t n, size_t clen,
+                                                c128* __restrict__ partials) {
+  __shared__ double sh[2 * NT / 64];
+  const size_t lo = (size_t)blockIdx.x * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  double bad = 0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
+    const double v = k[i];
+    if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+  }
+  const c128 s = block_sum(bad, 0.0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(NT) k_max_partial(const double* __restrict__ a, size_t n, size_t clen,
+                                                    c128* __restrict__ partials) {
+  __shared__ double sh[NT / 64];
+  const size_t lo = (size_t)blockIdx.x * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  double m = -INFINITY;
+  for (size_t i = lo + threadIdx.x; i < hi; i += NT) m = fmax(m, a[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NT / 64; ++w) m = fmax(m, sh[w]);
+    partials[blockIdx.x] = mk(m, 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_max_final(const c128* __restrict__ partials, int nchunks,
+                                                  c128* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double m = -INFINITY;
+  for (int c = 0; c < nchunks; ++c) m = fmax(m, partials[c].re);
+  out[0] = mk(m, 0.0);
+}
+
+}  // namespace
+
+// ============================ launchers ======================================
+
+template <typename T>
+hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
+                          cx<T>* out, T omega, hipStream_t s) {
+  const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
+#define HM_ST(R, M) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega)
+#define HM_STR(R)                              \
+  if (mode == ST_APPLY) HM_ST(R, ST_APPLY);    \
+  else if (mode == ST_RESID) HM_ST(R, ST_RESID); \
+  else HM_ST(R, ST_JACOBI);
+  if (d.R == 1) { HM_STR(1) }
+  else if (d.R == 2) { HM_STR(2) }
+  else if (d.R == 3) { HM_STR(3) }
+  else return hipErrorInvalidValue;
+#undef HM_STR
+#undef HM_ST
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x, T omega,
+                          hipStream_t s) {
+  const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
+  if (d.R == 1) k_jacobi0<T, 1><<<g, blk, 0, s>>>(d, k, b, x, omega);
+  else if (d.R == 2) k_jacobi0<T, 2><<<g, blk, 0, s>>>(d, k, b, x, omega);
+  else if (d.R == 3) k_jacobi0<T, 3><<<g, blk, 0, s>>>(d, k, b, x, omega);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, hipStream_t s) {
+  const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
+  k_restrict_z<Ti, To><<<grid2d(nxc, nyc), dim3(BX, BY), 0, s>>>(f, nxf, nyf, c, nxc, nyc);
+  return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, hipStream_t s) {
+  const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
+  k_prolong_z<Ti, To><<<grid2d(nxf, nyf), dim3(BX, BY), 0, s>>>(c, nxc, nyc, f, nxf, nyf);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, hipStream_t s) {
+  const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
+  k_restrict_fw<T><<<grid2d(nxc, nyc), dim3(BX, BY), 0, s>>>(f, nxf, nyf, c, nxc, nyc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, hipStream_t s) {
+  const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
+  k_prolong_bilinear_add<T><<<grid2d(nxf, nyf), dim3(BX, BY), 0, s>>>(c, nxc, nyc, f, nxf, nyf);
+  return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+hipError_t launch_inject(const Ti* f, int nxf, int nyf, To* c, hipStream_t s) {
+  const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
+  k_inject<Ti, To><<<grid2d(nxc, nyc), dim3(BX, BY), 0, s>>>(f, nxf, c, nxc, nyc);
+  return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+hipError_t launch_convert_real(const Ti* a, To* b, size_t n, hipStream_t s) {
+  k_convert_real<Ti, To><<<blocks1d(n), NT, 0, s>>>(a, b, n);
+  return hipGetLastError();
+}
+
+template <typename Ti, typename To>
+hipError_t launch_convert(const cx<Ti>* a, cx<To>* b, size_t n, hipStream_t s) {
+  k_convert<Ti, To><<<blocks1d(n), NT, 0, s>>>(a, b, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_add(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s) {
+  k_add<T><<<blocks1d(n), NT, 0, s>>>(a, b, out, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale_dev(const cx<T>* x, cx<T>* y, const c128* scal, int inv, size_t n,
+                            hipStream_t s) {
+  k_scale_dev<T><<<blocks1d(n), NT, 0, s>>>(x, y, scal, inv, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zero(cx<T>* x, size_t n, hipStream_t s) {
+  k_zero<T><<<blocks1d(n), NT, 0, s>>>(x, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, double sign,
+                          cx<T>* out, int accumulate, size_t n, hipStream_t s) {
+  k_combine<T><<<blocks1d(n), NT, 0, s>>>(V, ldv, m, coef, sign, out, accumulate, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s) {
+  k_dense_matvec<T><<<blocks1d((size_t)n), NT, 0, s>>>(A, n, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity(c128* out, int n, hipStream_t s) {
+  k_identity<<<blocks1d((size_t)n * n), NT, 0, s>>>(out, n);
+  return hipGetLastError();
+}
+
+int reduction_chunks(size_t n) {
+  size_t c = (n + NT * 8 - 1) / (NT * 8);
+  if (c < 1) c = 1;
+  if (c > (size_t)kMaxChunks) c = kMaxChunks;
+  return (int)c;
+}
+
+template <typename T>
+hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n, RedBuf rb,
+                           c128* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const size_t clen = chunk_len(n, rb.nchunks);
+  k_multidot<T><<<dim3(rb.nchunks, (m + G - 1) / G), NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials,
+                                                                   rb.nchunks);
+  k_final<<<m, NT, 0, s>>>(rb.partials, rb.nchunks, out, 0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const cx<T>* next,
+                           size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  const size_t clen = chunk_len(n, rb.nchunks);
+  k_mgs_step<T><<<rb.nchunks, NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, next ? 0 : 1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
+                                  size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  const size_t clen = chunk_len(n, rb.nchunks);
+  k_cgs_update_norm<T><<<rb.nchunks, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  const size_t clen = chunk_len(n, rb.nchunks);
+  k_norm2<T><<<rb.nchunks, NT, 0, s>>>(x, n, clen, rb.partials);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  const size_t clen = chunk_len(n, rb.nchunks);
+  k_max_partial<<<rb.nchunks, NT, 0, s>>>(a, n, clen, rb.partials);
+  k_max_final<<<1, 64, 0, s>>>(rb.partials, rb.nchunks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  const size_t clen = chunk_len(n, rb.nchunks);
+  k_check_k<<<rb.nchunks, NT, 0, s>>>(k, n, clen, rb.partials);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 0);
+  return hipGetLastError();
+}
+
+// ---- explicit instantiations ----------------------------------------------------
+#define HM_INST_T(T)                                                                              \
+  template hipError_t launch_stencil<T>(const OpDesc<T>&, int, const cx<T>*, const T*,              \
+                                        const cx<T>*, cx<T>*, T, hipStream_t);                       \
+  template hipError_t launch_jacobi0<T>(const OpDesc<T>&, const T*, const cx<T>*, cx<T>*, T,         \
+                                        hipStream_t);                                               \
+  template hipError_t launch_restrict_fw<T>(const cx<T>*, int, int, cx<T>*, hipStream_t);          \
+  template hipError_t launch_prolong_bilinear_add<T>(const cx<T>*, int, int, cx<T>*, hipStream_t); \
+  template hipError_t launch_add<T>(const cx<T>*, const cx<T>*, cx<T>*, size_t, hipStream_t);      \
+  template hipError_t launch_scale_dev<T>(const cx<T>*, cx<T>*, const c128*, int, size_t,          \
+                                          hipStream_t);                                             \
+  template hipError_t launch_zero<T>(cx<T>*, size_t, hipStream_t);                                 \
+  template hipError_t launch_dense_matvec<T>(const cx<T>*, int, const cx<T>*, cx<T>*, hipStream_t); \
+  template hipError_t launch_combine<T>(const cx<T>*, size_t, int, const c128*, double, cx<T>*,    \
+                                        int, size_t, hipStream_t);                                  \
+  template hipError_t launch_multidot<T>(const cx<T>*, size_t, int, const cx<T>*, size_t, RedBuf,  \
+                                         c128*, hipStream_t);                                       \
+  template hipError_t launch_mgs_step<T>(cx<T>*, const cx<T>*, const c128*, const cx<T>*, size_t,  \
+                                         RedBuf, c128*, hipStream_t);                               \
+  template hipError_t launch_cgs_update_norm<T>(cx<T>*, const cx<T>*, size_t, int, const c128*,    \
+                                                size_t, RedBuf, c128*, hipStream_t);                \
+  template hipError_t launch_norm<T>(const cx<T>*, size_t, RedBuf, c128*, hipStream_t);
+HM_INST_T(float)
+HM_INST_T(double)
+#undef HM_INST_T
+
+#define HM_INST_2(A, B)                                                                          \
+  template hipError_t launch_restrict_z<A, B>(const cx<A>*, int, int, cx<B>*, hipStream_t);     \
+  template hipError_t launch_prolong_z<A, B>(const cx<A>*, int, int, cx<B>*, hipStream_t);      \
+  template hipError_t launch_inject<A, B>(const A*, int, int, B*, hipStream_t);                 \
+  template hipError_t launch_convert_real<A, B>(const A*, B*, size_t, hipStream_t);             \
+  template hipError_t launch_convert<A, B>(const cx<A>*, cx<B>*, size_t, hipStream_t);
+HM_INST_2(float, float)
+HM_INST_2(double, double)
+HM_INST_2(float, double)
+HM_INST_2(double, float)
+#undef HM_INST_2
+
+}  // namespace hm

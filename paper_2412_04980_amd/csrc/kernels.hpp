@@ -1,0 +1,120 @@
+// Host-side launchers of the HIP kernels of the MADP library (gfx950).
+// Every launcher enqueues on the given stream and returns hipSuccess or the
+// launch error; none synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+#include "cplx.hpp"
+
+namespace hm {
+
+// Description of one grid operator (Sec. 2.1 / 3.3):
+//   R = 1: five-point rows everywhere:
+//          scale * ( inv_H2 (4u - sum of 4 neighbours) - sigma k^2 u )
+//   R = 2, 3: re-discretised (2R+1)^2 stencil on non-boundary rows
+//          sum_{a,b} ( L[b][a] - sigma K[b][a] k^2_{p} ) u_p
+//          and the five-point row above on boundary nodes.
+// Points outside the grid take the Sommerfeld ghost value
+// u_m + i two_H k_b u_b (one step out in exactly one direction, wavenumber 0)
+// or zero (further out, or out in both directions).
+template <typename T>
+struct OpDesc {
+  int nx, ny;
+  int R;
+  T inv_H2;   // 1 / H^2 of the five-point rows
+  T two_H;    // 2 H of the ghost term
+  T scale;    // s_l of the five-point rows
+  T sig_re, sig_im;
+  T L[49];    // (2R+1)^2 Laplace coefficients, already divided by h^2 (finest h)
+  T K[49];    // (2R+1)^2 wavenumber coefficients
+};
+
+enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_JACOBI = 2 };
+
+// out = Op(u)                         (ST_APPLY, b unused)
+// out = b - Op(u)                     (ST_RESID)
+// out = u + omega D^-1 (b - Op(u))    (ST_JACOBI, D = diagonal of Op)
+template <typename T>
+hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
+                          cx<T>* out, T omega, hipStream_t s);
+
+// x = omega D^-1 b  (first damped-Jacobi sweep from x = 0)
+template <typename T>
+hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x, T omega,
+                          hipStream_t s);
+
+// Deflation restriction Z^T: fine (nxf x nyf) -> coarse; weights p (x) p,
+// p = [1 4 6 4 1]/8 at fine offsets -2..2 around 2J; outside values zero.
+template <typename Ti, typename To>
+hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, hipStream_t s);
+// Deflation interpolation Z: coarse -> fine (transpose of the above).
+template <typename Ti, typename To>
+hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, hipStream_t s);
+
+// Full-weighting restriction (1/16)[1 2 1;2 4 2;1 2 1], fine -> coarse.
+template <typename T>
+hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, hipStream_t s);
+// x_fine += bilinear interpolation of e_coarse.
+template <typename T>
+hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, hipStream_t s);
+// Injection of a real nodal field: c(J) = f(2J).
+template <typename Ti, typename To>
+hipError_t launch_inject(const Ti* f, int nxf, int nyf, To* c, hipStream_t s);
+// Real-field conversion.
+template <typename Ti, typename To>
+hipError_t launch_convert_real(const Ti* a, To* b, size_t n, hipStream_t s);
+
+// ---- vector kernels ------------------------------------------------------
+template <typename Ti, typename To>
+hipError_t launch_convert(const cx<Ti>* a, cx<To>* b, size_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_add(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s);  // out=a+b
+// y = scal[0] * x  (scal on the device; `inv` = use 1/scal[0].re instead)
+template <typename T>
+hipError_t launch_scale_dev(const cx<T>* x, cx<T>* y, const c128* scal, int inv, size_t n,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_zero(cx<T>* x, size_t n, hipStream_t s);
+// out = (accumulate ? out : 0) + sign * sum_{i<m} coef[i] * V_i  (coef on the device)
+template <typename T>
+hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, double sign,
+                          cx<T>* out, int accumulate, size_t n, hipStream_t s);
+
+// y = A x with A a dense n x n row-major matrix (coarsest multigrid solve)
+template <typename T>
+hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s);
+// out = unit vectors: out[j*n + i] = (i == j)
+hipError_t launch_identity(c128* out, int n, hipStream_t s);
+
+// ---- reductions (double accumulation; results on the device) --------------
+struct RedBuf {
+  c128* partials;   // >= kMaxChunks * (max dots) entries
+  int nchunks;
+};
+constexpr int kMaxChunks = 512;
+int reduction_chunks(size_t n);
+
+// out[i] = (V_i, w) = sum conj(V_i) w, i = 0..m-1
+template <typename T>
+hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n, RedBuf rb,
+                           c128* out, hipStream_t s);
+// Modified Gram-Schmidt step: if (prev) w -= hprev[0] * prev;  out[0] = (next, w)
+// If next == nullptr: out[0] = ||w||_2 (real part).
+template <typename T>
+hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const cx<T>* next,
+                           size_t n, RedBuf rb, c128* out, hipStream_t s);
+// Classical Gram-Schmidt update fused with the norm: w -= sum_{i<m} h[i] V_i ; out[0] = ||w||
+template <typename T>
+hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
+                                  size_t n, RedBuf rb, c128* out, hipStream_t s);
+// out[0] = ||x||_2 (real part)
+template <typename T>
+hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream_t s);
+// out[0].re = max of a real field (reduction over chunks)
+hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipStream_t s);
+// Validation of the wavenumber field: out[0] = number of entries that are not
+// finite or negative (as a double in the real part).
+hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s);
+
+}  // namespace hm

@@ -1,0 +1,1135 @@
+// Host orchestration of the MADP preconditioner and FGMRES on the GPU.
+//
+// The paper's method (Algorithm 1 with the MADP configuration of Sec. 4.3):
+//   Prec_l(v): v_hat = Z^T v; v_t ~ E^-1 v_hat (level-2 FGMRES to tolerance
+//   0.3, or one FGMRES step with Krylov CSLP on the coarsest level);
+//   t = Z v_t; r~ = v - A t; r ~ M^-1 r~ (one V-cycle on levels 1-2, GMRES
+//   below); return r + t.
+// Outer: FGMRES with modified Gram-Schmidt, restart 30, relative residual
+// 1e-6, true residual recomputed in FP64.
+//
+// Every grid step runs in a HIP kernel (kernels.hip); the host holds only the
+// control flow and the small Hessenberg least-squares problems.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/helmdefl.h"
+#include "kernels.hpp"
+#include "tables.hpp"
+
+namespace hm {
+
+using cd = std::complex<double>;
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+struct ArgError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HM_CHECK(...)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (__VA_ARGS__);                                                         \
+    if (e_ != hipSuccess)                                                                  \
+      throw HipError(std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Workspace carving: the same walk computes the size (base == nullptr) and
+// assigns the pointers.
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Host side of an Arnoldi least-squares problem (Givens rotations).
+struct LSQ {
+  int cap = 0;
+  double beta = 0;
+  std::vector<cd> R, cs_s, g;   // R: (cap+1) x cap column-major, rotated
+  std::vector<double> cs_c;
+  void init(int cap_, double beta_) {
+    cap = cap_;
+    beta = beta_;
+    R.assign((size_t)(cap + 1) * cap, cd(0));
+    cs_c.assign(cap, 0.0);
+    cs_s.assign(cap, cd(0));
+    g.assign(cap + 1, cd(0));
+    g[0] = beta;
+  }
+  // column j from h[0..j+1]; returns |g_{j+1}|
+  double add(int j, const c128* h) {
+    cd* col = &R[(size_t)j * (cap + 1)];
+    for (int i = 0; i <= j + 1; ++i) col[i] = cd(h[i].re, h[i].im);
+    for (int i = 0; i < j; ++i) {
+      const cd t = cs_c[i] * col[i] + cs_s[i] * col[i + 1];
+      col[i + 1] = -std::conj(cs_s[i]) * col[i] + cs_c[i] * col[i + 1];
+      col[i] = t;
+    }
+    const cd a = col[j], b = col[j + 1];
+    double c;
+    cd s;
+    if (b == cd(0)) {
+      c = 1.0; s = 0.0;
+    } else if (a == cd(0)) {
+      c = 0.0; s = 1.0;
+    } else {
+      const double aa = std::abs(a);
+      const double nrm = std::hypot(aa, std::abs(b));
+      c = aa / nrm;
+      s = (a / aa) * std::conj(b) / nrm;
+    }
+    cs_c[j] = c;
+    cs_s[j] = s;
+    col[j] = c * a + s * b;
+    col[j + 1] = 0.0;
+    g[j + 1] = -std::conj(s) * g[j];
+    g[j] = c * g[j];
+    return std::abs(g[j + 1]);
+  }
+  void solve(int m, std::vector<c128>& y) const {
+    std::vector<cd> yy(m);
+    for (int i = m - 1; i >= 0; --i) {
+      cd acc = g[i];
+      for (int k = i + 1; k < m; ++k) acc -= R[(size_t)k * (cap + 1) + i] * yy[k];
+      yy[i] = acc / R[(size_t)i * (cap + 1) + i];
+    }
+    y.resize(m);
+    for (int i = 0; i < m; ++i) y[i] = mk(yy[i].real(), yy[i].imag());
+  }
+};
+
+// Krylov workspace of one solver instance (type of its vectors given at use).
+struct KrylovWS {
+  int cap = 0;
+  size_t N = 0;
+  void* V = nullptr;   // (cap+1) x N
+  void* X = nullptr;   // cap x N  (flexible basis; unused by plain GMRES)
+  void* w = nullptr;   // N
+  c128* h = nullptr;   // device column / scalars, cap + 2
+};
+
+struct MGLevel {
+  int nx = 0, ny = 0;
+  size_t N = 0;
+  double H = 0, omega = 0;
+  OpDesc<double> op64{};
+  OpDesc<float> op32{};
+  double* k = nullptr; // wavenumber, q >= 1 (q = 0 uses the deflation level's)
+  float* k32 = nullptr;
+  void* x = nullptr;
+  void* y = nullptr;
+  void* r = nullptr;
+  void* b = nullptr;   // q >= 1
+};
+
+struct MGHier {
+  std::vector<MGLevel> lv;
+  bool dense = false;
+  void* inv = nullptr;        // dense inverse of the coarsest operator (level type)
+  c128* tmpA = nullptr;       // set-up scratch for the dense inverse (n x n each)
+  c128* tmpB = nullptr;
+  KrylovWS gm;                // coarsest GMRES otherwise
+  int maxit = 0;
+};
+
+struct DefLevel {
+  int l = 0, nx = 0, ny = 0;
+  size_t N = 0;
+  double hl = 0, sl = 0, kmax = 0;
+  bool dbl = true;            // precision of the level's work
+  OpDesc<double> A64{}, M64{};
+  OpDesc<float> A32{}, M32{};
+  double* k64 = nullptr;
+  float* k32 = nullptr;
+  // this level as a coarse problem (l >= 2): FGMRES workspace, rhs / solution
+  KrylovWS fg;
+  void* rhs = nullptr;
+  void* sol = nullptr;
+  // preconditioner temporaries
+  void* t = nullptr;
+  void* rt = nullptr;
+  void* xo = nullptr;
+  // CSLP approximation
+  bool has_mg = false;
+  MGHier mg;
+  KrylovWS cslp;              // l >= 3: GMRES on M_l
+  int cslp_maxit = 0;
+};
+
+enum Kind { K_LEVEL2 = 0, K_CSLP = 1, K_MGC = 2, K_OUTER = 3, K_NKIND = 4 };
+
+inline int krylov_maxit(size_t N, double coef) {
+  const int m = (int)std::floor(coef * std::pow((double)N, 0.25));
+  return m < 1 ? 1 : m;
+}
+
+static const int kDenseMax = 512;
+
+template <typename T>
+static void set_five_point(OpDesc<T>& d, int nx, int ny, double H, double scale, cd sigma) {
+  std::memset(&d, 0, sizeof(d));
+  d.nx = nx; d.ny = ny; d.R = 1;
+  d.inv_H2 = (T)(1.0 / (H * H));
+  d.two_H = (T)(2.0 * H);
+  d.scale = (T)scale;
+  d.sig_re = (T)sigma.real();
+  d.sig_im = (T)sigma.imag();
+}
+
+template <typename T>
+static void set_wide(OpDesc<T>& d, int nx, int ny, double h, int level, cd sigma) {
+  int R = 0;
+  std::vector<double> lap, wav;
+  coarse_tables(level, &R, lap, wav);
+  const double hl = h * std::ldexp(1.0, level - 1);
+  const double sl = std::ldexp(1.0, 2 * (level - 1));
+  set_five_point(d, nx, ny, hl, sl, sigma);
+  d.R = R;
+  const double h2 = h * h;
+  for (size_t i = 0; i < lap.size(); ++i) {
+    d.L[i] = (T)(lap[i] / h2);
+    d.K[i] = (T)wav[i];
+  }
+}
+
+template <typename T> static inline const OpDesc<T>& opsel(const DefLevel& L, bool cslp);
+template <> inline const OpDesc<double>& opsel<double>(const DefLevel& L, bool cslp) { return cslp ? L.M64 : L.A64; }
+template <> inline const OpDesc<float>& opsel<float>(const DefLevel& L, bool cslp) { return cslp ? L.M32 : L.A32; }
+template <typename T> static inline const OpDesc<T>& mgop(const MGLevel& m);
+template <> inline const OpDesc<double>& mgop<double>(const MGLevel& m) { return m.op64; }
+template <> inline const OpDesc<float>& mgop<float>(const MGLevel& m) { return m.op32; }
+template <typename T> static inline const T* levk(const DefLevel& L);
+template <> inline const double* levk<double>(const DefLevel& L) { return L.k64; }
+template <> inline const float* levk<float>(const DefLevel& L) { return L.k32; }
+template <typename T> static inline const T* mgk(const DefLevel& D, int q);
+template <> inline const double* mgk<double>(const DefLevel& D, int q) { return q == 0 ? D.k64 : D.mg.lv[q].k; }
+template <> inline const float* mgk<float>(const DefLevel& D, int q) { return q == 0 ? D.k32 : D.mg.lv[q].k32; }
+
+}  // namespace hm
+
+using namespace hm;
+
+struct hm_problem {
+  hm_config cfg{};
+  std::vector<DefLevel> lev;   // index 1..L
+  int L = 0;
+  bool mixed = false;
+  hipStream_t s = nullptr;
+  // outer FGMRES (always FP64)
+  KrylovWS outer;
+  c128* tmp64 = nullptr;       // N1
+  void* pin_v = nullptr;       // precondition input in the level-1 type (mixed)
+  void* pin_x = nullptr;
+  // reductions / scalars
+  RedBuf rb{};
+  c128* scal = nullptr;        // small device scratch
+  c128* coef = nullptr;        // combination coefficients (device)
+  int coef_cap = 0;
+  c128* host = nullptr;        // pinned host staging for device results
+  c128* host_coef = nullptr;   // pinned host staging for coefficient uploads
+  int host_cap = 0;
+  // counts
+  std::vector<int> rec[K_NKIND];
+  std::vector<int> rep[K_NKIND];
+  size_t rep_pos[K_NKIND] = {0, 0, 0, 0};
+  double last_estimate = 0;
+};
+
+namespace hm {
+
+static thread_local std::string g_last_error;
+
+static int forced_count(hm_problem* p, int kind) {
+  if (p->rep[kind].empty()) return -1;
+  if (p->rep_pos[kind] >= p->rep[kind].size()) throw ArgError("replay counts exhausted");
+  return p->rep[kind][p->rep_pos[kind]++];
+}
+
+static inline RedBuf rbuf(const hm_problem* p, size_t n) {
+  return RedBuf{p->rb.partials, reduction_chunks(n)};
+}
+
+static void d2h(hm_problem* p, const c128* dev, int n) {
+  HM_CHECK(hipMemcpyAsync(p->host, dev, sizeof(c128) * n, hipMemcpyDeviceToHost, p->s));
+  HM_CHECK(hipStreamSynchronize(p->s));
+}
+
+static void h2d_coef(hm_problem* p, const std::vector<c128>& y) {
+  if ((int)y.size() > p->coef_cap) throw ArgError("coefficient buffer too small");
+  // the staging buffer may still feed an earlier upload: wait for the stream
+  HM_CHECK(hipStreamSynchronize(p->s));
+  std::memcpy(p->host_coef, y.data(), sizeof(c128) * y.size());
+  HM_CHECK(hipMemcpyAsync(p->coef, p->host_coef, sizeof(c128) * y.size(), hipMemcpyHostToDevice,
+                          p->s));
+}
+
+// ---- operator application on a level -----------------------------------------
+template <typename T>
+static void apply_level(hm_problem* p, const DefLevel& L, bool cslp, int mode, const cx<T>* u,
+                        const cx<T>* b, cx<T>* out) {
+  HM_CHECK(launch_stencil<T>(opsel<T>(L, cslp), mode, u, levk<T>(L), b, out, T(0), p->s));
+}
+
+// ---- GMRES with classical Gram-Schmidt (Krylov CSLP) ----------------------------
+// Unpreconditioned GMRES from x = 0 on the operator `op` with wavenumber `k`.
+template <typename T>
+static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& ws, int maxit,
+                     double tol, int kind, const cx<T>* b, cx<T>* x) {
+  const size_t N = ws.N;
+  cx<T>* V = (cx<T>*)ws.V;
+  cx<T>* w = (cx<T>*)ws.w;
+  HM_CHECK(launch_norm<T>(b, N, rbuf(p, N), ws.h, p->s));
+  d2h(p, ws.h, 1);
+  const double beta = p->host[0].re;
+  if (beta == 0.0) {
+    HM_CHECK(launch_zero<T>(x, N, p->s));
+    p->rec[kind].push_back(0);
+    return 0;
+  }
+  const int forced = forced_count(p, kind);
+  if (forced >= 0) {
+    maxit = forced;
+    tol = -1;
+  }
+  if (maxit > ws.cap) throw ArgError("GMRES step count exceeds the workspace");
+  HM_CHECK(launch_scale_dev<T>(b, V, ws.h, 1, N, p->s));
+  LSQ lsq;
+  lsq.init(maxit, beta);
+  int steps = 0;
+  for (int j = 0; j < maxit; ++j) {
+    HM_CHECK(launch_stencil<T>(op, ST_APPLY, V + (size_t)j * N, k, nullptr, w, T(0), p->s));
+    HM_CHECK(launch_multidot<T>(V, N, j + 1, w, N, rbuf(p, N), ws.h, p->s));
+    HM_CHECK(launch_cgs_update_norm<T>(w, V, N, j + 1, ws.h, N, rbuf(p, N), ws.h + j + 1, p->s));
+    d2h(p, ws.h, j + 2);
+    const double est = lsq.add(j, p->host);
+    steps = j + 1;
+    const bool broke = p->host[j + 1].re <= 1e-14 * beta;
+    if (!broke) HM_CHECK(launch_scale_dev<T>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s));
+    if (broke) break;
+    if (tol >= 0 && est <= tol * beta) break;
+  }
+  std::vector<c128> y;
+  lsq.solve(steps, y);
+  h2d_coef(p, y);
+  HM_CHECK(launch_combine<T>(V, N, steps, p->coef, 1.0, x, 0, N, p->s));
+  p->rec[kind].push_back(steps);
+  return steps;
+}
+
+// ---- multigrid V-cycle for the CSLP of level l -----------------------------------
+template <typename T>
+static const cx<T>* mg_cycle(hm_problem* p, DefLevel& D, int q, const cx<T>* b) {
+  MGHier& H = D.mg;
+  MGLevel& m = H.lv[q];
+  const OpDesc<T>& op = mgop<T>(m);
+  const T* k = mgk<T>(D, q);
+  cx<T>* x = (cx<T>*)m.x;
+  cx<T>* y = (cx<T>*)m.y;
+  if (q == (int)H.lv.size() - 1) {
+    if (H.dense) {
+      HM_CHECK(launch_dense_matvec<T>((const cx<T>*)H.inv, (int)m.N, b, x, p->s));
+      return x;
+    }
+    gmres_cgs<T>(p, op, k, H.gm, H.maxit, p->cfg.tol_cslp, K_MGC, b, x);
+    return x;
+  }
+  const T om = (T)m.omega;
+  HM_CHECK(launch_jacobi0<T>(op, k, b, x, om, p->s));
+  for (int s = 1; s < p->cfg.mg_nu_pre; ++s) {
+    HM_CHECK(launch_stencil<T>(op, ST_JACOBI, x, k, b, y, om, p->s));
+    std::swap(x, y);
+  }
+  cx<T>* r = (cx<T>*)m.r;
+  HM_CHECK(launch_stencil<T>(op, ST_RESID, x, k, b, r, T(0), p->s));
+  MGLevel& mc = H.lv[q + 1];
+  HM_CHECK(launch_restrict_fw<T>(r, m.nx, m.ny, (cx<T>*)mc.b, p->s));
+  const cx<T>* e = mg_cycle<T>(p, D, q + 1, (const cx<T>*)mc.b);
+  HM_CHECK(launch_prolong_bilinear_add<T>(e, m.nx, m.ny, x, p->s));
+  for (int s = 0; s < p->cfg.mg_nu_post; ++s) {
+    HM_CHECK(launch_stencil<T>(op, ST_JACOBI, x, k, b, y, om, p->s));
+    std::swap(x, y);
+  }
+  return x;
+}
+
+}  // namespace hm
+
+namespace hm {
+
+template <typename T> static void precond(hm_problem* p, int l, const cx<T>* v, cx<T>* x);
+
+// CSLP^-1 approximation of level l: one V-cycle (levels 1-2) or GMRES.  Returns
+// the buffer holding the result (`out` for GMRES, a multigrid buffer otherwise).
+template <typename T>
+static const cx<T>* cslp_apply(hm_problem* p, int l, const cx<T>* r, cx<T>* out) {
+  DefLevel& D = p->lev[l];
+  if (D.has_mg) return mg_cycle<T>(p, D, 0, r);
+  gmres_cgs<T>(p, opsel<T>(D, true), levk<T>(D), D.cslp, D.cslp_maxit, p->cfg.tol_cslp, K_CSLP, r,
+               out);
+  return out;
+}
+
+// FGMRES with modified Gram-Schmidt (Algorithm 1) on the operator of level c,
+// zero initial guess.  Preconditioner: Prec_c (c < L) or the Krylov CSLP (c == L).
+template <typename T>
+static int fgmres_level(hm_problem* p, int c, const cx<T>* b, cx<T>* x, double tol, int maxit,
+                        int kind) {
+  DefLevel& D = p->lev[c];
+  KrylovWS& ws = D.fg;
+  const size_t N = D.N;
+  cx<T>* V = (cx<T>*)ws.V;
+  cx<T>* X = (cx<T>*)ws.X;
+  cx<T>* w = (cx<T>*)ws.w;
+  HM_CHECK(launch_norm<T>(b, N, rbuf(p, N), ws.h, p->s));
+  d2h(p, ws.h, 1);
+  const double beta = p->host[0].re;
+  if (beta == 0.0) {
+    HM_CHECK(launch_zero<T>(x, N, p->s));
+    if (kind >= 0) p->rec[kind].push_back(0);
+    return 0;
+  }
+  if (kind >= 0) {
+    const int forced = forced_count(p, kind);
+    if (forced >= 0) {
+      maxit = forced;
+      tol = -1;
+    }
+  }
+  if (maxit > ws.cap) throw ArgError("FGMRES step count exceeds the workspace");
+  HM_CHECK(launch_scale_dev<T>(b, V, ws.h, 1, N, p->s));
+  LSQ lsq;
+  lsq.init(maxit, beta);
+  int steps = 0;
+  for (int j = 0; j < maxit; ++j) {
+    cx<T>* Vj = V + (size_t)j * N;
+    cx<T>* Xj = X + (size_t)j * N;
+    if (c == p->L) {
+      cslp_apply<T>(p, c, Vj, Xj);
+    } else {
+      precond<T>(p, c, Vj, Xj);
+    }
+    apply_level<T>(p, D, false, ST_APPLY, Xj, nullptr, w);
+    for (int i = 0; i <= j; ++i)
+      HM_CHECK(launch_mgs_step<T>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr, ws.h + i - 1,
+                                  V + (size_t)i * N, N, rbuf(p, N), ws.h + i, p->s));
+    HM_CHECK(launch_mgs_step<T>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s));
+    d2h(p, ws.h, j + 2);
+    const double est = lsq.add(j, p->host);
+    steps = j + 1;
+    const bool broke = p->host[j + 1].re <= 1e-14 * beta;
+    if (!broke) HM_CHECK(launch_scale_dev<T>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s));
+    if (broke) break;
+    if (tol >= 0 && est <= tol * beta) break;
+  }
+  std::vector<c128> y;
+  lsq.solve(steps, y);
+  h2d_coef(p, y);
+  HM_CHECK(launch_combine<T>(X, N, steps, p->coef, 1.0, x, 0, N, p->s));
+  if (kind >= 0) p->rec[kind].push_back(steps);
+  return steps;
+}
+
+// Coarse problem E_c x = b of level c (Algorithm 1, lines "restriction" to
+// "interpolation"): level-2 FGMRES to tol_level2, one step elsewhere.
+template <typename T>
+static void coarse_solve(hm_problem* p, int c, const cx<T>* b, cx<T>* x) {
+  if (c == p->L) {
+    fgmres_level<T>(p, c, b, x, -1.0, 1, -1);
+  } else if (c == 2) {
+    fgmres_level<T>(p, c, b, x, p->cfg.tol_level2, p->cfg.level2_maxit, K_LEVEL2);
+  } else {
+    fgmres_level<T>(p, c, b, x, -1.0, 1, -1);
+  }
+}
+
+template <typename T, typename Tn>
+static void coarse_branch(hm_problem* p, int l, const cx<T>* v) {
+  DefLevel& D = p->lev[l];
+  DefLevel& C = p->lev[l + 1];
+  HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, (cx<Tn>*)C.rhs, p->s));
+  coarse_solve<Tn>(p, l + 1, (const cx<Tn>*)C.rhs, (cx<Tn>*)C.sol);
+  HM_CHECK(launch_prolong_z<Tn, T>((const cx<Tn>*)C.sol, D.nx, D.ny, (cx<T>*)D.t, p->s));
+}
+
+// Prec_l(v) = M_l^-1 (v - A_l t) + t,  t = Z E^-1 Z^T v   (A-DEF1, Sec. 3.1)
+template <typename T>
+static void precond(hm_problem* p, int l, const cx<T>* v, cx<T>* x) {
+  DefLevel& D = p->lev[l];
+  if (p->lev[l + 1].dbl)
+    coarse_branch<T, double>(p, l, v);
+  else
+    coarse_branch<T, float>(p, l, v);
+  cx<T>* t = (cx<T>*)D.t;
+  cx<T>* rt = (cx<T>*)D.rt;
+  apply_level<T>(p, D, false, ST_RESID, t, v, rt);          // r~ = v - A t
+  const cx<T>* r = cslp_apply<T>(p, l, rt, (cx<T>*)D.xo);    // r ~ M^-1 r~
+  HM_CHECK(launch_add<T>(r, t, x, D.N, p->s));                // x = r + t
+}
+
+// Finest-level preconditioner on complex128 vectors (casts in mixed mode).
+static void precond_top(hm_problem* p, const c128* v, c128* x) {
+  const size_t N = p->lev[1].N;
+  if (p->mixed) {
+    HM_CHECK(launch_convert<double, float>(v, (c64*)p->pin_v, N, p->s));
+    precond<float>(p, 1, (const c64*)p->pin_v, (c64*)p->pin_x);
+    HM_CHECK(launch_convert<float, double>((const c64*)p->pin_x, x, N, p->s));
+  } else {
+    precond<double>(p, 1, v, x);
+  }
+}
+
+// Outer FGMRES (Algorithm 1 at level 1, FP64, restarted).
+static hm_status outer_solve(hm_problem* p, const c128* b, c128* u, hm_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  DefLevel& D = p->lev[1];
+  KrylovWS& ws = p->outer;
+  const size_t N = D.N;
+  c128* V = (c128*)ws.V;
+  c128* X = (c128*)ws.X;
+  c128* w = (c128*)ws.w;
+  const hm_config& cf = p->cfg;
+  const size_t rec0[K_NKIND] = {p->rec[0].size(), p->rec[1].size(), p->rec[2].size(),
+                                p->rec[3].size()};
+  HM_CHECK(launch_norm<double>(b, N, rbuf(p, N), ws.h, p->s));
+  d2h(p, ws.h, 1);
+  const double bnorm = p->host[0].re;
+  HM_CHECK(launch_zero<double>(u, N, p->s));
+  int total = 0;
+  double rel_true = 0, est_rel = 0;
+  while (true) {
+    HM_CHECK(launch_stencil<double>(D.A64, ST_RESID, u, D.k64, b, p->tmp64, 0.0, p->s));
+    HM_CHECK(launch_norm<double>(p->tmp64, N, rbuf(p, N), ws.h, p->s));
+    d2h(p, ws.h, 1);
+    const double rnorm = p->host[0].re;
+    rel_true = bnorm > 0 ? rnorm / bnorm : 0.0;
+    if (bnorm == 0.0 || rnorm <= cf.tol_outer * bnorm || total >= cf.outer_maxit) break;
+    int m = std::min(cf.outer_restart, cf.outer_maxit - total);
+    double tol = cf.tol_outer;
+    const int forced = forced_count(p, K_OUTER);
+    if (forced >= 0) {
+      m = forced;
+      tol = -1;
+    }
+    if (m > ws.cap) throw ArgError("outer step count exceeds the restart length");
+    HM_CHECK(launch_scale_dev<double>(p->tmp64, V, ws.h, 1, N, p->s));
+    LSQ lsq;
+    lsq.init(m, rnorm);
+    int steps = 0;
+    for (int j = 0; j < m; ++j) {
+      c128* Vj = V + (size_t)j * N;
+      c128* Xj = X + (size_t)j * N;
+      precond_top(p, Vj, Xj);
+      HM_CHECK(launch_stencil<double>(D.A64, ST_APPLY, Xj, D.k64, nullptr, w, 0.0, p->s));
+      for (int i = 0; i <= j; ++i)
+        HM_CHECK(launch_mgs_step<double>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr, ws.h + i - 1,
+                                         V + (size_t)i * N, N, rbuf(p, N), ws.h + i, p->s));
+      HM_CHECK(launch_mgs_step<double>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s));
+      d2h(p, ws.h, j + 2);
+      const double est = lsq.add(j, p->host);
+      est_rel = bnorm > 0 ? est / bnorm : 0.0;
+      steps = j + 1;
+      const bool broke = p->host[j + 1].re <= 1e-14 * rnorm;
+      if (!broke) HM_CHECK(launch_scale_dev<double>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s));
+      if (broke) break;
+      if (tol >= 0 && est <= tol * bnorm) break;
+    }
+    std::vector<c128> y;
+    lsq.solve(steps, y);
+    h2d_coef(p, y);
+    HM_CHECK(launch_combine<double>(X, N, steps, p->coef, 1.0, u, 1, N, p->s));
+    total += steps;
+    p->rec[K_OUTER].push_back(steps);
+  }
+  HM_CHECK(hipStreamSynchronize(p->s));
+  p->last_estimate = est_rel;
+  if (info) {
+    auto sum_since = [&](int kind) {
+      long s = 0;
+      for (size_t i = rec0[kind]; i < p->rec[kind].size(); ++i) s += p->rec[kind][i];
+      return (int)s;
+    };
+    info->outer_iters = total;
+    info->level2_iters_total = sum_since(K_LEVEL2);
+    info->cslp_iters_total = sum_since(K_CSLP);
+    info->mg_coarse_iters_total = sum_since(K_MGC);
+    info->rel_res_estimate = est_rel;
+    info->rel_res_true = rel_true;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return rel_true <= cf.tol_outer ? HM_OK : HM_NOT_CONVERGED;
+}
+
+// ---- set-up ------------------------------------------------------------------------
+
+static bool validate(const hm_config* c, std::string* why) {
+  auto bad = [&](const char* m) { if (why) *why = m; return false; };
+  if (!c) return bad("null config");
+  if (c->levels < 2 || c->levels > 6) return bad("levels must be in [2, 6]");
+  const int f = 1 << (c->levels - 1);
+  if (c->nx < 3 || c->ny < 3) return bad("grid too small");
+  if ((c->nx - 1) % f || (c->ny - 1) % f) return bad("(n-1) must be divisible by 2^(levels-1)");
+  if ((c->nx - 1) / f + 1 < 3 || (c->ny - 1) / f + 1 < 3) return bad("coarsest level below 3 nodes");
+  if (!(c->h > 0) || !std::isfinite(c->h)) return bad("h must be positive");
+  if (c->bc != HM_BC_SOMMERFELD) return bad("only Sommerfeld boundaries are supported");
+  if (!std::isfinite(c->beta1) || !std::isfinite(c->beta2)) return bad("beta not finite");
+  if (c->precision != HM_FP64 && c->precision != HM_MIXED_FP32) return bad("precision");
+  if (c->outer_restart < 1 || c->outer_maxit < 1 || c->level2_maxit < 1) return bad("step caps");
+  if (c->mg_nu_pre < 1 || c->mg_nu_post < 0) return bad("smoothing steps");
+  if (!(c->tol_outer > 0) || !(c->tol_level2 > 0) || !(c->tol_cslp > 0) || !(c->maxit_coef > 0))
+    return bad("tolerances");
+  for (int r : c->reserved)
+    if (r != 0) return bad("reserved fields must be zero");
+  return true;
+}
+
+static bool can_coarsen(int nx, int ny) {
+  return (nx - 1) % 2 == 0 && (ny - 1) % 2 == 0 && (nx - 1) / 2 + 1 >= 3 && (ny - 1) / 2 + 1 >= 3;
+}
+
+// Lays out the workspace (sizes + pointers) and fills the static level data.
+static void plan(hm_problem* p, Carver& cv) {
+  const hm_config& c = p->cfg;
+  p->L = c.levels;
+  p->mixed = c.precision == HM_MIXED_FP32;
+  p->lev.assign(p->L + 2, DefLevel());
+  const cd sig_m(c.beta1, c.beta2);
+  int mmax = c.outer_restart + 2;
+  int nx = c.nx, ny = c.ny;
+  auto esz = [](bool dbl) { return dbl ? sizeof(c128) : sizeof(c64); };
+  for (int l = 1; l <= p->L; ++l) {
+    DefLevel& D = p->lev[l];
+    D.l = l; D.nx = nx; D.ny = ny; D.N = (size_t)nx * ny;
+    D.hl = c.h * std::ldexp(1.0, l - 1);
+    D.sl = std::ldexp(1.0, 2 * (l - 1));
+    D.dbl = (l >= 3) || !p->mixed;
+    const size_t es = esz(D.dbl);
+    D.k64 = cv.take<double>(D.N);
+    if (!D.dbl) D.k32 = cv.take<float>(D.N);
+    if (l == 1) {
+      set_five_point(D.A64, nx, ny, c.h, 1.0, cd(1, 0));
+      set_five_point(D.M64, nx, ny, c.h, 1.0, sig_m);
+      set_five_point(D.A32, nx, ny, c.h, 1.0, cd(1, 0));
+      set_five_point(D.M32, nx, ny, c.h, 1.0, sig_m);
+    } else {
+      set_wide(D.A64, nx, ny, c.h, l, cd(1, 0));
+      set_wide(D.M64, nx, ny, c.h, l, sig_m);
+      set_wide(D.A32, nx, ny, c.h, l, cd(1, 0));
+      set_wide(D.M32, nx, ny, c.h, l, sig_m);
+    }
+    if (l >= 2) {
+      D.fg.cap = (l == 2 && p->L > 2) ? c.level2_maxit : 1;
+      D.fg.N = D.N;
+      D.fg.V = cv.take<char>((size_t)(D.fg.cap + 1) * D.N * es);
+      D.fg.X = cv.take<char>((size_t)D.fg.cap * D.N * es);
+      D.fg.w = cv.take<char>(D.N * es);
+      D.fg.h = cv.take<c128>(D.fg.cap + 2);
+      D.rhs = cv.take<char>(D.N * es);
+      D.sol = cv.take<char>(D.N * es);
+      mmax = std::max(mmax, D.fg.cap + 2);
+    }
+    if (l < p->L) {
+      D.t = cv.take<char>(D.N * es);
+      D.rt = cv.take<char>(D.N * es);
+      D.xo = cv.take<char>(D.N * es);
+    }
+    if (l <= 2) {
+      D.has_mg = true;
+      MGHier& H = D.mg;
+      H.lv.clear();
+      int mx = nx, my = ny;
+      double Hs = D.hl;
+      for (int q = 0;; ++q) {
+        MGLevel m;
+        m.nx = mx; m.ny = my; m.N = (size_t)mx * my; m.H = Hs;
+        if (q == 0) {
+          m.op64 = D.M64;
+          m.op32 = D.M32;
+        } else {
+          set_five_point(m.op64, mx, my, Hs, D.sl, sig_m);
+          set_five_point(m.op32, mx, my, Hs, D.sl, sig_m);
+          m.k = cv.take<double>(m.N);
+          if (!D.dbl) m.k32 = cv.take<float>(m.N);
+          m.b = cv.take<char>(m.N * es);
+        }
+        m.x = cv.take<char>(m.N * es);
+        m.y = cv.take<char>(m.N * es);
+        m.r = cv.take<char>(m.N * es);
+        H.lv.push_back(m);
+        if (!can_coarsen(mx, my)) break;
+        mx = (mx - 1) / 2 + 1;
+        my = (my - 1) / 2 + 1;
+        Hs *= 2;
+      }
+      MGLevel& last = H.lv.back();
+      H.dense = last.N <= (size_t)kDenseMax;
+      if (H.dense) {
+        H.inv = cv.take<char>(last.N * last.N * es);
+        H.tmpA = cv.take<c128>(last.N * last.N);
+        H.tmpB = cv.take<c128>(last.N * last.N);
+      } else {
+        H.maxit = krylov_maxit(last.N, c.maxit_coef);
+        H.gm.cap = H.maxit;
+        H.gm.N = last.N;
+        H.gm.V = cv.take<char>((size_t)(H.maxit + 1) * last.N * es);
+        H.gm.w = cv.take<char>(last.N * es);
+        H.gm.h = cv.take<c128>(H.maxit + 2);
+        mmax = std::max(mmax, H.maxit + 2);
+      }
+    } else {
+      D.cslp_maxit = krylov_maxit(D.N, c.maxit_coef);
+      D.cslp.cap = D.cslp_maxit;
+      D.cslp.N = D.N;
+      D.cslp.V = cv.take<char>((size_t)(D.cslp_maxit + 1) * D.N * es);
+      D.cslp.w = cv.take<char>(D.N * es);
+      D.cslp.h = cv.take<c128>(D.cslp_maxit + 2);
+      mmax = std::max(mmax, D.cslp_maxit + 2);
+    }
+    if (l < p->L) {
+      nx = (nx - 1) / 2 + 1;
+      ny = (ny - 1) / 2 + 1;
+    }
+  }
+  DefLevel& D1 = p->lev[1];
+  KrylovWS& o = p->outer;
+  o.cap = c.outer_restart;
+  o.N = D1.N;
+  o.V = cv.take<c128>((size_t)(o.cap + 1) * D1.N);
+  o.X = cv.take<c128>((size_t)o.cap * D1.N);
+  o.w = cv.take<c128>(D1.N);
+  o.h = cv.take<c128>(o.cap + 2);
+  p->tmp64 = cv.take<c128>(D1.N);
+  if (p->mixed) {
+    p->pin_v = cv.take<c64>(D1.N);
+    p->pin_x = cv.take<c64>(D1.N);
+  }
+  p->rb.partials = cv.take<c128>((size_t)kMaxChunks * (mmax + 2));
+  p->rb.nchunks = 0;   // chosen per reduction from its length (rbuf)
+  p->scal = cv.take<c128>(16);
+  p->coef_cap = mmax + 2;
+  p->coef = cv.take<c128>(p->coef_cap);
+}
+
+}  // namespace hm
+
+namespace hm {
+
+// Gauss-Jordan inversion with partial pivoting (host, FP64), row-major.
+static void invert_dense(std::vector<cd>& A, int n) {
+  std::vector<cd> I((size_t)n * n, cd(0));
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    double best = std::abs(A[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r) {
+      const double v = std::abs(A[(size_t)r * n + c]);
+      if (v > best) { best = v; piv = r; }
+    }
+    if (best == 0.0) throw ArgError("singular coarsest multigrid operator");
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]);
+        std::swap(I[(size_t)c * n + k], I[(size_t)piv * n + k]);
+      }
+    const cd d = 1.0 / A[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[(size_t)c * n + k] *= d;
+      I[(size_t)c * n + k] *= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const cd f = A[(size_t)r * n + c];
+      if (f == cd(0)) continue;
+      for (int k = 0; k < n; ++k) {
+        A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+        I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
+      }
+    }
+  }
+  A.swap(I);
+}
+
+static double omega_rule(double kmax, double H) { return kmax * kmax * H * H <= 1.0 ? 0.8 : 0.5; }
+
+static void initialize(hm_problem* p, const double* k_dev) {
+  DefLevel& D1 = p->lev[1];
+  HM_CHECK(hipMemcpyAsync(D1.k64, k_dev, sizeof(double) * D1.N, hipMemcpyDeviceToDevice, p->s));
+  {
+    const size_t N = D1.N;
+    HM_CHECK(launch_check_k(D1.k64, N, rbuf(p, N), p->scal, p->s));
+    d2h(p, p->scal, 1);
+    if (p->host[0].re != 0.0) throw ArgError("wavenumber field has negative or non-finite entries");
+  }
+  for (int l = 2; l <= p->L; ++l) {
+    const DefLevel& F = p->lev[l - 1];
+    HM_CHECK(launch_inject<double, double>(F.k64, F.nx, F.ny, p->lev[l].k64, p->s));
+  }
+  for (int l = 1; l <= p->L; ++l) {
+    DefLevel& D = p->lev[l];
+    if (!D.dbl) HM_CHECK(launch_convert_real<double, float>(D.k64, D.k32, D.N, p->s));
+    const size_t N = D.N;
+    HM_CHECK(launch_max_real(D.k64, N, rbuf(p, N), p->scal, p->s));
+    d2h(p, p->scal, 1);
+    D.kmax = p->host[0].re;
+    if (!D.has_mg) continue;
+    MGHier& H = D.mg;
+    for (size_t q = 0; q < H.lv.size(); ++q) {
+      MGLevel& m = H.lv[q];
+      m.omega = omega_rule(D.kmax, m.H);
+      if (q >= 1) {
+        const MGLevel& f = H.lv[q - 1];
+        const double* kf = q == 1 ? D.k64 : f.k;
+        HM_CHECK(launch_inject<double, double>(kf, f.nx, f.ny, m.k, p->s));
+        if (!D.dbl) HM_CHECK(launch_convert_real<double, float>(m.k, m.k32, m.N, p->s));
+      }
+    }
+    if (H.dense) {
+      const int q = (int)H.lv.size() - 1;
+      MGLevel& m = H.lv[q];
+      const int n = (int)m.N;
+      const double* kq = mgk<double>(D, q);
+      HM_CHECK(launch_identity(H.tmpA, n, p->s));
+      for (int j = 0; j < n; ++j)
+        HM_CHECK(launch_stencil<double>(m.op64, ST_APPLY, H.tmpA + (size_t)j * n, kq, nullptr,
+                                        H.tmpB + (size_t)j * n, 0.0, p->s));
+      std::vector<c128> cols((size_t)n * n);
+      HM_CHECK(hipMemcpyAsync(cols.data(), H.tmpB, sizeof(c128) * cols.size(),
+                              hipMemcpyDeviceToHost, p->s));
+      HM_CHECK(hipStreamSynchronize(p->s));
+      std::vector<cd> A((size_t)n * n);
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          const c128 v = cols[(size_t)j * n + i];   // (M e_j)_i = M[i][j]
+          A[(size_t)i * n + j] = cd(v.re, v.im);
+        }
+      invert_dense(A, n);
+      if (D.dbl) {
+        std::vector<c128> up((size_t)n * n);
+        for (size_t i = 0; i < up.size(); ++i) up[i] = mk(A[i].real(), A[i].imag());
+        HM_CHECK(hipMemcpyAsync(H.inv, up.data(), sizeof(c128) * up.size(), hipMemcpyHostToDevice, p->s));
+        HM_CHECK(hipStreamSynchronize(p->s));
+      } else {
+        std::vector<c64> up((size_t)n * n);
+        for (size_t i = 0; i < up.size(); ++i) up[i] = mk((float)A[i].real(), (float)A[i].imag());
+        HM_CHECK(hipMemcpyAsync(H.inv, up.data(), sizeof(c64) * up.size(), hipMemcpyHostToDevice, p->s));
+        HM_CHECK(hipStreamSynchronize(p->s));
+      }
+    }
+  }
+  HM_CHECK(hipStreamSynchronize(p->s));
+}
+
+// ---- component access (tests) --------------------------------------------------------
+
+template <typename T>
+static const cx<T>* to_level(hm_problem* p, const c128* in, size_t n, void* tmp) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    (void)p; (void)n; (void)tmp;
+    return (const cx<T>*)in;
+  } else {
+    HM_CHECK(launch_convert<double, float>(in, (c64*)tmp, n, p->s));
+    return (const cx<T>*)tmp;
+  }
+}
+template <typename T>
+static cx<T>* out_level(c128* out, void* tmp) {
+  if constexpr (sizeof(T) == sizeof(double)) { (void)tmp; return (cx<T>*)out; }
+  else return (cx<T>*)tmp;
+}
+template <typename T>
+static void from_level(hm_problem* p, const cx<T>* buf, c128* out, size_t n) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    if ((const void*)buf != (const void*)out)
+      HM_CHECK(hipMemcpyAsync(out, buf, sizeof(c128) * n, hipMemcpyDeviceToDevice, p->s));
+  } else {
+    HM_CHECK(launch_convert<float, double>((const c64*)buf, out, n, p->s));
+  }
+}
+
+template <typename T, typename Tn>
+static void op_transfer(hm_problem* p, int l, int which, const c128* in, c128* out) {
+  DefLevel& D = p->lev[l];
+  DefLevel& C = p->lev[l + 1];
+  if (which == HM_OP_ZT) {
+    const cx<T>* v = to_level<T>(p, in, D.N, p->pin_v);
+    cx<Tn>* o = out_level<Tn>(out, p->pin_x);
+    HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, o, p->s));
+    from_level<Tn>(p, o, out, C.N);
+  } else {
+    const cx<Tn>* v = to_level<Tn>(p, in, C.N, p->pin_v);
+    cx<T>* o = out_level<T>(out, p->pin_x);
+    HM_CHECK(launch_prolong_z<Tn, T>(v, D.nx, D.ny, o, p->s));
+    from_level<T>(p, o, out, D.N);
+  }
+}
+
+template <typename T>
+static void op_level(hm_problem* p, int l, int sub, int which, const c128* in, c128* out) {
+  DefLevel& D = p->lev[l];
+  size_t nin = D.N, nout = D.N;
+  if (which >= HM_OP_MG_M) {
+    if (!D.has_mg || sub < 0 || sub >= (int)D.mg.lv.size()) throw ArgError("no such multigrid level");
+    if ((which == HM_OP_MG_RESTRICT || which == HM_OP_MG_PROLONG) && sub + 1 >= (int)D.mg.lv.size())
+      throw ArgError("no coarser multigrid level");
+    nin = nout = D.mg.lv[sub].N;
+    if (which == HM_OP_MG_RESTRICT) nout = D.mg.lv[sub + 1].N;
+    if (which == HM_OP_MG_PROLONG) nin = D.mg.lv[sub + 1].N;
+  }
+  const cx<T>* v = to_level<T>(p, in, nin, p->pin_v);
+  cx<T>* o = out_level<T>(out, p->pin_x);
+  switch (which) {
+    case HM_OP_A: apply_level<T>(p, D, false, ST_APPLY, v, nullptr, o); break;
+    case HM_OP_M: apply_level<T>(p, D, true, ST_APPLY, v, nullptr, o); break;
+    case HM_OP_VCYCLE: {
+      if (!D.has_mg) throw ArgError("level has no multigrid hierarchy");
+      const cx<T>* r = mg_cycle<T>(p, D, 0, v);
+      HM_CHECK(hipMemcpyAsync(o, r, sizeof(cx<T>) * D.N, hipMemcpyDeviceToDevice, p->s));
+      break;
+    }
+    case HM_OP_CSLP: {
+      const cx<T>* r = cslp_apply<T>(p, l, v, o);
+      if (r != o) HM_CHECK(hipMemcpyAsync(o, r, sizeof(cx<T>) * D.N, hipMemcpyDeviceToDevice, p->s));
+      break;
+    }
+    case HM_OP_PRECOND:
+      if (l >= p->L) throw ArgError("no preconditioner on the coarsest level");
+      precond<T>(p, l, v, o);
+      break;
+    case HM_OP_MG_M: {
+      const MGLevel& m = D.mg.lv[sub];
+      HM_CHECK(launch_stencil<T>(mgop<T>(m), ST_APPLY, v, mgk<T>(D, sub), nullptr, o, T(0), p->s));
+      break;
+    }
+    case HM_OP_MG_JACOBI: {
+      const MGLevel& m = D.mg.lv[sub];
+      HM_CHECK(launch_jacobi0<T>(mgop<T>(m), mgk<T>(D, sub), v, o, (T)m.omega, p->s));
+      break;
+    }
+    case HM_OP_MG_RESTRICT: {
+      const MGLevel& m = D.mg.lv[sub];
+      HM_CHECK(launch_restrict_fw<T>(v, m.nx, m.ny, o, p->s));
+      break;
+    }
+    case HM_OP_MG_PROLONG: {
+      const MGLevel& m = D.mg.lv[sub];
+      HM_CHECK(launch_zero<T>(o, m.N, p->s));
+      HM_CHECK(launch_prolong_bilinear_add<T>(v, m.nx, m.ny, o, p->s));
+      break;
+    }
+    default: throw ArgError("unknown operator");
+  }
+  from_level<T>(p, o, out, nout);
+}
+
+template <typename F>
+static hm_status guard(F&& f) {
+  try {
+    return f();
+  } catch (const ArgError& e) {
+    g_last_error = e.what();
+    return HM_ERR_ARG;
+  } catch (const HipError& e) {
+    g_last_error = e.what();
+    return HM_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return HM_ERR_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HM_ERR_STATE;
+  }
+}
+
+}  // namespace hm
+
+// ================================ C ABI ======================================
+
+extern "C" {
+
+void hm_default_config(hm_config* c, int nx, int ny, double h) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->nx = nx; c->ny = ny; c->h = h;
+  c->bc = HM_BC_SOMMERFELD;
+  c->beta1 = 1.0; c->beta2 = 0.5;
+  c->levels = 3;
+  c->tol_outer = 1e-6; c->tol_level2 = 0.3; c->tol_cslp = 0.1; c->maxit_coef = 6.0;
+  c->outer_restart = 30; c->outer_maxit = 300; c->level2_maxit = 100;
+  c->mg_nu_pre = 1; c->mg_nu_post = 1;
+  c->precision = HM_FP64;
+}
+
+size_t hm_workspace_bytes(const hm_config* cfg) {
+  std::string why;
+  if (!validate(cfg, &why)) {
+    g_last_error = why;
+    return 0;
+  }
+  try {
+    hm_problem tmp;
+    tmp.cfg = *cfg;
+    Carver cv;
+    plan(&tmp, cv);
+    return cv.off;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return 0;
+  }
+}
+
+hm_status hm_create_problem(const hm_config* cfg, const double* k_dev, void* workspace,
+                            size_t workspace_bytes, void* stream, hm_problem** out) {
+  if (out) *out = nullptr;
+  return guard([&]() -> hm_status {
+    std::string why;
+    if (!out) throw ArgError("out is null");
+    if (!validate(cfg, &why)) throw ArgError(why);
+    if (!k_dev || !workspace) throw ArgError("null device pointer");
+    if (((uintptr_t)workspace) & 255) throw ArgError("workspace must be 256-byte aligned");
+    const size_t need = hm_workspace_bytes(cfg);
+    if (workspace_bytes < need) {
+      g_last_error = "workspace too small: need " + std::to_string(need) + " bytes";
+      return HM_ERR_NOMEM;
+    }
+    hm_problem* p = new hm_problem();
+    try {
+      p->cfg = *cfg;
+      p->s = (hipStream_t)stream;
+      Carver cv;
+      cv.base = (char*)workspace;
+      plan(p, cv);
+      p->host_cap = std::max(p->coef_cap, 16);
+      HM_CHECK(hipHostMalloc((void**)&p->host, sizeof(c128) * p->host_cap, hipHostMallocDefault));
+      HM_CHECK(hipHostMalloc((void**)&p->host_coef, sizeof(c128) * p->host_cap, hipHostMallocDefault));
+      initialize(p, k_dev);
+    } catch (...) {
+      hm_destroy_problem(p);
+      throw;
+    }
+    *out = p;
+    return HM_OK;
+  });
+}
+
+hm_status hm_precond_apply(hm_problem* p, const void* v_dev, void* x_dev, void* stream) {
+  return guard([&]() -> hm_status {
+    if (!p || !v_dev || !x_dev) throw ArgError("null argument");
+    if (v_dev == x_dev) throw ArgError("v and x must not alias");
+    p->s = (hipStream_t)stream;
+    precond_top(p, (const c128*)v_dev, (c128*)x_dev);
+    HM_CHECK(hipStreamSynchronize(p->s));
+    return HM_OK;
+  });
+}
+
+hm_status hm_fgmres_solve(hm_problem* p, const void* b_dev, void* u_dev, hm_solve_info* info,
+                          void* stream) {
+  return guard([&]() -> hm_status {
+    if (!p || !b_dev || !u_dev) throw ArgError("null argument");
+    if (b_dev == u_dev) throw ArgError("b and u must not alias");
+    p->s = (hipStream_t)stream;
+    return outer_solve(p, (const c128*)b_dev, (c128*)u_dev, info);
+  });
+}
+
+hm_status hm_apply_operator(hm_problem* p, int level, int sub, int which, const void* in_dev,
+                            void* out_dev, void* stream) {
+  return guard([&]() -> hm_status {
+    if (!p || !in_dev || !out_dev) throw ArgError("null argument");
+    if (level < 1 || level > p->L) throw ArgError("level out of range");
+    if (in_dev == out_dev) throw ArgError("in and out must not alias");
+    p->s = (hipStream_t)stream;
+    const bool dbl = p->lev[level].dbl;
+    if (which == HM_OP_ZT || which == HM_OP_Z) {
+      if (level >= p->L) throw ArgError("no coarser deflation level");
+      const bool dn = p->lev[level + 1].dbl;
+      if (dbl && dn) op_transfer<double, double>(p, level, which, (const c128*)in_dev, (c128*)out_dev);
+      else if (!dbl && dn) op_transfer<float, double>(p, level, which, (const c128*)in_dev, (c128*)out_dev);
+      else if (!dbl && !dn) op_transfer<float, float>(p, level, which, (const c128*)in_dev, (c128*)out_dev);
+      else throw ArgError("unsupported precision layout");
+    } else if (dbl) {
+      op_level<double>(p, level, sub, which, (const c128*)in_dev, (c128*)out_dev);
+    } else {
+      op_level<float>(p, level, sub, which, (const c128*)in_dev, (c128*)out_dev);
+    }
+    HM_CHECK(hipStreamSynchronize(p->s));
+    return HM_OK;
+  });
+}
+
+hm_status hm_level_shape(const hm_problem* p, int level, int sub, int* nx, int* ny) {
+  if (!p || !nx || !ny || level < 1 || level > p->L) return HM_ERR_ARG;
+  const DefLevel& D = p->lev[level];
+  if (sub == 0) {
+    *nx = D.nx; *ny = D.ny;
+    return HM_OK;
+  }
+  if (!D.has_mg || sub < 0 || sub >= (int)D.mg.lv.size()) return HM_ERR_ARG;
+  *nx = D.mg.lv[sub].nx;
+  *ny = D.mg.lv[sub].ny;
+  return HM_OK;
+}
+
+hm_status hm_set_replay(hm_problem* p, int kind, const int* counts, int n) {
+  if (!p || kind < 0 || kind >= K_NKIND || n < 0 || (n > 0 && !counts)) return HM_ERR_ARG;
+  p->rep[kind].assign(counts, counts + n);
+  p->rep_pos[kind] = 0;
+  return HM_OK;
+}
+
+hm_status hm_get_counts(const hm_problem* p, int kind, int* counts, int cap, int* n) {
+  if (!p || kind < 0 || kind >= K_NKIND || !n || cap < 0 || (cap > 0 && !counts)) return HM_ERR_ARG;
+  const std::vector<int>& r = p->rec[kind];
+  *n = (int)r.size();
+  for (int i = 0; i < cap && i < (int)r.size(); ++i) counts[i] = r[i];
+  return HM_OK;
+}
+
+hm_status hm_reset_counts(hm_problem* p) {
+  if (!p) return HM_ERR_ARG;
+  for (int k = 0; k < K_NKIND; ++k) {
+    p->rec[k].clear();
+    p->rep_pos[k] = 0;
+  }
+  return HM_OK;
+}
+
+hm_status hm_destroy_problem(hm_problem* p) {
+  if (!p) return HM_ERR_ARG;
+  if (p->host) (void)hipHostFree(p->host);
+  if (p->host_coef) (void)hipHostFree(p->host_coef);
+  delete p;
+  return HM_OK;
+}
+
+const char* hm_status_string(hm_status s) {
+  switch (s) {
+    case HM_OK: return "ok";
+    case HM_NOT_CONVERGED: return "not converged";
+    case HM_ERR_ARG: return "invalid argument";
+    case HM_ERR_NOMEM: return "workspace too small";
+    case HM_ERR_HIP: return "HIP error";
+    case HM_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* hm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/helmdefl.h declares, and validates configurations on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "helmdefl.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("hm_create_problem", "hm_precond_apply", "hm_fgmres_solve", "hm_workspace_bytes",
+              "hm_destroy_problem", "hm_apply_operator"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    hm = pytest.importorskip("paper_2412_04980_amd")
+    lib = ctypes.CDLL(hm.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(hm.EXPORTED) == _declared()
+
+
+def test_default_config_is_madp():
+    import paper_2412_04980_amd as hm
+    c = hm.default_config(129, 129, 1 / 128)
+    assert (c.levels, c.beta1, c.beta2) == (3, 1.0, 0.5)
+    assert (c.tol_outer, c.tol_level2, c.tol_cslp, c.maxit_coef) == (1e-6, 0.3, 0.1, 6.0)
+    assert (c.outer_restart, c.outer_maxit, c.level2_maxit) == (30, 300, 100)
+    assert (c.mg_nu_pre, c.mg_nu_post, c.precision) == (1, 1, hm.HM_FP64)
+
+
+def test_workspace_bytes_validation():
+    import paper_2412_04980_amd as hm
+    assert hm.workspace_bytes(hm.default_config(129, 129, 1 / 128)) > 0
+    for bad in (dict(nx=130), dict(levels=1), dict(levels=7), dict(h=-1.0), dict(bc=1),
+                dict(precision=5), dict(outer_restart=0), dict(tol_outer=0.0)):
+        c = hm.default_config(129, 129, 1 / 128)
+        for key, val in bad.items():
+            setattr(c, key, val)
+        with pytest.raises(hm.HelmDeflError):
+            hm.workspace_bytes(c)
+    c = hm.default_config(129, 129, 1 / 128)
+    c.reserved[3] = 1
+    with pytest.raises(hm.HelmDeflError):
+        hm.workspace_bytes(c)
+
+
+def test_workspace_grows_with_grid_and_mixed_is_smaller():
+    import paper_2412_04980_amd as hm
+    a = hm.workspace_bytes(hm.default_config(129, 129, 1 / 128))
+    b = hm.workspace_bytes(hm.default_config(257, 257, 1 / 256))
+    assert b > 3 * a
+    f64 = hm.workspace_bytes(hm.default_config(601, 1001, 1.0))
+    mix = hm.workspace_bytes(hm.default_config(601, 1001, 1.0, precision=hm.HM_MIXED_FP32))
+    assert mix < f64
+
+
+def test_status_strings():
+    import paper_2412_04980_amd as hm
+    assert hm.status_string(0) == "ok"
+    assert hm.status_string(-2) == "workspace too small"

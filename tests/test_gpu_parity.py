@@ -1,0 +1,302 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Component tests compare every building block element by element on seeded
+random inputs (several tiles plus ragged edges: 33 x 41 nodes at level 1);
+solver tests compare the preconditioner in fixed-count (replay) mode, where the
+oracle's inner iteration counts make both sides the same map, and full solves
+with the gates of the method: true relative residual <= 1e-6, solution error
+<= 1e-5 against the oracle and outer iteration counts within +-1 (FP64).
+
+Tolerances: FP64 building blocks 1e-13 (relative to the largest entry; the two
+sides differ only in the order of the stencil sums); the preconditioner in
+replay mode 1e-11 (it nests three Krylov solves; the coarsest CSLP GMRES uses
+classical Gram-Schmidt on the GPU and modified Gram-Schmidt in the oracle);
+FP32 building blocks 2e-6 (a few float roundings of O(1) values).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2412_04980_amd as hm
+import workloads
+from oracle.krylov import CountLog
+from oracle.madp import MADP
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def rand_c(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def medium(nx, ny, kval, seed, spread=0.25):
+    rng = np.random.default_rng(seed)
+    return kval * rng.uniform(1 - spread, 1 + spread, nx * ny)
+
+
+def make(nx, ny, h, k, **overrides):
+    cfg = hm.default_config(nx, ny, h)
+    for key, val in overrides.items():
+        setattr(cfg, key, val)
+    return hm.create_problem(cfg, gpu(k))
+
+
+@pytest.fixture(scope="module")
+def small():
+    nx, ny, h = 33, 41, 1.0 / 32
+    k = medium(nx, ny, 11.0, 1)
+    o = MADP(nx, ny, h, k, levels=3)
+    p64 = make(nx, ny, h, k)
+    p32 = make(nx, ny, h, k, precision=hm.HM_MIXED_FP32)
+    yield nx, ny, h, k, o, p64, p32
+    p64.close()
+    p32.close()
+
+
+@pytest.mark.parametrize("level", [1, 2, 3])
+@pytest.mark.parametrize("which", [hm.HM_OP_A, hm.HM_OP_M])
+def test_level_operators(small, level, which):
+    nx, ny, h, k, o, p64, p32 = small
+    lev = o.levels[level]
+    x = rand_c(lev.N, 10 + level)
+    ref = (lev.A if which == hm.HM_OP_A else lev.M) @ x
+    got = host(hm.apply_operator(p64, level, which, gpu(x)))
+    assert relerr(got, ref) <= 1e-13
+    got32 = host(hm.apply_operator(p32, level, which, gpu(x)))
+    tol = 2e-6 if level <= 2 else 1e-13          # level 3 stays FP64 in mixed mode
+    assert relerr(got32, ref) <= tol
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_deflation_transfers(small, level):
+    nx, ny, h, k, o, p64, p32 = small
+    Z = o.levels[level].Z
+    xf = rand_c(Z.shape[0], 20 + level)
+    xc = rand_c(Z.shape[1], 30 + level)
+    assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_ZT, gpu(xf))), Z.T @ xf) <= 1e-14
+    assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_Z, gpu(xc))), Z @ xc) <= 1e-14
+    assert relerr(host(hm.apply_operator(p32, level, hm.HM_OP_ZT, gpu(xf))), Z.T @ xf) <= 2e-6
+    assert relerr(host(hm.apply_operator(p32, level, hm.HM_OP_Z, gpu(xc))), Z @ xc) <= 2e-6
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_multigrid_components(small, level):
+    nx, ny, h, k, o, p64, p32 = small
+    V = o.mg[level]
+    assert hm.level_shape(p64, level, len(V.levels) - 1) == (V.levels[-1].nx, V.levels[-1].ny)
+    for q, lv in enumerate(V.levels):
+        x = rand_c(lv.nx * lv.ny, 40 + q)
+        assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_MG_M, gpu(x), sub=q)),
+                      lv.M @ x) <= 1e-13
+        assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_MG_JACOBI, gpu(x), sub=q)),
+                      lv.omega * x / lv.diag) <= 1e-13
+        if q + 1 < len(V.levels):
+            assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_MG_RESTRICT, gpu(x), sub=q)),
+                          V.R[q] @ x) <= 1e-14
+            c = rand_c(V.levels[q + 1].nx * V.levels[q + 1].ny, 50 + q)
+            assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_MG_PROLONG, gpu(c), sub=q)),
+                          V.P[q] @ c) <= 1e-14
+
+
+@pytest.mark.parametrize("level", [1, 2])
+def test_vcycle(small, level):
+    nx, ny, h, k, o, p64, p32 = small
+    x = rand_c(o.levels[level].N, 60 + level)
+    ref = o.mg[level](x)
+    assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_VCYCLE, gpu(x))), ref) <= 1e-12
+    assert relerr(host(hm.apply_operator(p32, level, hm.HM_OP_VCYCLE, gpu(x))), ref) <= 1e-5
+
+
+def test_coarsest_cslp_gmres(small):
+    nx, ny, h, k, o, p64, p32 = small
+    lev = o.levels[3]
+    x = rand_c(lev.N, 70)
+    o.log = CountLog("record")
+    ref = o.cslp(3, x)
+    counts = o.log.data["cslp_l3"]
+    hm.reset_counts(p64)
+    got = host(hm.apply_operator(p64, 3, hm.HM_OP_CSLP, gpu(x)))
+    assert hm.get_counts(p64, hm.KIND_CSLP) == counts
+    assert relerr(got, ref) <= 1e-11
+
+
+def _replay_all(prob, log):
+    for kind, key in ((hm.KIND_LEVEL2, "level2"), (hm.KIND_CSLP, "cslp_l3"),
+                      (hm.KIND_MG_COARSE, "mg_coarse"), (hm.KIND_OUTER, "outer")):
+        hm.set_replay(prob, kind, log.data.get(key, []))
+
+
+def _replay_off(prob):
+    for kind in range(4):
+        hm.set_replay(prob, kind, [])
+
+
+def test_precond_apply_replay(small):
+    nx, ny, h, k, o, p64, p32 = small
+    v = rand_c(nx * ny, 80)
+    o.log = CountLog("record")
+    ref = o.apply(v)
+    _replay_all(p64, o.log)
+    try:
+        got = host(hm.precond_apply(p64, gpu(v)))
+    finally:
+        _replay_off(p64)
+    assert relerr(got, ref) <= 1e-11
+
+
+def test_precond_apply_free_counts_match(small):
+    nx, ny, h, k, o, p64, p32 = small
+    v = rand_c(nx * ny, 81)
+    o.log = CountLog("record")
+    ref = o.apply(v)
+    hm.reset_counts(p64)
+    got = host(hm.precond_apply(p64, gpu(v)))
+    assert hm.get_counts(p64, hm.KIND_LEVEL2) == o.log.data["level2"]
+    assert relerr(got, ref) <= 1e-10
+
+
+def test_precond_mixed_close_to_fp64(small):
+    nx, ny, h, k, o, p64, p32 = small
+    v = rand_c(nx * ny, 82)
+    o.log = CountLog("record")
+    ref = o.apply(v)
+    _replay_all(p32, o.log)
+    try:
+        got = host(hm.precond_apply(p32, gpu(v)))
+    finally:
+        _replay_off(p32)
+    assert relerr(got, ref) <= 1e-4
+
+
+def _solve_pair(prob_name, nx, ny, h, k, src, precision=hm.HM_FP64):
+    o = MADP(nx, ny, h, k, levels=3)
+    b = workloads.point_source(nx, ny, h, *src)
+    u_ref, info_ref = o.solve(b)
+    p = make(nx, ny, h, k, precision=precision)
+    try:
+        u, info = hm.fgmres_solve(p, gpu(b))
+    finally:
+        p.close()
+    u = host(u)
+    err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+    print("%s prec=%d outer gpu=%d oracle=%d rel_res=%.3e err=%.3e" % (
+        prob_name, precision, info["outer_iters"], info_ref["outer_iters"],
+        info["rel_res_true"], err))
+    return o, u, info, u_ref, info_ref, err
+
+
+def test_solve_fp64_config0():
+    p = workloads.config(0)
+    o, u, info, u_ref, info_ref, err = _solve_pair("config0", p.nx, p.ny, p.h, p.k, p.sources[0])
+    assert info["status"] == hm.HM_OK
+    assert info["rel_res_true"] <= 1e-6
+    b = p.rhs()
+    A = o.levels[1].A
+    assert np.linalg.norm(b - A @ u) <= 1e-6 * np.linalg.norm(b)
+    assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+    assert err <= 1e-5
+
+
+def test_solve_mixed_config0():
+    p = workloads.config(0)
+    o, u, info, u_ref, info_ref, err = _solve_pair("config0", p.nx, p.ny, p.h, p.k, p.sources[0],
+                                                   hm.HM_MIXED_FP32)
+    b = p.rhs()
+    A = o.levels[1].A
+    assert info["status"] == hm.HM_OK
+    assert np.linalg.norm(b - A @ u) <= 1e-6 * np.linalg.norm(b)
+    assert err <= 1e-5
+
+
+def test_solve_heterogeneous_gmres_coarsest_multigrid():
+    # 93 x 93: the multigrid hierarchies end on 24 x 24 = 576 > 512 nodes, so the
+    # coarsest multigrid solve is GMRES (nonlinear) on both sides
+    nx = ny = 93
+    h = 1.0 / 92
+    k = medium(nx, ny, 16.0, 5)
+    o, u, info, u_ref, info_ref, err = _solve_pair("gmres-coarse", nx, ny, h, k, (40, 50))
+    assert info["rel_res_true"] <= 1e-6
+    assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+    assert err <= 1e-5
+    assert info["mg_coarse_iters_total"] > 0
+
+
+def test_replayed_solve_matches_oracle_closely():
+    nx = ny = 65
+    h = 1.0 / 64
+    k = medium(nx, ny, 14.0, 6)
+    o = MADP(nx, ny, h, k, levels=3)
+    b = workloads.point_source(nx, ny, h, 20, 33)
+    u_ref, info_ref = o.solve(b)
+    p = make(nx, ny, h, k)
+    try:
+        _replay_all(p, o.log)
+        u, info = hm.fgmres_solve(p, gpu(b))
+    finally:
+        p.close()
+    assert info["outer_iters"] == info_ref["outer_iters"]
+    assert relerr(host(u), u_ref) <= 1e-9
+
+
+def test_zero_rhs_gives_zero():
+    nx = ny = 17
+    p = make(nx, ny, 1 / 16, np.full(nx * ny, 3.0))
+    try:
+        u, info = hm.fgmres_solve(p, torch.zeros(nx * ny, dtype=torch.complex128, device=DEV))
+    finally:
+        p.close()
+    assert info["outer_iters"] == 0 and info["status"] == hm.HM_OK
+    assert not host(u).any()
+
+
+def test_rejects_bad_wavenumber():
+    nx = ny = 17
+    k = np.full(nx * ny, 3.0)
+    k[100] = np.nan
+    with pytest.raises(hm.HelmDeflError) as e:
+        make(nx, ny, 1 / 16, k)
+    assert e.value.status == hm.HM_ERR_ARG
+    k[100] = -1.0
+    with pytest.raises(hm.HelmDeflError):
+        make(nx, ny, 1 / 16, k)
+
+
+def test_rejects_short_workspace():
+    nx = ny = 17
+    cfg = hm.default_config(nx, ny, 1 / 16)
+    ws = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    with pytest.raises(hm.HelmDeflError) as e:
+        hm.create_problem(cfg, gpu(np.full(nx * ny, 3.0)), workspace=ws)
+    assert e.value.status == hm.HM_ERR_NOMEM
+
+
+def test_two_problems_are_independent():
+    nx = ny = 33
+    h = 1 / 32
+    k1, k2 = medium(nx, ny, 9.0, 7), medium(nx, ny, 12.0, 8)
+    b = workloads.point_source(nx, ny, h, 16, 16)
+    pa = make(nx, ny, h, k1)
+    pb = make(nx, ny, h, k2)
+    try:
+        ua, _ = hm.fgmres_solve(pa, gpu(b))
+        ub, _ = hm.fgmres_solve(pb, gpu(b))
+        ua2, _ = hm.fgmres_solve(pa, gpu(b))
+    finally:
+        pa.close()
+        pb.close()
+    assert torch.equal(ua, ua2)
+    assert not torch.equal(ua, ub)
