@@ -1,0 +1,206 @@
+"""Benchmark: MADP-preconditioned FGMRES solves on one MI355X.
+
+One step = one complete solve (outer FGMRES with the 3-level MADP
+preconditioner, i.e. every hot-path kernel) of the constant-wavenumber
+workload k = 200 on the unit square, 4097 x 4097 nodes (h = 1/4096,
+k^3 h^2 = 0.48), Sommerfeld boundaries, point source at the centre, to
+relative residual 1e-6, FP64.  Inputs (wavenumber field, right-hand side) are
+resident in HBM before timing.  The same workload is also solved with the
+mixed-precision preconditioner (FP32 levels 1-2) and reported beside it.
+
+Prints one JSON line: solves/s (value), p50/p99 latency, the roofline of the
+dominant kernel class measured with HIP events inside the timed region, and
+the CPU oracle baseline (a bounded sample scaled to one solve).
+
+    python bench.py [--steps K] [--warmup W] [--config I] [--no-mixed] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1, help="workload index (0-3)")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel event timing")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_solves(hm, torch, prob, b, steps, warmup, timing):
+    u = torch.empty_like(b)
+    for i in range(warmup):
+        hm.fgmres_solve(prob, b, out=u)
+        log("warmup solve %d done" % i)
+    if timing:
+        hm.set_timing(prob, (1 << len(hm.TIMING_CLASSES)) - 1)
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t_start = time.perf_counter()
+    for i in range(steps):
+        t0 = time.perf_counter()
+        _, info = hm.fgmres_solve(prob, b, out=u)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        infos.append(info)
+        log("timed solve %d: %.3f s, outer %d" % (i, lat[-1], info["outer_iters"]))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    kt = hm.get_timing(prob) if timing else {}
+    if timing:
+        hm.set_timing(prob, 0)
+    return u, total, lat, infos, kt
+
+
+def cpu_baseline(problem, info, counts_l3):
+    """The oracle timed on a bounded sample of the same workload: its
+    coarsest-level Krylov CSLP (GMRES, modified Gram-Schmidt, on the level-3
+    grid) with the mean step count of the GPU solve, and one level-1 CSLP
+    V-cycle; projected to one solve as (number of coarsest CSLP solves) x
+    (GMRES time) + (outer steps) x (V-cycle time), a lower bound on the oracle's
+    full solve (all other steps omitted).  BLAS limited to one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import operators as op
+    from oracle.krylov import fgmres
+    from oracle.multigrid import VCycle
+
+    with threadpool_limits(limits=1):
+        nx, ny, h, k = problem.nx, problem.ny, problem.h, problem.k
+        sigma = 1 + 0.5j
+        k2 = op.inject(k, nx, ny)
+        n2x, n2y = (nx - 1) // 2 + 1, (ny - 1) // 2 + 1
+        k3 = op.inject(k2, n2x, n2y)
+        n3x, n3y = (n2x - 1) // 2 + 1, (n2y - 1) // 2 + 1
+        M3 = op.wide_stencil(n3x, n3y, h, 3, k3, sigma)
+        m_mean = int(round(float(np.mean(counts_l3)))) if counts_l3 else 1
+        rng = np.random.default_rng(0)
+        r3 = rng.standard_normal(n3x * n3y) + 1j * rng.standard_normal(n3x * n3y)
+        t0 = time.perf_counter()
+        fgmres(lambda v: M3 @ v, r3, None, tol=None, maxit=m_mean)
+        t_l3 = time.perf_counter() - t0
+        log("oracle coarsest CSLP GMRES (%d steps): %.2f s" % (m_mean, t_l3))
+        del M3
+        M1 = op.five_point(nx, ny, h, k, sigma)
+        V1 = VCycle(nx, ny, h, k, M1, sigma, 1.0)
+        r1 = rng.standard_normal(nx * ny) + 0j
+        t0 = time.perf_counter()
+        V1(r1)
+        t_v1 = time.perf_counter() - t0
+        log("oracle level-1 V-cycle: %.2f s" % t_v1)
+    n_l3 = len(counts_l3)
+    t_solve = n_l3 * t_l3 + info["outer_iters"] * t_v1
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle (FP64, SciPy CSR, 1 BLAS thread) on this workload: one "
+                      "coarsest-level CSLP GMRES of %d steps (%.2f s) and one level-1 "
+                      "V-cycle (%.2f s), projected to one solve as %d x GMRES + %d x "
+                      "V-cycle = %.1f s (lower bound: other steps omitted)"
+                      % (m_mean, t_l3, t_v1, n_l3, info["outer_iters"], t_solve),
+            "projected_seconds_per_solve": t_solve}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (independent "
+              "solves shard across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2412_04980_amd as hm
+    import workloads
+
+    dev = torch.device("cuda:0")
+    problem = workloads.config(args.config)
+    k = torch.from_numpy(problem.k).to(dev)
+    b = torch.from_numpy(problem.rhs(0)).to(dev)
+    cfg = hm.default_config(problem.nx, problem.ny, problem.h)
+    t0 = time.perf_counter()
+    prob = hm.create_problem(cfg, k)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log("fp64 problem set up in %.3f s" % setup_s)
+    u64, total, lat, infos, kt = timed_solves(hm, torch, prob, b, args.steps, args.warmup,
+                                              not args.no_timing)
+    hm.reset_counts(prob)
+    hm.fgmres_solve(prob, b, out=torch.empty_like(b))
+    counts_l3 = hm.get_counts(prob, hm.KIND_CSLP)
+    prob.close()
+    lat_ms = np.array(lat) * 1e3
+    info = infos[-1]
+    res = {
+        "metric": "solves/s + p50/p99 latency, FP32-precond vs FP64, at rel. residual 1e-6",
+        "value": args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": float(total / args.steps * 1e3),
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": problem.name, "nx": problem.nx, "ny": problem.ny,
+                   "h": problem.h, "k": float(problem.k[0]) if args.config in (0, 1) else None,
+                   "levels": cfg.levels, "precond": "MADP (tol L2 0.3, V-cycle L1-L2, "
+                                                    "GMRES CSLP L3)"},
+        "solve": {"outer_iters": info["outer_iters"],
+                  "level2_iters_total": info["level2_iters_total"],
+                  "cslp_iters_total": info["cslp_iters_total"],
+                  "rel_res_true": info["rel_res_true"], "setup_s": setup_s},
+    }
+    if kt:
+        classes = {name: {"ms": ms, "launches": n, "GBps": (by / (ms * 1e-3) / 1e9) if ms else 0.0,
+                          "bytes": by}
+                   for name, (ms, by, n) in kt.items()}
+        dom = max(classes, key=lambda c: classes[c]["ms"])
+        d = classes[dom]
+        res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"],
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                           "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1),
+                           "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1)}
+        res["kernel_classes"] = {c: {"ms_per_solve": v["ms"] / args.steps, "GBps": v["GBps"],
+                                     "launches_per_solve": v["launches"] / args.steps}
+                                 for c, v in classes.items()}
+    if not args.no_mixed:
+        cfgm = hm.default_config(problem.nx, problem.ny, problem.h, precision=hm.HM_MIXED_FP32)
+        probm = hm.create_problem(cfgm, k)
+        um, totm, latm, infm, _ = timed_solves(hm, torch, probm, b, args.steps, args.warmup, False)
+        probm.close()
+        err = float(torch.linalg.vector_norm(um - u64) / torch.linalg.vector_norm(u64))
+        lm = np.array(latm) * 1e3
+        res["mixed"] = {"value": args.steps / totm, "unit": "solves/s",
+                        "p50_ms": float(np.percentile(lm, 50)),
+                        "p99_ms": float(np.percentile(lm, 99)),
+                        "outer_iters": infm[-1]["outer_iters"],
+                        "rel_res_true": infm[-1]["rel_res_true"],
+                        "rel_err_vs_fp64_solution": err, "dtype": "f32 precond / f64 outer"}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(problem, info, counts_l3)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -165,6 +165,24 @@ hm_status hm_set_replay(hm_problem* p, int kind, const int* counts, int n);
 hm_status hm_get_counts(const hm_problem* p, int kind, int* counts, int cap, int* n);
 hm_status hm_reset_counts(hm_problem* p);
 
+/* Kernel timing for roofline measurements.  hm_set_timing(p, mask) resets the
+ * counters and, for every kernel class whose bit is set in mask, brackets each
+ * launch with HIP events on the problem's stream (adds a few microseconds of
+ * host work per launch; mask 0 turns it off).  hm_get_timing returns, for one
+ * class, the summed event time in milliseconds, the summed algorithmic bytes of
+ * those launches (each input array read once, each output written once) and the
+ * number of launches. */
+enum {
+  HM_TK_CGS_DOT = 0,     /* Krylov CSLP: dots of w against the basis (classical GS)    */
+  HM_TK_CGS_UPDATE = 1,  /* Krylov CSLP: w -= V h fused with ||w||                       */
+  HM_TK_WIDE = 2,        /* 5x5 / 7x7 coarse-level operator applications in Krylov loops  */
+  HM_TK_FIVE_POINT = 3,  /* 5-point operator applications in Krylov loops                  */
+  HM_TK_MGS = 4,         /* modified Gram-Schmidt steps (outer and level-2 FGMRES)        */
+  HM_TK_COUNT = 5
+};
+hm_status hm_set_timing(hm_problem* p, unsigned mask);
+hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes, long* launches);
+
 hm_status hm_destroy_problem(hm_problem* p);
 
 const char* hm_status_string(hm_status s);

@@ -35,10 +35,16 @@ HM_OP_MG_M, HM_OP_MG_JACOBI, HM_OP_MG_RESTRICT, HM_OP_MG_PROLONG = 7, 8, 9, 10
 
 KIND_LEVEL2, KIND_CSLP, KIND_MG_COARSE, KIND_OUTER = 0, 1, 2, 3
 
+# kernel classes of hm_set_timing / hm_get_timing
+HM_TK_CGS_DOT, HM_TK_CGS_UPDATE, HM_TK_WIDE, HM_TK_FIVE_POINT, HM_TK_MGS = range(5)
+TIMING_CLASSES = {HM_TK_CGS_DOT: "cgs_dot", HM_TK_CGS_UPDATE: "cgs_update_norm",
+                  HM_TK_WIDE: "wide_stencil_apply", HM_TK_FIVE_POINT: "five_point_apply",
+                  HM_TK_MGS: "mgs_step"}
+
 EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_precond_apply",
             "hm_fgmres_solve", "hm_apply_operator", "hm_level_shape", "hm_set_replay",
-            "hm_get_counts", "hm_reset_counts", "hm_destroy_problem", "hm_status_string",
-            "hm_last_error"]
+            "hm_get_counts", "hm_reset_counts", "hm_set_timing", "hm_get_timing",
+            "hm_destroy_problem", "hm_status_string", "hm_last_error"]
 
 
 class HmConfig(ctypes.Structure):
@@ -78,7 +84,7 @@ class HelmDeflError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libhelmdefl.so is not built (expected at %s); run "
-                          "`python -m paper_2412_04980_amd.build`" % LIB_PATH)
+                          "`python paper_2412_04980_amd/build.py`" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     P, V, I, D = ctypes.c_void_p, None, ctypes.c_int, ctypes.c_double
     sig = {
@@ -93,6 +99,9 @@ def _load():
         "hm_set_replay": (I, [P, I, ctypes.POINTER(I), I]),
         "hm_get_counts": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "hm_reset_counts": (I, [P]),
+        "hm_set_timing": (I, [P, ctypes.c_uint]),
+        "hm_get_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D),
+                              ctypes.POINTER(ctypes.c_long)]),
         "hm_destroy_problem": (I, [P]),
         "hm_status_string": (ctypes.c_char_p, [I]),
         "hm_last_error": (ctypes.c_char_p, []),
@@ -249,6 +258,22 @@ def get_counts(prob, kind):
 
 def reset_counts(prob):
     _check(_lib.hm_reset_counts(prob.handle))
+
+
+def set_timing(prob, mask):
+    """Enables HIP-event timing of the kernel classes in `mask` (bit per class)."""
+    _check(_lib.hm_set_timing(prob.handle, ctypes.c_uint(mask)))
+
+
+def get_timing(prob):
+    """{class name: (milliseconds, algorithmic bytes, launches)} since set_timing."""
+    out = {}
+    for cls, name in TIMING_CLASSES.items():
+        ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_long()
+        _check(_lib.hm_get_timing(prob.handle, cls, ctypes.byref(ms), ctypes.byref(by),
+                                  ctypes.byref(n)))
+        out[name] = (ms.value, by.value, n.value)
+    return out
 
 
 def destroy_problem(prob):

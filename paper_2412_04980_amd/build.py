@@ -1,6 +1,7 @@
 """Builds libhelmdefl.so (the C-ABI MADP library) for gfx950 with hipcc.
 
-Usage:  python -m paper_2412_04980_amd.build        (or build() from Python)
+Usage:  python paper_2412_04980_amd/build.py   (run by path: importing the package
+        loads the library, which may be missing or stale before a build)
 Objects go to _build/ at the repository root; the shared library is written
 next to this file so that it travels with the source tree.
 """

@@ -166,6 +166,98 @@ __global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __rest
   }
 }
 
+// Wide (5x5 / 7x7) stencil with the ghost-extended input tile staged in LDS.
+// Block = 64 x 4 threads, tile = 64 x 16 outputs; each thread produces WT_R
+// vertically adjacent outputs and keeps one stencil row in registers while it
+// is reused by the outputs that need it (fewer LDS reads per output).
+constexpr int WT_X = 64;
+constexpr int WT_R = 4;
+constexpr int WT_Y = BY * WT_R;
+
+template <typename T, int R, int MODE>
+__global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __restrict__ u,
+                                                   const T* __restrict__ k,
+                                                   const cx<T>* __restrict__ b,
+                                                   cx<T>* __restrict__ out, T omega) {
+  constexpr int W = 2 * R + 1;
+  constexpr int SX = WT_X + 2 * R;
+  constexpr int SY = WT_Y + 2 * R;
+  __shared__ cx<T> su[SY][SX];
+  __shared__ T sk[SY][SX];
+  const int x0 = blockIdx.x * WT_X, y0 = blockIdx.y * WT_Y;
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  for (int idx = tid; idx < SX * SY; idx += NT) {
+    const int r = idx / SX, c = idx - r * SX;
+    cx<T> uv;
+    T k2;
+    ext_val(d, u, k, x0 - R + c, y0 - R + r, uv, k2);
+    su[r][c] = uv;
+    sk[r][c] = k2;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x;
+  const int x = x0 + tx;
+  const int ly0 = threadIdx.y * WT_R;          // local row of this thread's first output
+  T are[WT_R], aim[WT_R];
+#pragma unroll
+  for (int o = 0; o < WT_R; ++o) { are[o] = T(0); aim[o] = T(0); }
+#pragma unroll 1
+  for (int rr = 0; rr < WT_R + 2 * R; ++rr) {
+    cx<T> uu[W];
+    T kk[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+      uu[a] = su[ly0 + rr][tx + a];
+      kk[a] = sk[ly0 + rr][tx + a];
+    }
+#pragma unroll
+    for (int o = 0; o < WT_R; ++o) {
+      const int bb = rr - o;                   // tap row (b + R)
+      if (bb >= 0 && bb < W) {
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+          const T kc = d.K[bb * W + a] * kk[a];
+          const T cre = d.L[bb * W + a] - d.sig_re * kc;
+          const T cim = -d.sig_im * kc;
+          are[o] += cre * uu[a].re - cim * uu[a].im;
+          aim[o] += cre * uu[a].im + cim * uu[a].re;
+        }
+      }
+    }
+  }
+  if (x >= d.nx) return;
+#pragma unroll
+  for (int o = 0; o < WT_R; ++o) {
+    const int y = y0 + ly0 + o;
+    if (y >= d.ny) break;
+    const size_t p = (size_t)y * d.nx + x;
+    const int cy = ly0 + o + R, cxl = tx + R;
+    const cx<T> uc = su[cy][cxl];
+    cx<T> au;
+    const bool bnd = x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1;
+    if (bnd) {
+      const T k2 = sk[cy][cxl];
+      cx<T> s = mk(T(4) * uc.re, T(4) * uc.im);
+      s = s - su[cy][cxl - 1];
+      s = s - su[cy][cxl + 1];
+      s = s - su[cy - 1][cxl];
+      s = s - su[cy + 1][cxl];
+      const cx<T> sk2 = mk(d.sig_re * k2, d.sig_im * k2) * uc;
+      au = d.scale * (d.inv_H2 * s - sk2);
+    } else {
+      au = mk(are[o], aim[o]);
+    }
+    if constexpr (MODE == ST_APPLY) {
+      out[p] = au;
+    } else if constexpr (MODE == ST_RESID) {
+      out[p] = b[p] - au;
+    } else {
+      const cx<T> dg = bnd ? five_point_diag(d, k, x, y) : wide_diag<T, R>(d, k, x, y);
+      out[p] = uc + omega * cdiv(b[p] - au, dg);
+    }
+  }
+}
+
 template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_jacobi0(OpDesc<T> d, const T* __restrict__ k,
                                                 const cx<T>* __restrict__ b, cx<T>* __restrict__ x_out,
@@ -363,6 +455,7 @@ __global__ void __launch_bounds__(NT) k_combine(const cx<T>* __restrict__ V, siz
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
   double re = 0, im = 0;
+#pragma unroll 8
   for (int j = 0; j < m; ++j) {
     const c128 c = coef[j];
     const cx<T> v = V[(size_t)j * ldv + i];
@@ -432,7 +525,7 @@ __device__ __forceinline__ c128 block_sum(double re, double im, double* sh) {
 
 inline size_t chunk_len(size_t n, int nchunks) { return (n + nchunks - 1) / nchunks; }
 
-constexpr int G = 8;   // dot products per block in the multi-dot
+constexpr int G = 16;  // dot products per block in the multi-dot
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, size_t ldv, int m,
@@ -523,6 +616,7 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
   for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
     const cx<T> w0 = w[i];
     double re = 0, im = 0;
+#pragma unroll 8
     for (int j = 0; j < m; ++j) {
       const c128 c = h[j];
       const cx<T> v = V[(size_t)j * ldv + i];
@@ -599,7 +693,10 @@ template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
                           cx<T>* out, T omega, hipStream_t s) {
   const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
-#define HM_ST(R, M) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega)
+  const dim3 gw((d.nx + WT_X - 1) / WT_X, (d.ny + WT_Y - 1) / WT_Y);
+#define HM_ST(R, M)                                                                   \
+  if constexpr (R == 1) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega);  \
+  else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega)
 #define HM_STR(R)                              \
   if (mode == ST_APPLY) HM_ST(R, ST_APPLY);    \
   else if (mode == ST_RESID) HM_ST(R, ST_RESID); \
@@ -709,7 +806,7 @@ hipError_t launch_identity(c128* out, int n, hipStream_t s) {
 }
 
 int reduction_chunks(size_t n) {
-  size_t c = (n + NT * 8 - 1) / (NT * 8);
+  size_t c = (n + NT * 2 - 1) / (NT * 2);
   if (c < 1) c = 1;
   if (c > (size_t)kMaxChunks) c = kMaxChunks;
   return (int)c;

@@ -92,7 +92,7 @@ struct RedBuf {
   c128* partials;   // >= kMaxChunks * (max dots) entries
   int nchunks;
 };
-constexpr int kMaxChunks = 512;
+constexpr int kMaxChunks = 2048;
 int reduction_chunks(size_t n);
 
 // out[i] = (V_i, w) = sum conj(V_i) w, i = 0..m-1

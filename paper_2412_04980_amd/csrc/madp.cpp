@@ -250,6 +250,14 @@ struct hm_problem {
   std::vector<int> rep[K_NKIND];
   size_t rep_pos[K_NKIND] = {0, 0, 0, 0};
   double last_estimate = 0;
+  // optional per-kernel-class timing with HIP events on the problem's stream
+  unsigned timing_mask = 0;
+  struct Pending { hipEvent_t a, b; int cls; double bytes; };
+  std::vector<Pending> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  double t_ms[HM_TK_COUNT] = {0};
+  double t_bytes[HM_TK_COUNT] = {0};
+  long t_launches[HM_TK_COUNT] = {0};
 };
 
 namespace hm {
@@ -262,6 +270,40 @@ static int forced_count(hm_problem* p, int kind) {
   return p->rep[kind][p->rep_pos[kind]++];
 }
 
+// Timed launch: brackets the launch with events when its class is enabled.
+template <typename F>
+static void timed(hm_problem* p, int cls, double bytes, F&& launch) {
+  if (!(p->timing_mask & (1u << cls))) {
+    HM_CHECK(launch());
+    return;
+  }
+  std::pair<hipEvent_t, hipEvent_t> ev;
+  if (p->pool.empty()) {
+    HM_CHECK(hipEventCreate(&ev.first));
+    HM_CHECK(hipEventCreate(&ev.second));
+  } else {
+    ev = p->pool.back();
+    p->pool.pop_back();
+  }
+  HM_CHECK(hipEventRecord(ev.first, p->s));
+  HM_CHECK(launch());
+  HM_CHECK(hipEventRecord(ev.second, p->s));
+  p->pending.push_back({ev.first, ev.second, cls, bytes});
+}
+
+// Collects finished event pairs (call after a stream synchronisation).
+static void harvest(hm_problem* p) {
+  for (auto& q : p->pending) {
+    float ms = 0;
+    HM_CHECK(hipEventElapsedTime(&ms, q.a, q.b));
+    p->t_ms[q.cls] += ms;
+    p->t_bytes[q.cls] += q.bytes;
+    p->t_launches[q.cls] += 1;
+    p->pool.push_back({q.a, q.b});
+  }
+  p->pending.clear();
+}
+
 static inline RedBuf rbuf(const hm_problem* p, size_t n) {
   return RedBuf{p->rb.partials, reduction_chunks(n)};
 }
@@ -269,6 +311,7 @@ static inline RedBuf rbuf(const hm_problem* p, size_t n) {
 static void d2h(hm_problem* p, const c128* dev, int n) {
   HM_CHECK(hipMemcpyAsync(p->host, dev, sizeof(c128) * n, hipMemcpyDeviceToHost, p->s));
   HM_CHECK(hipStreamSynchronize(p->s));
+  if (!p->pending.empty()) harvest(p);
 }
 
 static void h2d_coef(hm_problem* p, const std::vector<c128>& y) {
@@ -313,10 +356,18 @@ static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& w
   LSQ lsq;
   lsq.init(maxit, beta);
   int steps = 0;
+  const double es = (double)sizeof(cx<T>);
+  const int tk_op = op.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE;
   for (int j = 0; j < maxit; ++j) {
-    HM_CHECK(launch_stencil<T>(op, ST_APPLY, V + (size_t)j * N, k, nullptr, w, T(0), p->s));
-    HM_CHECK(launch_multidot<T>(V, N, j + 1, w, N, rbuf(p, N), ws.h, p->s));
-    HM_CHECK(launch_cgs_update_norm<T>(w, V, N, j + 1, ws.h, N, rbuf(p, N), ws.h + j + 1, p->s));
+    timed(p, tk_op, 2.5 * es * N, [&] {
+      return launch_stencil<T>(op, ST_APPLY, V + (size_t)j * N, k, nullptr, w, T(0), p->s);
+    });
+    timed(p, HM_TK_CGS_DOT, (j + 2) * es * N, [&] {
+      return launch_multidot<T>(V, N, j + 1, w, N, rbuf(p, N), ws.h, p->s);
+    });
+    timed(p, HM_TK_CGS_UPDATE, (j + 3) * es * N, [&] {
+      return launch_cgs_update_norm<T>(w, V, N, j + 1, ws.h, N, rbuf(p, N), ws.h + j + 1, p->s);
+    });
     d2h(p, ws.h, j + 2);
     const double est = lsq.add(j, p->host);
     steps = j + 1;
@@ -425,11 +476,18 @@ static int fgmres_level(hm_problem* p, int c, const cx<T>* b, cx<T>* x, double t
     } else {
       precond<T>(p, c, Vj, Xj);
     }
-    apply_level<T>(p, D, false, ST_APPLY, Xj, nullptr, w);
+    const double es = (double)sizeof(cx<T>);
+    timed(p, D.A64.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE, 2.5 * es * N, [&] {
+      return launch_stencil<T>(opsel<T>(D, false), ST_APPLY, Xj, levk<T>(D), nullptr, w, T(0), p->s);
+    });
     for (int i = 0; i <= j; ++i)
-      HM_CHECK(launch_mgs_step<T>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr, ws.h + i - 1,
-                                  V + (size_t)i * N, N, rbuf(p, N), ws.h + i, p->s));
-    HM_CHECK(launch_mgs_step<T>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s));
+      timed(p, HM_TK_MGS, (i > 0 ? 4.0 : 2.0) * es * N, [&] {
+        return launch_mgs_step<T>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr, ws.h + i - 1,
+                                  V + (size_t)i * N, N, rbuf(p, N), ws.h + i, p->s);
+      });
+    timed(p, HM_TK_MGS, 3.0 * es * N, [&] {
+      return launch_mgs_step<T>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s);
+    });
     d2h(p, ws.h, j + 2);
     const double est = lsq.add(j, p->host);
     steps = j + 1;
@@ -536,11 +594,18 @@ static hm_status outer_solve(hm_problem* p, const c128* b, c128* u, hm_solve_inf
       c128* Vj = V + (size_t)j * N;
       c128* Xj = X + (size_t)j * N;
       precond_top(p, Vj, Xj);
-      HM_CHECK(launch_stencil<double>(D.A64, ST_APPLY, Xj, D.k64, nullptr, w, 0.0, p->s));
+      timed(p, HM_TK_FIVE_POINT, 40.0 * N, [&] {
+        return launch_stencil<double>(D.A64, ST_APPLY, Xj, D.k64, nullptr, w, 0.0, p->s);
+      });
       for (int i = 0; i <= j; ++i)
-        HM_CHECK(launch_mgs_step<double>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr, ws.h + i - 1,
-                                         V + (size_t)i * N, N, rbuf(p, N), ws.h + i, p->s));
-      HM_CHECK(launch_mgs_step<double>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s));
+        timed(p, HM_TK_MGS, (i > 0 ? 64.0 : 32.0) * N, [&] {
+          return launch_mgs_step<double>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr,
+                                         ws.h + i - 1, V + (size_t)i * N, N, rbuf(p, N), ws.h + i,
+                                         p->s);
+        });
+      timed(p, HM_TK_MGS, 48.0 * N, [&] {
+        return launch_mgs_step<double>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s);
+      });
       d2h(p, ws.h, j + 2);
       const double est = lsq.add(j, p->host);
       est_rel = bnorm > 0 ? est / bnorm : 0.0;
@@ -558,6 +623,7 @@ static hm_status outer_solve(hm_problem* p, const c128* b, c128* u, hm_solve_inf
     p->rec[K_OUTER].push_back(steps);
   }
   HM_CHECK(hipStreamSynchronize(p->s));
+  if (!p->pending.empty()) harvest(p);
   p->last_estimate = est_rel;
   if (info) {
     auto sum_since = [&](int kind) {
@@ -1112,9 +1178,37 @@ hm_status hm_reset_counts(hm_problem* p) {
 
 hm_status hm_destroy_problem(hm_problem* p) {
   if (!p) return HM_ERR_ARG;
+  for (auto& q : p->pending) p->pool.push_back({q.a, q.b});
+  for (auto& e : p->pool) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (p->host) (void)hipHostFree(p->host);
   if (p->host_coef) (void)hipHostFree(p->host_coef);
   delete p;
+  return HM_OK;
+}
+
+hm_status hm_set_timing(hm_problem* p, unsigned mask) {
+  if (!p) return HM_ERR_ARG;
+  return guard([&]() -> hm_status {
+    HM_CHECK(hipStreamSynchronize(p->s));
+    harvest(p);
+    p->timing_mask = mask;
+    for (int c = 0; c < HM_TK_COUNT; ++c) {
+      p->t_ms[c] = 0;
+      p->t_bytes[c] = 0;
+      p->t_launches[c] = 0;
+    }
+    return HM_OK;
+  });
+}
+
+hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes, long* launches) {
+  if (!p || cls < 0 || cls >= HM_TK_COUNT || !ms || !bytes || !launches) return HM_ERR_ARG;
+  *ms = p->t_ms[cls];
+  *bytes = p->t_bytes[cls];
+  *launches = p->t_launches[cls];
   return HM_OK;
 }
 
