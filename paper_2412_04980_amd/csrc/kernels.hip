@@ -133,11 +133,15 @@ __device__ __forceinline__ bool is_boundary(const OpDesc<T>& d, int x, int y) {
   return x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1;
 }
 
+constexpr int ST_SCALED = 3;   // out = Op(s u), vout = s u, s = 1 / scal[0].re
+
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __restrict__ u,
                                                 const T* __restrict__ k,
                                                 const cx<T>* __restrict__ b,
-                                                cx<T>* __restrict__ out, T omega) {
+                                                cx<T>* __restrict__ out, T omega,
+                                                const c128* __restrict__ scal,
+                                                cx<T>* __restrict__ vout) {
   const int x = blockIdx.x * BX + threadIdx.x;
   const int y = blockIdx.y * BY + threadIdx.y;
   if (x >= d.nx || y >= d.ny) return;
@@ -152,6 +156,10 @@ __global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __rest
   }
   if constexpr (MODE == ST_APPLY) {
     out[p] = au;
+  } else if constexpr (MODE == ST_SCALED) {
+    const T sc = (T)(1.0 / scal[0].re);
+    out[p] = sc * au;
+    vout[p] = sc * u[p];
   } else if constexpr (MODE == ST_RESID) {
     out[p] = b[p] - au;
   } else {
@@ -178,7 +186,9 @@ template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __restrict__ u,
                                                    const T* __restrict__ k,
                                                    const cx<T>* __restrict__ b,
-                                                   cx<T>* __restrict__ out, T omega) {
+                                                   cx<T>* __restrict__ out, T omega,
+                                                   const c128* __restrict__ scal,
+                                                   cx<T>* __restrict__ vout) {
   constexpr int W = 2 * R + 1;
   constexpr int SX = WT_X + 2 * R;
   constexpr int SY = WT_Y + 2 * R;
@@ -186,11 +196,15 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
   __shared__ T sk[SY][SX];
   const int x0 = blockIdx.x * WT_X, y0 = blockIdx.y * WT_Y;
   const int tid = threadIdx.y * BX + threadIdx.x;
+  T sc = T(1);
+  if constexpr (MODE == ST_SCALED) sc = (T)(1.0 / scal[0].re);
   for (int idx = tid; idx < SX * SY; idx += NT) {
     const int r = idx / SX, c = idx - r * SX;
     cx<T> uv;
     T k2;
     ext_val(d, u, k, x0 - R + c, y0 - R + r, uv, k2);
+    // the ghost values are linear in u, so scaling the extended tile scales u
+    if constexpr (MODE == ST_SCALED) uv = sc * uv;
     su[r][c] = uv;
     sk[r][c] = k2;
   }
@@ -198,32 +212,42 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
   const int tx = threadIdx.x;
   const int x = x0 + tx;
   const int ly0 = threadIdx.y * WT_R;          // local row of this thread's first output
-  T are[WT_R], aim[WT_R];
+  // separable evaluation on the extended tile:
+  //   L u = sum_b m_b (t * u)_row + t_b (m * u)_row,  K (k^2 u) = sum_b m_b (m * k^2 u)_row
+  T lre[WT_R], lim[WT_R], kre[WT_R], kim[WT_R];
 #pragma unroll
-  for (int o = 0; o < WT_R; ++o) { are[o] = T(0); aim[o] = T(0); }
+  for (int o = 0; o < WT_R; ++o) { lre[o] = lim[o] = kre[o] = kim[o] = T(0); }
 #pragma unroll 1
   for (int rr = 0; rr < WT_R + 2 * R; ++rr) {
-    cx<T> uu[W];
-    T kk[W];
+    T tur = 0, tui = 0, mur = 0, mui = 0, mwr = 0, mwi = 0;
 #pragma unroll
     for (int a = 0; a < W; ++a) {
-      uu[a] = su[ly0 + rr][tx + a];
-      kk[a] = sk[ly0 + rr][tx + a];
+      const cx<T> uv = su[ly0 + rr][tx + a];
+      const T k2 = sk[ly0 + rr][tx + a];
+      const T ta = d.t1[a], ma = d.m1[a];
+      tur += ta * uv.re; tui += ta * uv.im;
+      mur += ma * uv.re; mui += ma * uv.im;
+      const T mk2 = ma * k2;
+      mwr += mk2 * uv.re; mwi += mk2 * uv.im;
     }
 #pragma unroll
     for (int o = 0; o < WT_R; ++o) {
       const int bb = rr - o;                   // tap row (b + R)
       if (bb >= 0 && bb < W) {
-#pragma unroll
-        for (int a = 0; a < W; ++a) {
-          const T kc = d.K[bb * W + a] * kk[a];
-          const T cre = d.L[bb * W + a] - d.sig_re * kc;
-          const T cim = -d.sig_im * kc;
-          are[o] += cre * uu[a].re - cim * uu[a].im;
-          aim[o] += cre * uu[a].im + cim * uu[a].re;
-        }
+        const T mb = d.m1[bb], tb = d.t1[bb];
+        lre[o] += mb * tur + tb * mur;
+        lim[o] += mb * tui + tb * mui;
+        kre[o] += mb * mwr;
+        kim[o] += mb * mwi;
       }
     }
+  }
+  T are[WT_R], aim[WT_R];
+#pragma unroll
+  for (int o = 0; o < WT_R; ++o) {
+    // L u - sigma K w
+    are[o] = lre[o] - (d.sig_re * kre[o] - d.sig_im * kim[o]);
+    aim[o] = lim[o] - (d.sig_re * kim[o] + d.sig_im * kre[o]);
   }
   if (x >= d.nx) return;
 #pragma unroll
@@ -249,6 +273,9 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
     }
     if constexpr (MODE == ST_APPLY) {
       out[p] = au;
+    } else if constexpr (MODE == ST_SCALED) {
+      out[p] = au;
+      vout[p] = uc;
     } else if constexpr (MODE == ST_RESID) {
       out[p] = b[p] - au;
     } else {
@@ -525,17 +552,24 @@ __device__ __forceinline__ c128 block_sum(double re, double im, double* sh) {
 
 inline size_t chunk_len(size_t n, int nchunks) { return (n + nchunks - 1) / nchunks; }
 
-constexpr int G = 16;  // dot products per block in the multi-dot
+constexpr int G = 4;   // dot products per block in the multi-dot
 
+// Partial dots of w with V_{i0}..V_{i0+G-1} over one chunk of the vector
+// (block = (chunk, group)); partials[i * nchunks + chunk].  Few accumulators
+// per thread keep occupancy high; the re-reads of w by the groups of a chunk
+// are served by the caches.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, size_t ldv, int m,
                                                  const cx<T>* __restrict__ w, size_t n, size_t clen,
-                                                 c128* __restrict__ partials, int nchunks) {
-  __shared__ double sh[2 * NT / 64];
-  const int chunk = blockIdx.x;
-  const int i0 = blockIdx.y * G;
+                                                 c128* __restrict__ partials, int nchunks,
+                                                 int reverse) {
+  __shared__ double sh[NT / 64][2 * G];
+  // chunk-major block order: consecutive blocks share a chunk of w
+  const int chunk = reverse ? nchunks - 1 - (int)blockIdx.y : (int)blockIdx.y;
+  const int i0 = blockIdx.x * G;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double re[G], im[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) { re[g] = 0; im[g] = 0; }
@@ -545,7 +579,6 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
     for (int g = 0; g < G; ++g) {
       if (i0 + g < m) {
         const cx<T> v = V[(size_t)(i0 + g) * ldv + i];
-        // conj(v) * w
         re[g] += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
         im[g] += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
       }
@@ -553,10 +586,25 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
   }
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    if (i0 + g < m) {
-      const c128 s = block_sum(re[g], im[g], sh);
-      if (threadIdx.x == 0) partials[(size_t)(i0 + g) * nchunks + chunk] = s;
+    re[g] = wave_sum(re[g]);
+    im[g] = wave_sum(im[g]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      sh[wid][2 * g] = re[g];
+      sh[wid][2 * g + 1] = im[g];
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < G && i0 + (int)threadIdx.x < m) {
+    const int g = threadIdx.x;
+    double sr = 0, si = 0;
+    for (int w2 = 0; w2 < NT / 64; ++w2) {
+      sr += sh[w2][2 * g];
+      si += sh[w2][2 * g + 1];
+    }
+    partials[(size_t)(i0 + g) * nchunks + chunk] = mk(sr, si);
   }
 }
 
@@ -608,9 +656,10 @@ template <typename T>
 __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, const cx<T>* __restrict__ V,
                                                         size_t ldv, int m, const c128* __restrict__ h,
                                                         size_t n, size_t clen,
-                                                        c128* __restrict__ partials) {
+                                                        c128* __restrict__ partials, int reverse) {
   __shared__ double sh[2 * NT / 64];
-  const size_t lo = (size_t)blockIdx.x * clen;
+  const int chunk = reverse ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   double acc = 0;
   for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
@@ -628,7 +677,7 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
     acc += (double)wn.re * (double)wn.re + (double)wn.im * (double)wn.im;
   }
   const c128 s = block_sum(acc, 0.0, sh);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (threadIdx.x == 0) partials[chunk] = s;
 }
 
 template <typename T>
@@ -694,9 +743,10 @@ hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T*
                           cx<T>* out, T omega, hipStream_t s) {
   const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
   const dim3 gw((d.nx + WT_X - 1) / WT_X, (d.ny + WT_Y - 1) / WT_Y);
-#define HM_ST(R, M)                                                                   \
-  if constexpr (R == 1) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega);  \
-  else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega)
+#define HM_ST(R, M)                                                                           \
+  if constexpr (R == 1) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega, nullptr,    \
+                                                            nullptr);                          \
+  else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega, nullptr, nullptr)
 #define HM_STR(R)                              \
   if (mode == ST_APPLY) HM_ST(R, ST_APPLY);    \
   else if (mode == ST_RESID) HM_ST(R, ST_RESID); \
@@ -707,6 +757,22 @@ hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T*
   else return hipErrorInvalidValue;
 #undef HM_STR
 #undef HM_ST
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k, const c128* scal,
+                                 cx<T>* vout, cx<T>* out, hipStream_t s) {
+  const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
+  const dim3 gw((d.nx + WT_X - 1) / WT_X, (d.ny + WT_Y - 1) / WT_Y);
+  if (d.R == 1)
+    k_stencil<T, 1, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
+  else if (d.R == 2)
+    k_wide_tiled<T, 2, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
+  else if (d.R == 3)
+    k_wide_tiled<T, 3, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -812,15 +878,36 @@ int reduction_chunks(size_t n) {
   return (int)c;
 }
 
+// longer chunks than the single-vector reductions: (m / G) groups per chunk
+static int multidot_chunks(size_t n, const RedBuf& rb) {
+  int nch = (int)((n + NT * 16 - 1) / (NT * 16));
+  return nch < 1 ? 1 : (nch > rb.nchunks ? rb.nchunks : nch);
+}
+
+template <typename T>
+hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
+                                   RedBuf rb, int reverse, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int nch = multidot_chunks(n, rb);
+  const size_t clen = chunk_len(n, nch);
+  k_multidot<T><<<dim3((m + G - 1) / G, nch), NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch,
+                                                          reverse);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  k_final<<<m, NT, 0, s>>>(rb.partials, multidot_chunks(n, rb), out, 0);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n, RedBuf rb,
                            c128* out, hipStream_t s) {
-  if (m <= 0) return hipSuccess;
-  const size_t clen = chunk_len(n, rb.nchunks);
-  k_multidot<T><<<dim3(rb.nchunks, (m + G - 1) / G), NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials,
-                                                                   rb.nchunks);
-  k_final<<<m, NT, 0, s>>>(rb.partials, rb.nchunks, out, 0);
-  return hipGetLastError();
+  const hipError_t e = launch_multidot_partial<T>(V, ldv, m, w, n, rb, 0, s);
+  if (e != hipSuccess) return e;
+  return launch_multidot_final<T>(m, n, rb, out, s);
 }
 
 template <typename T>
@@ -833,12 +920,24 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
 }
 
 template <typename T>
-hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
-                                  size_t n, RedBuf rb, c128* out, hipStream_t s) {
+hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
+                                     size_t n, RedBuf rb, int reverse, hipStream_t s) {
   const size_t clen = chunk_len(n, rb.nchunks);
-  k_cgs_update_norm<T><<<rb.nchunks, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials);
+  k_cgs_update_norm<T><<<rb.nchunks, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, reverse);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_final(RedBuf rb, c128* out, hipStream_t s) {
   k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 1);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
+                                  size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  const hipError_t e = launch_cgs_update_partial<T>(w, V, ldv, m, h, n, rb, 0, s);
+  if (e != hipSuccess) return e;
+  return launch_norm_final(rb, out, s);
 }
 
 template <typename T>
@@ -880,6 +979,13 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
                                         int, size_t, hipStream_t);                                  \
   template hipError_t launch_multidot<T>(const cx<T>*, size_t, int, const cx<T>*, size_t, RedBuf,  \
                                          c128*, hipStream_t);                                       \
+  template hipError_t launch_multidot_partial<T>(const cx<T>*, size_t, int, const cx<T>*, size_t,  \
+                                                 RedBuf, int, hipStream_t);                         \
+  template hipError_t launch_multidot_final<T>(int, size_t, RedBuf, c128*, hipStream_t);           \
+  template hipError_t launch_cgs_update_partial<T>(cx<T>*, const cx<T>*, size_t, int, const c128*, \
+                                                   size_t, RedBuf, int, hipStream_t);               \
+  template hipError_t launch_stencil_scaled<T>(const OpDesc<T>&, const cx<T>*, const T*,            \
+                                               const c128*, cx<T>*, cx<T>*, hipStream_t);           \
   template hipError_t launch_mgs_step<T>(cx<T>*, const cx<T>*, const c128*, const cx<T>*, size_t,  \
                                          RedBuf, c128*, hipStream_t);                               \
   template hipError_t launch_cgs_update_norm<T>(cx<T>*, const cx<T>*, size_t, int, const c128*,    \

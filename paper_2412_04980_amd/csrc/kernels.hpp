@@ -28,6 +28,10 @@ struct OpDesc {
   T sig_re, sig_im;
   T L[49];    // (2R+1)^2 Laplace coefficients, already divided by h^2 (finest h)
   T K[49];    // (2R+1)^2 wavenumber coefficients
+  // 1-D factors: L[b][a] = t[a] m[b] + m[a] t[b] (t already divided by h^2),
+  // K[b][a] = m[a] m[b]
+  T t1[7];
+  T m1[7];
 };
 
 enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_JACOBI = 2 };
@@ -38,6 +42,13 @@ enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_JACOBI = 2 };
 template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
                           cx<T>* out, T omega, hipStream_t s);
+
+// Scaled apply for Krylov steps: with s = 1 / scal[0].re,
+//   vout = s u   and   out = Op(s u)
+// (normalises the new basis vector and applies the operator in one pass).
+template <typename T>
+hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k, const c128* scal,
+                                 cx<T>* vout, cx<T>* out, hipStream_t s);
 
 // x = omega D^-1 b  (first damped-Jacobi sweep from x = 0)
 template <typename T>
@@ -95,7 +106,15 @@ struct RedBuf {
 constexpr int kMaxChunks = 2048;
 int reduction_chunks(size_t n);
 
-// out[i] = (V_i, w) = sum conj(V_i) w, i = 0..m-1
+// out[i] = (V_i, w) = sum conj(V_i) w, i = 0..m-1.  Split in two launches
+// (partial sums over chunks of the vector, then the sums of the partials) so
+// that the streaming kernel can be timed on its own.  `reverse` sweeps the
+// chunks from the end of the vectors (cache reuse between successive passes).
+template <typename T>
+hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
+                                   RedBuf rb, int reverse, hipStream_t s);
+template <typename T>
+hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s);
 template <typename T>
 hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n, RedBuf rb,
                            c128* out, hipStream_t s);
@@ -105,6 +124,10 @@ template <typename T>
 hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const cx<T>* next,
                            size_t n, RedBuf rb, c128* out, hipStream_t s);
 // Classical Gram-Schmidt update fused with the norm: w -= sum_{i<m} h[i] V_i ; out[0] = ||w||
+template <typename T>
+hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
+                                     size_t n, RedBuf rb, int reverse, hipStream_t s);
+hipError_t launch_norm_final(RedBuf rb, c128* out, hipStream_t s);
 template <typename T>
 hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                   size_t n, RedBuf rb, c128* out, hipStream_t s);

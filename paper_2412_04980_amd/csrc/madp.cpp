@@ -122,7 +122,9 @@ struct KrylovWS {
   void* V = nullptr;   // (cap+1) x N
   void* X = nullptr;   // cap x N  (flexible basis; unused by plain GMRES)
   void* w = nullptr;   // N
+  void* w2 = nullptr;  // GMRES: second work vector (ping-pong with w)
   c128* h = nullptr;   // device column / scalars, cap + 2
+  c128* H = nullptr;   // GMRES: device Hessenberg, cap columns of stride cap + 2
 };
 
 struct MGLevel {
@@ -207,6 +209,13 @@ static void set_wide(OpDesc<T>& d, int nx, int ny, double h, int level, cd sigma
     d.L[i] = (T)(lap[i] / h2);
     d.K[i] = (T)wav[i];
   }
+  int R1 = 0;
+  std::vector<double> t1, m1;
+  coarse_tables_1d(level, &R1, t1, m1);
+  for (size_t i = 0; i < t1.size(); ++i) {
+    d.t1[i] = (T)(t1[i] / h2);
+    d.m1[i] = (T)m1[i];
+  }
 }
 
 template <typename T> static inline const OpDesc<T>& opsel(const DefLevel& L, bool cslp);
@@ -245,6 +254,9 @@ struct hm_problem {
   c128* host = nullptr;        // pinned host staging for device results
   c128* host_coef = nullptr;   // pinned host staging for coefficient uploads
   int host_cap = 0;
+  c128* host_H = nullptr;      // pinned mirror of a GMRES Hessenberg (lookahead loop)
+  size_t host_H_cap = 0;
+  hipEvent_t col_ev[2] = {nullptr, nullptr};
   // counts
   std::vector<int> rec[K_NKIND];
   std::vector<int> rep[K_NKIND];
@@ -332,6 +344,11 @@ static void apply_level(hm_problem* p, const DefLevel& L, bool cslp, int mode, c
 
 // ---- GMRES with classical Gram-Schmidt (Krylov CSLP) ----------------------------
 // Unpreconditioned GMRES from x = 0 on the operator `op` with wavenumber `k`.
+// The device never waits for the host: step j+1 is enqueued before the host
+// reads the Hessenberg column of step j (copied to pinned memory, waited on
+// with an event), so the host's stopping test overlaps the next step.  When
+// step j meets the tolerance, the speculative step j+1 has only written w,
+// column j+1 and V_{j+2}, none of which the solution uses.
 template <typename T>
 static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& ws, int maxit,
                      double tol, int kind, const cx<T>* b, cx<T>* x) {
@@ -352,27 +369,46 @@ static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& w
     tol = -1;
   }
   if (maxit > ws.cap) throw ArgError("GMRES step count exceeds the workspace");
-  HM_CHECK(launch_scale_dev<T>(b, V, ws.h, 1, N, p->s));
+  const size_t ld = (size_t)ws.cap + 2;
+  if ((size_t)maxit * ld > p->host_H_cap) throw ArgError("Hessenberg mirror too small");
+  const double es = (double)sizeof(cx<T>);
+  const int tk_op = op.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE;
+  cx<T>* wb[2] = {w, (cx<T>*)ws.w2};
+  // step j: v_j = src / s_j (s_0 = ||b||, s_j = h_{j,j-1}) written to the basis
+  // in the same pass as w = M v_j; classical Gram-Schmidt with the two sweeps
+  // over the basis in opposite directions (the second starts on the chunks the
+  // first read last, which the caches still hold)
+  auto enqueue_step = [&](int j) {
+    c128* col = ws.H + (size_t)j * ld;
+    const cx<T>* src = j == 0 ? b : wb[(j - 1) & 1];
+    const c128* sc = j == 0 ? ws.h : ws.H + (size_t)(j - 1) * ld + j;
+    cx<T>* wj = wb[j & 1];
+    timed(p, tk_op, 3.5 * es * N, [&] {
+      return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, wj, p->s);
+    });
+    timed(p, HM_TK_CGS_DOT, (j + 2) * es * N, [&] {
+      return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), 0, p->s);
+    });
+    HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s));
+    timed(p, HM_TK_CGS_UPDATE, (j + 3) * es * N, [&] {
+      return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), 1, p->s);
+    });
+    HM_CHECK(launch_norm_final(rbuf(p, N), col + j + 1, p->s));
+    HM_CHECK(hipMemcpyAsync(p->host_H + (size_t)j * ld, col, sizeof(c128) * (j + 2),
+                            hipMemcpyDeviceToHost, p->s));
+    HM_CHECK(hipEventRecord(p->col_ev[j & 1], p->s));
+  };
   LSQ lsq;
   lsq.init(maxit, beta);
   int steps = 0;
-  const double es = (double)sizeof(cx<T>);
-  const int tk_op = op.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE;
+  if (maxit > 0) enqueue_step(0);
   for (int j = 0; j < maxit; ++j) {
-    timed(p, tk_op, 2.5 * es * N, [&] {
-      return launch_stencil<T>(op, ST_APPLY, V + (size_t)j * N, k, nullptr, w, T(0), p->s);
-    });
-    timed(p, HM_TK_CGS_DOT, (j + 2) * es * N, [&] {
-      return launch_multidot<T>(V, N, j + 1, w, N, rbuf(p, N), ws.h, p->s);
-    });
-    timed(p, HM_TK_CGS_UPDATE, (j + 3) * es * N, [&] {
-      return launch_cgs_update_norm<T>(w, V, N, j + 1, ws.h, N, rbuf(p, N), ws.h + j + 1, p->s);
-    });
-    d2h(p, ws.h, j + 2);
-    const double est = lsq.add(j, p->host);
+    if (j + 1 < maxit) enqueue_step(j + 1);
+    HM_CHECK(hipEventSynchronize(p->col_ev[j & 1]));
+    const c128* hc = p->host_H + (size_t)j * ld;
+    const double est = lsq.add(j, hc);
     steps = j + 1;
-    const bool broke = p->host[j + 1].re <= 1e-14 * beta;
-    if (!broke) HM_CHECK(launch_scale_dev<T>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s));
+    const bool broke = hc[j + 1].re <= 1e-14 * beta;
     if (broke) break;
     if (tol >= 0 && est <= tol * beta) break;
   }
@@ -755,8 +791,11 @@ static void plan(hm_problem* p, Carver& cv) {
         H.gm.N = last.N;
         H.gm.V = cv.take<char>((size_t)(H.maxit + 1) * last.N * es);
         H.gm.w = cv.take<char>(last.N * es);
+        H.gm.w2 = cv.take<char>(last.N * es);
         H.gm.h = cv.take<c128>(H.maxit + 2);
+        H.gm.H = cv.take<c128>((size_t)(H.maxit + 2) * H.maxit);
         mmax = std::max(mmax, H.maxit + 2);
+        p->host_H_cap = std::max(p->host_H_cap, (size_t)(H.maxit + 2) * H.maxit);
       }
     } else {
       D.cslp_maxit = krylov_maxit(D.N, c.maxit_coef);
@@ -764,8 +803,11 @@ static void plan(hm_problem* p, Carver& cv) {
       D.cslp.N = D.N;
       D.cslp.V = cv.take<char>((size_t)(D.cslp_maxit + 1) * D.N * es);
       D.cslp.w = cv.take<char>(D.N * es);
+      D.cslp.w2 = cv.take<char>(D.N * es);
       D.cslp.h = cv.take<c128>(D.cslp_maxit + 2);
+      D.cslp.H = cv.take<c128>((size_t)(D.cslp_maxit + 2) * D.cslp_maxit);
       mmax = std::max(mmax, D.cslp_maxit + 2);
+      p->host_H_cap = std::max(p->host_H_cap, (size_t)(D.cslp_maxit + 2) * D.cslp_maxit);
     }
     if (l < p->L) {
       nx = (nx - 1) / 2 + 1;
@@ -1083,6 +1125,10 @@ hm_status hm_create_problem(const hm_config* cfg, const double* k_dev, void* wor
       p->host_cap = std::max(p->coef_cap, 16);
       HM_CHECK(hipHostMalloc((void**)&p->host, sizeof(c128) * p->host_cap, hipHostMallocDefault));
       HM_CHECK(hipHostMalloc((void**)&p->host_coef, sizeof(c128) * p->host_cap, hipHostMallocDefault));
+      HM_CHECK(hipHostMalloc((void**)&p->host_H, sizeof(c128) * std::max<size_t>(p->host_H_cap, 1),
+                             hipHostMallocDefault));
+      HM_CHECK(hipEventCreateWithFlags(&p->col_ev[0], hipEventDisableTiming));
+      HM_CHECK(hipEventCreateWithFlags(&p->col_ev[1], hipEventDisableTiming));
       initialize(p, k_dev);
     } catch (...) {
       hm_destroy_problem(p);
@@ -1183,6 +1229,9 @@ hm_status hm_destroy_problem(hm_problem* p) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  for (auto& e : p->col_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (p->host_H) (void)hipHostFree(p->host_H);
   if (p->host) (void)hipHostFree(p->host);
   if (p->host_coef) (void)hipHostFree(p->host_coef);
   delete p;

@@ -76,4 +76,22 @@ inline void coarse_tables(int level, int* R, std::vector<double>& lap, std::vect
     }
 }
 
+// 1-D factors t_l, m_l of deflation level `level` (centred, length 2R+1).
+inline void coarse_tables_1d(int level, int* R, std::vector<double>& t1, std::vector<double>& m1) {
+  Table1D t, m;
+  t.num = {-1, 2, -1};
+  m.num = {1};
+  for (int l = 1; l < level; ++l) {
+    t = galerkin_step(t);
+    m = galerkin_step(m);
+  }
+  const int n = (int)(t.num.size() > m.num.size() ? t.num.size() : m.num.size());
+  *R = n / 2;
+  t1.assign(n, 0.0);
+  m1.assign(n, 0.0);
+  const int ot = (n - (int)t.num.size()) / 2, om = (n - (int)m.num.size()) / 2;
+  for (size_t i = 0; i < t.num.size(); ++i) t1[ot + i] = (double)t.num[i] / __builtin_ldexp(1.0, t.shift);
+  for (size_t i = 0; i < m.num.size(); ++i) m1[om + i] = (double)m.num[i] / __builtin_ldexp(1.0, m.shift);
+}
+
 }  // namespace hm
