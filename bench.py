@@ -24,6 +24,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+# calibrated hardware byte counts of the dominant kernel (two rocprofv3 --pmc
+# passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size);
+# valid only while the kernel source is unchanged
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_k_multidot.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_04980_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(kernel_class):
+    import hashlib
+    if kernel_class != "cgs_dot" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = json.load(open(TRAFFIC_RECORD))
+    digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if rec.get("kernels_hip_sha256") != digest:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def parse():
@@ -35,6 +51,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (a plain copy "
+                         "kernel of known size, to calibrate hardware byte counters)")
     return ap.parse_args()
 
 
@@ -119,7 +138,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (independent "
-              "solves shard across GPUs with no exchange; see the design notes)",
+              "solves shard across GPUs with no exchange)",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
@@ -129,6 +148,15 @@ def main():
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 16
+        src = torch.ones(n, dtype=torch.complex128, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x %d MiB device-to-device" % args.copy_calibration)
+        del src, dst
     problem = workloads.config(args.config)
     k = torch.from_numpy(problem.k).to(dev)
     b = torch.from_numpy(problem.rhs(0)).to(dev)
@@ -178,7 +206,7 @@ def main():
         d = classes[dom]
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                           "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                            "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1),
                            "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1)}
         res["kernel_classes"] = {c: {"ms_per_solve": v["ms"] / args.steps, "GBps": v["GBps"],

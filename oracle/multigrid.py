@@ -4,7 +4,7 @@ Sec. 3.2 and Sec. 4.3 of the paper replace the Krylov approximation of the CSLP
 inverse on the first and second levels by one multigrid V-cycle with complex
 shift beta2 = 0.5 and defer the settings to the authors' earlier matrix-free
 multigrid.  Those settings are not printed, so this module fixes a reading
-(R10, with the reasons in the design notes):
+(reading R10):
 
   * V(1,1) cycle, damped Jacobi x <- x + omega D^-1 (b - M x), first sweep from
     x = 0; omega_q = 0.8 where k_max^2 H_q^2 <= 1 and 0.5 otherwise (H_q the

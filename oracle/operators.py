@@ -4,7 +4,7 @@ Grid convention: a level holds nx*ny vertex-centred nodes including the
 boundary nodes (Sec. 2.1); node (i, j) has index j*nx + i (x fastest).
 All matrices are scipy.sparse CSR in complex128.
 
-Readings of the paper this module fixes (listed with reasons in the design notes):
+Readings of the paper this module fixes:
   * Sommerfeld ghost point (Sec. 2.1, eq. ghost_sommerfeld): the ghost behind a
     boundary node b, mirrored from the interior neighbour m, is
     u_ghost = u_m + 2 i H k_b u_b, with H the spacing of the grid concerned.
