@@ -1,0 +1,84 @@
+"""CPU tests of the serving scheduler with a simulated executor: FIFO admission,
+the slot limit, the memory budget, continuous (non-batch) admission and error
+propagation."""
+import threading
+import time
+
+import pytest
+
+from paper_2412_04980_amd.serving import Job, Scheduler, summarize
+
+
+def job(rid, arrival, size, work=0.02):
+    return Job(rid, arrival, 3, 3, 1.0, None, [None], {"size": size, "work": work})
+
+
+class FakeExecutor:
+    def __init__(self):
+        self.lock = threading.Lock()
+        self.active = 0
+        self.max_seen = 0
+        self.order = []
+
+    def __call__(self, j):
+        with self.lock:
+            self.active += 1
+            self.max_seen = max(self.max_seen, self.active)
+            self.order.append(j.rid)
+        time.sleep(j.meta["work"])
+        with self.lock:
+            self.active -= 1
+        return [{"rel_res_true": 1e-7, "rid": j.rid}], None
+
+
+def test_fifo_and_slot_limit():
+    ex = FakeExecutor()
+    s = Scheduler(ex, lambda j: j.meta["size"], budget_bytes=100, max_active=2, realtime=False)
+    res = s.run([job(i, 0.0, 10) for i in range(6)])
+    assert [r.rid for r in res] == list(range(6))
+    assert ex.order == list(range(6))
+    assert ex.max_seen == 2
+
+
+def test_memory_budget_limits_concurrency():
+    ex = FakeExecutor()
+    s = Scheduler(ex, lambda j: j.meta["size"], budget_bytes=100, max_active=8, realtime=False)
+    s.run([job(i, 0.0, 60) for i in range(4)])
+    assert ex.max_seen == 1                      # 60 + 60 > 100
+    assert all(e[3] <= 100 for e in s.events)
+
+
+def test_continuous_admission_no_batch_barrier():
+    # a long job must not hold back short ones behind it once slots free up
+    ex = FakeExecutor()
+    s = Scheduler(ex, lambda j: j.meta["size"], budget_bytes=100, max_active=2, realtime=False)
+    jobs = [job(0, 0.0, 10, work=0.3)] + [job(i, 0.0, 10, work=0.01) for i in range(1, 6)]
+    t0 = time.perf_counter()
+    res = s.run(jobs)
+    assert time.perf_counter() - t0 < 0.6
+    finish = {r.rid: r.finished for r in res}
+    assert all(finish[i] < finish[0] for i in range(1, 6))
+
+
+def test_realtime_arrivals_respected():
+    ex = FakeExecutor()
+    s = Scheduler(ex, lambda j: j.meta["size"], budget_bytes=100, max_active=4, realtime=True)
+    res = s.run([job(0, 0.0, 10, 0.01), job(1, 0.15, 10, 0.01)])
+    assert res[1].admitted >= 0.15
+    assert res[1].latency < 0.15
+    summ = summarize(res, 0.2)
+    assert summ["requests"] == 2 and summ["solves"] == 2
+
+
+def test_oversized_request_rejected():
+    s = Scheduler(FakeExecutor(), lambda j: j.meta["size"], budget_bytes=50, max_active=2)
+    with pytest.raises(ValueError):
+        s.run([job(0, 0.0, 60)])
+
+
+def test_executor_error_propagates():
+    def bad(j):
+        raise RuntimeError("boom")
+    s = Scheduler(bad, lambda j: 1, budget_bytes=10, max_active=2, realtime=False)
+    with pytest.raises(RuntimeError):
+        s.run([job(0, 0.0, 1), job(1, 0.0, 1)])
