@@ -554,6 +554,15 @@ inline size_t chunk_len(size_t n, int nchunks) { return (n + nchunks - 1) / nchu
 
 constexpr int G = 4;   // dot products per block in the multi-dot
 
+// Streaming load of a basis element that is not re-read within the same pass
+// (non-temporal hint).
+template <typename T>
+__device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return mk(t.x, t.y);
+}
+
 // Partial dots of w with V_{i0}..V_{i0+G-1} over one chunk of the vector
 // (block = (chunk, group)); partials[i * nchunks + chunk].  Few accumulators
 // per thread keep occupancy high; the re-reads of w by the groups of a chunk
@@ -578,7 +587,7 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (i0 + g < m) {
-        const cx<T> v = V[(size_t)(i0 + g) * ldv + i];
+        const cx<T> v = load_stream(V + (size_t)(i0 + g) * ldv + i);
         re[g] += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
         im[g] += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
       }
@@ -652,6 +661,8 @@ __global__ void __launch_bounds__(NT) k_mgs_step(cx<T>* __restrict__ w, const cx
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// w -= sum_j h_j V_j with the partial ||w||^2 of one chunk; every thread
+// updates two elements (i, i + NT) per pass for more loads in flight.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, const cx<T>* __restrict__ V,
                                                         size_t ldv, int m, const c128* __restrict__ h,
@@ -662,19 +673,32 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   double acc = 0;
-  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
+  for (size_t i = lo + threadIdx.x; i < hi; i += 2 * NT) {
+    const size_t i2 = i + NT;
+    const bool two = i2 < hi;
     const cx<T> w0 = w[i];
-    double re = 0, im = 0;
+    const cx<T> w1 = two ? w[i2] : mk(T(0), T(0));
+    double re0 = 0, im0 = 0, re1 = 0, im1 = 0;
 #pragma unroll 8
     for (int j = 0; j < m; ++j) {
       const c128 c = h[j];
-      const cx<T> v = V[(size_t)j * ldv + i];
-      re += c.re * (double)v.re - c.im * (double)v.im;
-      im += c.re * (double)v.im + c.im * (double)v.re;
+      const cx<T> v0 = V[(size_t)j * ldv + i];
+      re0 += c.re * (double)v0.re - c.im * (double)v0.im;
+      im0 += c.re * (double)v0.im + c.im * (double)v0.re;
+      if (two) {
+        const cx<T> v1 = V[(size_t)j * ldv + i2];
+        re1 += c.re * (double)v1.re - c.im * (double)v1.im;
+        im1 += c.re * (double)v1.im + c.im * (double)v1.re;
+      }
     }
-    const cx<T> wn = mk((T)((double)w0.re - re), (T)((double)w0.im - im));
-    w[i] = wn;
-    acc += (double)wn.re * (double)wn.re + (double)wn.im * (double)wn.im;
+    const cx<T> n0 = mk((T)((double)w0.re - re0), (T)((double)w0.im - im0));
+    w[i] = n0;
+    acc += (double)n0.re * (double)n0.re + (double)n0.im * (double)n0.im;
+    if (two) {
+      const cx<T> n1 = mk((T)((double)w1.re - re1), (T)((double)w1.im - im1));
+      w[i2] = n1;
+      acc += (double)n1.re * (double)n1.re + (double)n1.im * (double)n1.im;
+    }
   }
   const c128 s = block_sum(acc, 0.0, sh);
   if (threadIdx.x == 0) partials[chunk] = s;
@@ -878,9 +902,11 @@ int reduction_chunks(size_t n) {
   return (int)c;
 }
 
-// longer chunks than the single-vector reductions: (m / G) groups per chunk
-static int multidot_chunks(size_t n, const RedBuf& rb) {
-  int nch = (int)((n + NT * 16 - 1) / (NT * 16));
+// chunks of the multi-dot: long chunks (fewer partials per dot) for short
+// bases, shorter ones once the (m / G) groups already give enough blocks
+static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
+  const size_t per = m >= 40 ? NT * 4 : NT * 16;
+  int nch = (int)((n + per - 1) / per);
   return nch < 1 ? 1 : (nch > rb.nchunks ? rb.nchunks : nch);
 }
 
@@ -888,7 +914,7 @@ template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
                                    RedBuf rb, int reverse, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  const int nch = multidot_chunks(n, rb);
+  const int nch = multidot_chunks(n, m, rb);
   const size_t clen = chunk_len(n, nch);
   k_multidot<T><<<dim3((m + G - 1) / G, nch), NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch,
                                                           reverse);
@@ -898,7 +924,7 @@ hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T
 template <typename T>
 hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  k_final<<<m, NT, 0, s>>>(rb.partials, multidot_chunks(n, rb), out, 0);
+  k_final<<<m, NT, 0, s>>>(rb.partials, multidot_chunks(n, m, rb), out, 0);
   return hipGetLastError();
 }
 
@@ -919,16 +945,23 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
   return hipGetLastError();
 }
 
+// chunks of the update: four elements per thread (two per pass)
+static int update_chunks(size_t n, const RedBuf& rb) {
+  int nch = (int)((n + NT * 4 - 1) / (NT * 4));
+  return nch < 1 ? 1 : (nch > rb.nchunks ? rb.nchunks : nch);
+}
+
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                      size_t n, RedBuf rb, int reverse, hipStream_t s) {
-  const size_t clen = chunk_len(n, rb.nchunks);
-  k_cgs_update_norm<T><<<rb.nchunks, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, reverse);
+  const int nch = update_chunks(n, rb);
+  const size_t clen = chunk_len(n, nch);
+  k_cgs_update_norm<T><<<nch, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, reverse);
   return hipGetLastError();
 }
 
-hipError_t launch_norm_final(RedBuf rb, c128* out, hipStream_t s) {
-  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 1);
+hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s) {
+  k_final<<<1, NT, 0, s>>>(rb.partials, update_chunks(n, rb), out, 1);
   return hipGetLastError();
 }
 
@@ -937,7 +970,7 @@ hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, c
                                   size_t n, RedBuf rb, c128* out, hipStream_t s) {
   const hipError_t e = launch_cgs_update_partial<T>(w, V, ldv, m, h, n, rb, 0, s);
   if (e != hipSuccess) return e;
-  return launch_norm_final(rb, out, s);
+  return launch_update_norm_final(n, rb, out, s);
 }
 
 template <typename T>

@@ -127,7 +127,8 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                      size_t n, RedBuf rb, int reverse, hipStream_t s);
-hipError_t launch_norm_final(RedBuf rb, c128* out, hipStream_t s);
+// sum of the partials written by launch_cgs_update_partial over a vector of length n
+hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s);
 template <typename T>
 hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                   size_t n, RedBuf rb, c128* out, hipStream_t s);

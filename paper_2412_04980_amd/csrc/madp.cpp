@@ -393,7 +393,7 @@ static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& w
     timed(p, HM_TK_CGS_UPDATE, (j + 3) * es * N, [&] {
       return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), 1, p->s);
     });
-    HM_CHECK(launch_norm_final(rbuf(p, N), col + j + 1, p->s));
+    HM_CHECK(launch_update_norm_final(N, rbuf(p, N), col + j + 1, p->s));
     HM_CHECK(hipMemcpyAsync(p->host_H + (size_t)j * ld, col, sizeof(c128) * (j + 2),
                             hipMemcpyDeviceToHost, p->s));
     HM_CHECK(hipEventRecord(p->col_ev[j & 1], p->s));
