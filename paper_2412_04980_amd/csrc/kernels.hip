@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __rest
 // vertically adjacent outputs and keeps one stencil row in registers while it
 // is reused by the outputs that need it (fewer LDS reads per output).
 constexpr int WT_X = 64;
-constexpr int WT_R = 4;
+constexpr int WT_R = 2;
 constexpr int WT_Y = BY * WT_R;
 
 template <typename T, int R, int MODE>
@@ -194,7 +194,14 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
   constexpr int SY = WT_Y + 2 * R;
   __shared__ cx<T> su[SY][SX];
   __shared__ T sk[SY][SX];
-  const int x0 = blockIdx.x * WT_X, y0 = blockIdx.y * WT_Y;
+  // XCD-aware tile order: the 8 XCDs (round-robin dispatch) each take one
+  // contiguous range of tiles in row-major order, so the tile above a tile ran
+  // shortly before on the same XCD and its halo rows are still in that L2
+  const int ntx = (d.nx + WT_X - 1) / WT_X, nty = (d.ny + WT_Y - 1) / WT_Y;
+  const int per = (ntx * nty + 7) / 8;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntx * nty) return;
+  const int x0 = (tile % ntx) * WT_X, y0 = (tile / ntx) * WT_Y;
   const int tid = threadIdx.y * BX + threadIdx.x;
   T sc = T(1);
   if constexpr (MODE == ST_SCALED) sc = (T)(1.0 / scal[0].re);
@@ -573,9 +580,15 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
                                                  c128* __restrict__ partials, int nchunks,
                                                  int reverse) {
   __shared__ double sh[NT / 64][2 * G];
-  // chunk-major block order: consecutive blocks share a chunk of w
-  const int chunk = reverse ? nchunks - 1 - (int)blockIdx.y : (int)blockIdx.y;
-  const int i0 = blockIdx.x * G;
+  // XCD-aware block order: workgroups are dispatched round-robin over the 8
+  // XCDs, so blocks b, b + 8, b + 16, ... share an L2.  All groups of one chunk
+  // go to the same XCD in consecutive order: the chunk of w comes from HBM once
+  // and from that L2 for the other groups.  nchunks is a multiple of 8.
+  const int ngroups = (m + G - 1) / G;
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+  const int c = (local / ngroups) * 8 + xcd;
+  const int chunk = reverse ? nchunks - 1 - c : c;
+  const int i0 = (local % ngroups) * G;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -762,11 +775,17 @@ __global__ void __launch_bounds__(NT) k_max_final(const c128* __restrict__ parti
 
 // ============================ launchers ======================================
 
+// blocks of the tiled wide stencil: 8 equal ranges of tiles (one per XCD)
+static unsigned wide_blocks(int nx, int ny) {
+  const int nt = ((nx + WT_X - 1) / WT_X) * ((ny + WT_Y - 1) / WT_Y);
+  return (unsigned)(8 * ((nt + 7) / 8));
+}
+
 template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
                           cx<T>* out, T omega, hipStream_t s) {
   const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
-  const dim3 gw((d.nx + WT_X - 1) / WT_X, (d.ny + WT_Y - 1) / WT_Y);
+  const dim3 gw(wide_blocks(d.nx, d.ny));
 #define HM_ST(R, M)                                                                           \
   if constexpr (R == 1) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega, nullptr,    \
                                                             nullptr);                          \
@@ -788,7 +807,7 @@ template <typename T>
 hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k, const c128* scal,
                                  cx<T>* vout, cx<T>* out, hipStream_t s) {
   const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
-  const dim3 gw((d.nx + WT_X - 1) / WT_X, (d.ny + WT_Y - 1) / WT_Y);
+  const dim3 gw(wide_blocks(d.nx, d.ny));
   if (d.R == 1)
     k_stencil<T, 1, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
   else if (d.R == 2)
@@ -907,7 +926,9 @@ int reduction_chunks(size_t n) {
 static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
   const size_t per = m >= 40 ? NT * 4 : NT * 16;
   int nch = (int)((n + per - 1) / per);
-  return nch < 1 ? 1 : (nch > rb.nchunks ? rb.nchunks : nch);
+  nch = nch < 1 ? 1 : (nch > kMaxChunks ? kMaxChunks : nch);
+  (void)rb;
+  return (nch + 7) & ~7;             // a multiple of 8 (one slot per XCD)
 }
 
 template <typename T>
@@ -916,8 +937,8 @@ hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T
   if (m <= 0) return hipSuccess;
   const int nch = multidot_chunks(n, m, rb);
   const size_t clen = chunk_len(n, nch);
-  k_multidot<T><<<dim3((m + G - 1) / G, nch), NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch,
-                                                          reverse);
+  k_multidot<T><<<((m + G - 1) / G) * nch, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch,
+                                                       reverse);
   return hipGetLastError();
 }
 

@@ -300,3 +300,42 @@ def test_two_problems_are_independent():
         pb.close()
     assert torch.equal(ua, ua2)
     assert not torch.equal(ua, ub)
+
+
+@pytest.mark.parametrize("levels", [4, 5])
+def test_deeper_hierarchies(levels):
+    """4- and 5-level MADP (the fourth- to sixth-level stencils of Appendix A):
+    one FGMRES step on every level below 2, Krylov CSLP on levels >= 3."""
+    nx = ny = 129
+    h = 1.0 / 128
+    k = medium(nx, ny, 20.0, 3, spread=0.2)
+    o = MADP(nx, ny, h, k, levels=levels)
+    b = workloads.point_source(nx, ny, h, 60, 70)
+    u_ref, info_ref = o.solve(b)
+    p = make(nx, ny, h, k, levels=levels)
+    try:
+        hm.reset_counts(p)
+        u, info = hm.fgmres_solve(p, gpu(b))
+        got = hm.get_counts(p, hm.KIND_CSLP)
+    finally:
+        p.close()
+    # per level-3..(L-1) preconditioner call the coarser solves run first; the
+    # GPU records all Krylov CSLP solves in call order
+    order = []
+    seqs = {l: list(o.log.data["cslp_l%d" % l]) for l in range(3, levels + 1)}
+
+    def expand(l):                      # the CSLP calls made by one Prec_l, l >= 3
+        if l + 1 == levels:
+            order.append(seqs[levels].pop(0))
+        else:
+            expand(l + 1)
+        order.append(seqs[l].pop(0))
+    while seqs[levels]:
+        if levels == 3:
+            order.append(seqs[3].pop(0))
+        else:
+            expand(3)
+    assert got == order
+    assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+    assert np.linalg.norm(host(u) - u_ref) / np.linalg.norm(u_ref) <= 1e-5
+    assert info["rel_res_true"] <= 1e-6
