@@ -27,19 +27,19 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 # calibrated hardware byte counts of the dominant kernel (two rocprofv3 --pmc
 # passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size);
 # valid only while the kernel source is unchanged
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_k_multidot.json")
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_gmres_kernels.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_04980_amd", "csrc", "kernels.hip")
 
 
 def measured_traffic(kernel_class):
     import hashlib
-    if kernel_class != "cgs_dot" or not os.path.exists(TRAFFIC_RECORD):
+    if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = json.load(open(TRAFFIC_RECORD))
     digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    if rec.get("kernels_hip_sha256") != digest:
+    if rec.get("kernels_hip_sha256") != digest or kernel_class not in rec["classes"]:
         return None
-    return rec["bytes_per_launch"]
+    return rec["classes"][kernel_class]["bytes_per_launch"]
 
 
 def parse():
