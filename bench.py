@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+TIMING_EVERY = 16
 # calibrated hardware byte counts of the dominant kernel (two rocprofv3 --pmc
 # passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size);
 # valid only while the kernel source is unchanged
@@ -73,7 +74,9 @@ def timed_solves(hm, torch, prob, b, steps, warmup, timing):
         hm.fgmres_solve(prob, b, out=u)
         log("warmup solve %d done" % i)
     if timing:
-        hm.set_timing(prob, (1 << len(hm.TIMING_CLASSES)) - 1)
+        # bracket every 16th launch of each class: enough samples for the
+        # averages, negligible event overhead in the timed solves
+        hm.set_timing(prob, (1 << len(hm.TIMING_CLASSES)) - 1, TIMING_EVERY)
     torch.cuda.synchronize()
     lat, infos = [], []
     t_start = time.perf_counter()
@@ -263,8 +266,11 @@ def main():
                            "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                            "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1),
                            "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1)}
-        res["kernel_classes"] = {c: {"ms_per_solve": v["ms"] / args.steps, "GBps": v["GBps"],
-                                     "launches_per_solve": v["launches"] / args.steps}
+        res["roofline"]["sampled_launches"] = d["launches"]
+        res["roofline"]["sampling"] = "every %d-th launch of the class" % TIMING_EVERY
+        res["kernel_classes"] = {c: {"est_ms_per_solve": v["ms"] * TIMING_EVERY / args.steps,
+                                     "GBps": v["GBps"],
+                                     "timed_launches": v["launches"]}
                                  for c, v in classes.items()}
     if not args.no_mixed:
         cfgm = hm.default_config(problem.nx, problem.ny, problem.h, precision=hm.HM_MIXED_FP32)

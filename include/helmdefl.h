@@ -165,13 +165,15 @@ hm_status hm_set_replay(hm_problem* p, int kind, const int* counts, int n);
 hm_status hm_get_counts(const hm_problem* p, int kind, int* counts, int cap, int* n);
 hm_status hm_reset_counts(hm_problem* p);
 
-/* Kernel timing for roofline measurements.  hm_set_timing(p, mask) resets the
- * counters and, for every kernel class whose bit is set in mask, brackets each
- * launch with HIP events on the problem's stream (adds a few microseconds of
- * host work per launch; mask 0 turns it off).  hm_get_timing returns, for one
- * class, the summed event time in milliseconds, the summed algorithmic bytes of
- * those launches (each input array read once, each output written once) and the
- * number of launches. */
+/* Kernel timing for roofline measurements.  hm_set_timing(p, mask, every)
+ * resets the counters and, for every kernel class whose bit is set in mask,
+ * brackets every `every`-th launch of that class (the 1st, (every+1)-th, ...)
+ * with HIP events on the problem's stream; mask 0 turns it off.  Each bracket
+ * costs a few microseconds of device time, so sampling (every > 1) keeps the
+ * measured run close to an untimed one.  hm_get_timing returns, for one class,
+ * the summed event time in milliseconds of the bracketed launches, their summed
+ * algorithmic bytes (each input array read once, each output written once) and
+ * their number. */
 enum {
   HM_TK_CGS_DOT = 0,     /* Krylov CSLP: dots of w against the basis (classical GS)    */
   HM_TK_CGS_UPDATE = 1,  /* Krylov CSLP: w -= V h fused with ||w||                       */
@@ -180,7 +182,7 @@ enum {
   HM_TK_MGS = 4,         /* modified Gram-Schmidt steps (outer and level-2 FGMRES)        */
   HM_TK_COUNT = 5
 };
-hm_status hm_set_timing(hm_problem* p, unsigned mask);
+hm_status hm_set_timing(hm_problem* p, unsigned mask, int every);
 hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes, long* launches);
 
 hm_status hm_destroy_problem(hm_problem* p);

@@ -99,7 +99,7 @@ def _load():
         "hm_set_replay": (I, [P, I, ctypes.POINTER(I), I]),
         "hm_get_counts": (I, [P, I, ctypes.POINTER(I), I, ctypes.POINTER(I)]),
         "hm_reset_counts": (I, [P]),
-        "hm_set_timing": (I, [P, ctypes.c_uint]),
+        "hm_set_timing": (I, [P, ctypes.c_uint, I]),
         "hm_get_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D),
                               ctypes.POINTER(ctypes.c_long)]),
         "hm_destroy_problem": (I, [P]),
@@ -260,13 +260,15 @@ def reset_counts(prob):
     _check(_lib.hm_reset_counts(prob.handle))
 
 
-def set_timing(prob, mask):
-    """Enables HIP-event timing of the kernel classes in `mask` (bit per class)."""
-    _check(_lib.hm_set_timing(prob.handle, ctypes.c_uint(mask)))
+def set_timing(prob, mask, every=1):
+    """Enables HIP-event timing of every `every`-th launch of the kernel classes in
+    `mask` (one bit per class); mask 0 turns it off."""
+    _check(_lib.hm_set_timing(prob.handle, ctypes.c_uint(mask), int(every)))
 
 
 def get_timing(prob):
-    """{class name: (milliseconds, algorithmic bytes, launches)} since set_timing."""
+    """{class name: (milliseconds, algorithmic bytes, launches)} of the timed
+    launches since set_timing."""
     out = {}
     for cls, name in TIMING_CLASSES.items():
         ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_long()

@@ -149,6 +149,10 @@ struct MGHier {
   c128* tmpB = nullptr;
   KrylovWS gm;                // coarsest GMRES otherwise
   int maxit = 0;
+  // with a dense coarsest solve the whole cycle is a fixed kernel sequence on
+  // fixed buffers: captured once as a HIP graph (input = the level's r~ buffer)
+  hipGraphExec_t graph = nullptr;
+  const void* graph_out = nullptr;
 };
 
 struct DefLevel {
@@ -257,6 +261,7 @@ struct hm_problem {
   c128* host_H = nullptr;      // pinned mirror of a GMRES Hessenberg (lookahead loop)
   size_t host_H_cap = 0;
   hipEvent_t col_ev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;   // private stream for graph capture
   // counts
   std::vector<int> rec[K_NKIND];
   std::vector<int> rep[K_NKIND];
@@ -264,6 +269,8 @@ struct hm_problem {
   double last_estimate = 0;
   // optional per-kernel-class timing with HIP events on the problem's stream
   unsigned timing_mask = 0;
+  int timing_every = 1;                 // bracket every n-th launch of a class
+  long timing_seen[HM_TK_COUNT] = {0};
   struct Pending { hipEvent_t a, b; int cls; double bytes; };
   std::vector<Pending> pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
@@ -285,7 +292,7 @@ static int forced_count(hm_problem* p, int kind) {
 // Timed launch: brackets the launch with events when its class is enabled.
 template <typename F>
 static void timed(hm_problem* p, int cls, double bytes, F&& launch) {
-  if (!(p->timing_mask & (1u << cls))) {
+  if (!(p->timing_mask & (1u << cls)) || (p->timing_seen[cls]++ % p->timing_every) != 0) {
     HM_CHECK(launch());
     return;
   }
@@ -456,6 +463,38 @@ static const cx<T>* mg_cycle(hm_problem* p, DefLevel& D, int q, const cx<T>* b) 
   return x;
 }
 
+// One V-cycle for the CSLP of level D on b.  When b is the level's r~ buffer
+// and the coarsest solve is dense, the cycle runs as a HIP graph captured on
+// first use (no host decisions inside, no memset nodes); otherwise eagerly.
+template <typename T>
+static const cx<T>* vcycle(hm_problem* p, DefLevel& D, const cx<T>* b) {
+  MGHier& H = D.mg;
+  if (!H.dense || (const void*)b != D.rt || !p->cap_stream) return mg_cycle<T>(p, D, 0, b);
+  if (!H.graph) {
+    hipStream_t saved = p->s;
+    hipGraph_t g = nullptr;
+    HM_CHECK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    p->s = p->cap_stream;
+    const cx<T>* out = nullptr;
+    try {
+      out = mg_cycle<T>(p, D, 0, b);
+    } catch (...) {
+      p->s = saved;
+      (void)hipStreamEndCapture(p->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    p->s = saved;
+    HM_CHECK(hipStreamEndCapture(p->cap_stream, &g));
+    const hipError_t e = hipGraphInstantiate(&H.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HM_CHECK(e);
+    H.graph_out = out;
+  }
+  HM_CHECK(hipGraphLaunch(H.graph, p->s));
+  return (const cx<T>*)H.graph_out;
+}
+
 }  // namespace hm
 
 namespace hm {
@@ -467,7 +506,7 @@ template <typename T> static void precond(hm_problem* p, int l, const cx<T>* v, 
 template <typename T>
 static const cx<T>* cslp_apply(hm_problem* p, int l, const cx<T>* r, cx<T>* out) {
   DefLevel& D = p->lev[l];
-  if (D.has_mg) return mg_cycle<T>(p, D, 0, r);
+  if (D.has_mg) return vcycle<T>(p, D, r);
   gmres_cgs<T>(p, opsel<T>(D, true), levk<T>(D), D.cslp, D.cslp_maxit, p->cfg.tol_cslp, K_CSLP, r,
                out);
   return out;
@@ -1006,7 +1045,12 @@ static void op_level(hm_problem* p, int l, int sub, int which, const c128* in, c
     case HM_OP_M: apply_level<T>(p, D, true, ST_APPLY, v, nullptr, o); break;
     case HM_OP_VCYCLE: {
       if (!D.has_mg) throw ArgError("level has no multigrid hierarchy");
-      const cx<T>* r = mg_cycle<T>(p, D, 0, v);
+      const cx<T>* src = v;
+      if (D.rt) {                       // the preconditioner's buffer: graph path
+        HM_CHECK(hipMemcpyAsync(D.rt, v, sizeof(cx<T>) * D.N, hipMemcpyDeviceToDevice, p->s));
+        src = (const cx<T>*)D.rt;
+      }
+      const cx<T>* r = vcycle<T>(p, D, src);
       HM_CHECK(hipMemcpyAsync(o, r, sizeof(cx<T>) * D.N, hipMemcpyDeviceToDevice, p->s));
       break;
     }
@@ -1127,6 +1171,7 @@ hm_status hm_create_problem(const hm_config* cfg, const double* k_dev, void* wor
       HM_CHECK(hipHostMalloc((void**)&p->host_coef, sizeof(c128) * p->host_cap, hipHostMallocDefault));
       HM_CHECK(hipHostMalloc((void**)&p->host_H, sizeof(c128) * std::max<size_t>(p->host_H_cap, 1),
                              hipHostMallocDefault));
+      HM_CHECK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
       HM_CHECK(hipEventCreateWithFlags(&p->col_ev[0], hipEventDisableTiming));
       HM_CHECK(hipEventCreateWithFlags(&p->col_ev[1], hipEventDisableTiming));
       initialize(p, k_dev);
@@ -1229,6 +1274,9 @@ hm_status hm_destroy_problem(hm_problem* p) {
     (void)hipEventDestroy(e.first);
     (void)hipEventDestroy(e.second);
   }
+  for (auto& D : p->lev)
+    if (D.mg.graph) (void)hipGraphExecDestroy(D.mg.graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (auto& e : p->col_ev)
     if (e) (void)hipEventDestroy(e);
   if (p->host_H) (void)hipHostFree(p->host_H);
@@ -1238,16 +1286,18 @@ hm_status hm_destroy_problem(hm_problem* p) {
   return HM_OK;
 }
 
-hm_status hm_set_timing(hm_problem* p, unsigned mask) {
-  if (!p) return HM_ERR_ARG;
+hm_status hm_set_timing(hm_problem* p, unsigned mask, int every) {
+  if (!p || every < 1) return HM_ERR_ARG;
   return guard([&]() -> hm_status {
     HM_CHECK(hipStreamSynchronize(p->s));
     harvest(p);
     p->timing_mask = mask;
+    p->timing_every = every;
     for (int c = 0; c < HM_TK_COUNT; ++c) {
       p->t_ms[c] = 0;
       p->t_bytes[c] = 0;
       p->t_launches[c] = 0;
+      p->timing_seen[c] = 0;
     }
     return HM_OK;
   });

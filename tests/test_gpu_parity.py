@@ -114,11 +114,17 @@ def test_multigrid_components(small, level):
 
 @pytest.mark.parametrize("level", [1, 2])
 def test_vcycle(small, level):
+    """The V-cycle runs as a captured HIP graph after its first use: replay it
+    several times on different inputs, with unrelated eager work and
+    synchronisations in between, and check every replay against the oracle."""
     nx, ny, h, k, o, p64, p32 = small
-    x = rand_c(o.levels[level].N, 60 + level)
-    ref = o.mg[level](x)
-    assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_VCYCLE, gpu(x))), ref) <= 1e-12
-    assert relerr(host(hm.apply_operator(p32, level, hm.HM_OP_VCYCLE, gpu(x))), ref) <= 1e-5
+    for rep in range(4):
+        x = rand_c(o.levels[level].N, 60 + 10 * rep + level)
+        ref = o.mg[level](x)
+        assert relerr(host(hm.apply_operator(p64, level, hm.HM_OP_VCYCLE, gpu(x))), ref) <= 1e-12
+        assert relerr(host(hm.apply_operator(p32, level, hm.HM_OP_VCYCLE, gpu(x))), ref) <= 1e-5
+        hm.apply_operator(p64, level, hm.HM_OP_A, gpu(x))          # eager work between replays
+        torch.cuda.synchronize()
 
 
 def test_coarsest_cslp_gmres(small):
