@@ -922,13 +922,19 @@ int reduction_chunks(size_t n) {
 }
 
 // chunks of the multi-dot: long chunks (fewer partials per dot) for short
-// bases, shorter ones once the (m / G) groups already give enough blocks
+// bases, shorter ones for long bases; at least ~2048 blocks in flight when the
+// vector allows one element per thread; a multiple of 8 (one slot per XCD)
 static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
-  const size_t per = m >= 40 ? NT * 4 : NT * 16;
-  int nch = (int)((n + per - 1) / per);
-  nch = nch < 1 ? 1 : (nch > kMaxChunks ? kMaxChunks : nch);
   (void)rb;
-  return (nch + 7) & ~7;             // a multiple of 8 (one slot per XCD)
+  const size_t per = m >= 40 ? NT * 4 : NT * 16;
+  const int ngroups = (m + G - 1) / G;
+  size_t nch = (n + per - 1) / per;
+  const size_t want = (2048 + ngroups - 1) / ngroups;
+  const size_t most = (n + NT - 1) / NT;          // one element per thread
+  if (nch < want) nch = want < most ? want : most;
+  if (nch < 1) nch = 1;
+  if (nch > (size_t)kMaxChunks) nch = kMaxChunks;
+  return (int)((nch + 7) & ~(size_t)7);
 }
 
 template <typename T>
@@ -966,10 +972,15 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
   return hipGetLastError();
 }
 
-// chunks of the update: four elements per thread (two per pass)
+// chunks of the update: about sqrt(n) blocks, i.e. more blocks with fewer
+// elements per thread as the vector grows (measured on 257^2 .. 1025^2 levels:
+// 1, 2 and 4 elements per thread beat the alternatives), at most kMaxChunks
 static int update_chunks(size_t n, const RedBuf& rb) {
-  int nch = (int)((n + NT * 4 - 1) / (NT * 4));
-  return nch < 1 ? 1 : (nch > rb.nchunks ? rb.nchunks : nch);
+  (void)rb;
+  size_t nch = (size_t)std::ceil(std::sqrt((double)n));
+  if (nch < 1) nch = 1;
+  if (nch > (size_t)kMaxChunks) nch = kMaxChunks;
+  return (int)nch;
 }
 
 template <typename T>
