@@ -923,17 +923,26 @@ int reduction_chunks(size_t n) {
 
 // chunks of the multi-dot: long chunks (fewer partials per dot) for short
 // bases, shorter ones for long bases; at least ~2048 blocks in flight when the
-// vector allows one element per thread; a multiple of 8 (one slot per XCD)
-static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
-  (void)rb;
+// vector allows one element per thread.  The chunk length is a whole number of
+// 256-element passes and the chunk count a multiple of 8 (one slot per XCD;
+// trailing chunks may be empty).
+static size_t multidot_chunk_len(size_t n, int m) {
   const size_t per = m >= 40 ? NT * 4 : NT * 16;
   const int ngroups = (m + G - 1) / G;
   size_t nch = (n + per - 1) / per;
   const size_t want = (2048 + ngroups - 1) / ngroups;
-  const size_t most = (n + NT - 1) / NT;          // one element per thread
+  const size_t most = (n + NT - 1) / NT;
   if (nch < want) nch = want < most ? want : most;
   if (nch < 1) nch = 1;
-  if (nch > (size_t)kMaxChunks) nch = kMaxChunks;
+  size_t clen = (n + nch - 1) / nch;
+  clen = (clen + NT - 1) / NT * NT;
+  while ((n + clen - 1) / clen > (size_t)kMaxChunks) clen += NT;
+  return clen;
+}
+static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
+  (void)rb;
+  const size_t clen = multidot_chunk_len(n, m);
+  const size_t nch = (n + clen - 1) / clen;
   return (int)((nch + 7) & ~(size_t)7);
 }
 
@@ -942,7 +951,7 @@ hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T
                                    RedBuf rb, int reverse, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const int nch = multidot_chunks(n, m, rb);
-  const size_t clen = chunk_len(n, nch);
+  const size_t clen = multidot_chunk_len(n, m);
   k_multidot<T><<<((m + G - 1) / G) * nch, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch,
                                                        reverse);
   return hipGetLastError();
@@ -972,22 +981,27 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
   return hipGetLastError();
 }
 
-// chunks of the update: about sqrt(n) blocks, i.e. more blocks with fewer
-// elements per thread as the vector grows (measured on 257^2 .. 1025^2 levels:
-// 1, 2 and 4 elements per thread beat the alternatives), at most kMaxChunks
+// chunk length of the update: whole passes of the two-element loop, with
+// e = 1, 2, 4, ... elements per thread growing like sqrt(n) / 256 (so the
+// block count also grows like sqrt(n)); a partial last pass would make one
+// thread of each block re-read all m basis vectors
+static size_t update_chunk_len(size_t n) {
+  size_t e = 1;
+  while ((double)(2 * e) * NT <= std::sqrt((double)n) * 1.5) e *= 2;
+  size_t clen = (size_t)NT * e;
+  while ((n + clen - 1) / clen > (size_t)kMaxChunks) clen += 2 * NT;
+  return clen;
+}
 static int update_chunks(size_t n, const RedBuf& rb) {
   (void)rb;
-  size_t nch = (size_t)std::ceil(std::sqrt((double)n));
-  if (nch < 1) nch = 1;
-  if (nch > (size_t)kMaxChunks) nch = kMaxChunks;
-  return (int)nch;
+  return (int)((n + update_chunk_len(n) - 1) / update_chunk_len(n));
 }
 
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                      size_t n, RedBuf rb, int reverse, hipStream_t s) {
   const int nch = update_chunks(n, rb);
-  const size_t clen = chunk_len(n, nch);
+  const size_t clen = update_chunk_len(n);
   k_cgs_update_norm<T><<<nch, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, reverse);
   return hipGetLastError();
 }
