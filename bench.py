@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--rate", type=float, default=50.0, help="offered requests/s")
     ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--matvec", action="store_true",
+                    help="matrix-free versus CSR matvec of the finest operator on grids "
+                         "17^2 .. 16385^2 (100 consecutive products per form and size)")
+    ap.add_argument("--matvec-max-side", type=int, default=16385)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size, to calibrate hardware byte counters)")
@@ -188,6 +192,86 @@ def serving_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# Per-row byte and flop counts of the two matvec forms (complex128 vectors,
+# float64 wavenumber, 32-bit indices).  "compulsory": every array touched once
+# (the HBM floor); "model": the per-row accounting of Appendix B (every value
+# read per use, result read and written) with 16-byte complex values.
+MATVEC_BYTES = {"matfree": {"compulsory": 16 + 8 + 16, "model": 5 * 16 + 8 + 16},
+                "csr": {"compulsory": 5 * 16 + 5 * 4 + 4 + 16 + 16,
+                        "model": 5 * (16 + 4 + 16) + 4 + 2 * 16}}
+# matrix-free: k^2 and the centre coefficient (2), five real-by-complex
+# products (10), four complex additions (8); CSR: five complex multiply-adds
+MATVEC_FLOPS = {"matfree": 20, "csr": 40}
+
+
+def matvec_bench(args, reps=100):
+    import torch
+
+    import paper_2412_04980_amd as hm
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    rows = []
+    side = 17
+    while side <= args.matvec_max_side:
+        n = side * side
+        h = 1.0 / (side - 1)
+        gen.manual_seed(side)
+        k = 20.0 + 40.0 * torch.rand(n, dtype=torch.float64, device=dev, generator=gen)
+        u = torch.randn(n, dtype=torch.complex128, device=dev, generator=gen)
+        v = torch.empty_like(u)
+        y = torch.empty_like(u)
+        rp, ci, va = hm.csr_assemble(side, side, h, k)
+        times = {}
+        for form in ("matfree", "csr"):
+            def once():
+                if form == "matfree":
+                    hm.matfree_apply(side, side, h, k, u, out=v)
+                else:
+                    hm.csr_spmv(rp, ci, va, u, out=y)
+            for _ in range(3):
+                once()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                once()
+            e1.record()
+            e1.synchronize()
+            times[form] = e0.elapsed_time(e1) / reps
+        diff = float((v - y).abs().max() / v.abs().max())
+        row = {"side": side, "N": n, "max_rel_diff": diff}
+        for form in ("matfree", "csr"):
+            ms = times[form]
+            row[form] = {"ms": ms,
+                         "GBs": MATVEC_BYTES[form]["compulsory"] * n / ms / 1e6,
+                         "GBs_model": MATVEC_BYTES[form]["model"] * n / ms / 1e6,
+                         "GFLOPs": MATVEC_FLOPS[form] * n / ms / 1e6}
+        row["time_ratio_csr_over_matfree"] = times["csr"] / times["matfree"]
+        log("N=%11d  matfree %.4f ms %7.1f GB/s | csr %.4f ms %7.1f GB/s | ratio %.2f" % (
+            n, times["matfree"], row["matfree"]["GBs"], times["csr"], row["csr"]["GBs"],
+            row["time_ratio_csr_over_matfree"]))
+        rows.append(row)
+        del k, u, v, y, rp, ci, va
+        torch.cuda.empty_cache()
+        side = 2 * (side - 1) + 1
+    big = rows[-1]
+    out = {"metric": "matvec time, matrix-free vs CSR, complex FP64 5-point Sommerfeld operator",
+           "value": big["time_ratio_csr_over_matfree"], "unit": "x (CSR time / matrix-free time)",
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "reps_per_size": reps,
+           "bytes_per_row": MATVEC_BYTES, "flops_per_row": MATVEC_FLOPS,
+           "roofline": {"bound": "hbm", "kernel": "matrix-free 5-point apply",
+                        "N": big["N"], "achieved": big["matfree"]["GBs"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": big["matfree"]["GBs"] / HBM_PEAK_GBS},
+           "roofline_csr": {"bound": "hbm", "achieved": big["csr"]["GBs"], "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": big["csr"]["GBs"] / HBM_PEAK_GBS},
+           "config": {"workload": "matvec sweep, square grids 17^2 .. %d^2, k uniform in "
+                                  "[20, 60]" % rows[-1]["side"]},
+           "table": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -203,6 +287,9 @@ def main():
 
     if args.serving:
         serving_bench(args)
+        return
+    if args.matvec:
+        matvec_bench(args)
         return
     dev = torch.device("cuda:0")
     if args.copy_calibration:

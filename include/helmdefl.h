@@ -10,7 +10,7 @@
  * all four sides imposed through the ghost point u_ghost = u_mirror + 2 i h k u_b
  * (eq. ghost_sommerfeld).  The outer solver is FGMRES from a zero initial guess
  * stopping at ||b - A u||_2 / ||b||_2 <= tol_outer (Sec. 4); the preconditioner
- * is MADP (Sec. 4.3): Algorithm 1 applied recursively over `levels` levels with
+ * is MADP (Sec. 4.4): Algorithm 1 applied recursively over `levels` levels with
  * the CSLP  M = -Lap - (beta1 + i beta2) k^2  (eq. CSLP def) approximated by one
  * multigrid V-cycle on levels 1-2 and by GMRES on coarser levels, the
  * Galerkin-derived re-discretised coarse stencils of Sec. 3.3 and the
@@ -67,10 +67,10 @@ typedef struct {
   int nx, ny;            /* nodes incl. boundary; (n-1) divisible by 2^(levels-1)   */
   double h;              /* mesh width                                              */
   int bc;                /* hm_bc                                                   */
-  double beta1, beta2;   /* CSLP shift (Sec. 3.1); MADP uses (1, 0.5) (Sec. 4.3)     */
+  double beta1, beta2;   /* CSLP shift (Sec. 3.1); MADP uses (1, 0.5) (Sec. 4.4)     */
   int levels;            /* deflation levels, >= 2 (MADP default 3)                 */
   double tol_outer;      /* outer relative residual (Sec. 4: 1e-6)                  */
-  double tol_level2;     /* level-2 FGMRES relative tolerance (Sec. 4.3: 0.3)       */
+  double tol_level2;     /* level-2 FGMRES relative tolerance (Sec. 4.4: 0.3)       */
   double tol_cslp;       /* Krylov CSLP relative tolerance (Sec. 4.2: 0.1)          */
   double maxit_coef;     /* Krylov CSLP step cap floor(coef * N^(1/4)) (Sec. 4.2: 6) */
   int outer_restart;     /* outer FGMRES restart length (30)                        */
@@ -78,7 +78,14 @@ typedef struct {
   int level2_maxit;      /* level-2 FGMRES step cap (100)                           */
   int mg_nu_pre, mg_nu_post;  /* Jacobi sweeps of the CSLP V-cycle (1, 1)           */
   int precision;         /* hm_precision                                            */
-  int reserved[8];       /* must be zero                                            */
+  int coarse_steps;      /* m: FGMRES steps on every coarse level solved without a
+                            tolerance, the coarsest always (Sec. 3.2, cycle type:
+                            1 = V-cycle, the MADP setting; 2 = W-cycle); 1..16      */
+  int tol_levels;        /* levels 2..tol_levels (above the coarsest) iterate to
+                            tol_level2 with at most level2_maxit steps: 2 = MADP;
+                            1 = every coarse level takes coarse_steps; 3-4 = the
+                            tolerance on the third/fourth levels too (Sec. 4.5)   */
+  int reserved[6];       /* must be zero                                            */
 } hm_config;
 
 typedef struct {
@@ -91,7 +98,7 @@ typedef struct {
   double seconds;              /* wall time of the call (host clock)                 */
 } hm_solve_info;
 
-/* Fills *cfg with the MADP configuration of Sec. 4.3 for an nx x ny grid of
+/* Fills *cfg with the MADP configuration of Sec. 4.4 for an nx x ny grid of
  * spacing h: 3 levels, beta = (1, 0.5), tolerances 1e-6 / 0.3 / 0.1, cap
  * coefficient 6, restart 30, outer cap 300, level-2 cap 100, V(1,1), FP64. */
 void hm_default_config(hm_config* cfg, int nx, int ny, double h);
@@ -186,6 +193,34 @@ hm_status hm_set_timing(hm_problem* p, unsigned mask, int every);
 hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes, long* launches);
 
 hm_status hm_destroy_problem(hm_problem* p);
+
+/* ---- Matrix-free versus stored-matrix matvec (Appendix B, Table of the
+ * matrix-free / CSR comparison) ----------------------------------------------
+ * Both forms compute v = A u for the finest-level operator of eq. (helm
+ * operator h): the 5-point Helmholtz stencil -Laplace_h - k^2 on an nx x ny
+ * node grid with spacing h, first-order Sommerfeld ghosts on all four sides
+ * (Sec. 2).  Row-major node order p = y*nx + x; u, v complex128 (interleaved
+ * re, im), k float64 per node, all device pointers owned by the caller.
+ * nx, ny >= 3; nx*ny*5 must fit in a 32-bit int (grids up to 20723^2).
+ * Asynchronous on `stream` (NULL = the default stream); HM_ERR_ARG for bad
+ * sizes or null pointers, HM_ERR_HIP for a failed launch.  They need no
+ * problem object.
+ *
+ * hm_matfree_apply: v = A u straight from the stencil (per node: u and its four
+ *   neighbours, k, one write).
+ * hm_csr_assemble: writes A in CSR form: row_ptr (nx*ny+1 ints), col_idx
+ *   (5*nx*ny ints), vals (5*nx*ny complex128).  Every row holds exactly five
+ *   entries (centre, west, east, south, north); at a boundary the ghost's
+ *   coupling is folded into the mirrored neighbour and the freed slot holds an
+ *   explicit zero whose column is the row itself.
+ * hm_csr_spmv: y = A x for any CSR matrix with 32-bit indices (nrows rows,
+ *   columns < the length of x), one thread per row. */
+hm_status hm_matfree_apply(int nx, int ny, double h, const double* k_dev, const void* u_dev,
+                           void* v_dev, void* stream);
+hm_status hm_csr_assemble(int nx, int ny, double h, const double* k_dev, int* row_ptr_dev,
+                          int* col_idx_dev, void* vals_dev, void* stream);
+hm_status hm_csr_spmv(int nrows, const int* row_ptr_dev, const int* col_idx_dev,
+                      const void* vals_dev, const void* x_dev, void* y_dev, void* stream);
 
 const char* hm_status_string(hm_status s);
 const char* hm_last_error(void);

@@ -15,7 +15,7 @@ Modules
              (Sec. 2.1), re-discretised 5x5/7x7 coarse operators with the
              boundary rule of Sec. 3.3, deflation vectors Z, multigrid transfers
   krylov     GMRES / FGMRES with modified Gram-Schmidt (Algorithm 1)
-  multigrid  V-cycle approximation of the CSLP inverse (Sec. 3.2, 4.3)
+  multigrid  V-cycle approximation of the CSLP inverse (Sec. 3.2, 4.4)
   madp       the MADP hierarchy, preconditioner application and outer solve
 
 Parity status of every function is recorded in its docstring; functions that

@@ -2,17 +2,17 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Operators are assembled
 CSR matrices; the steps follow Algorithm 1 of the paper (recursive two-level
-deflated FGMRES) with the MADP configuration of Sec. 4.3:
+deflated FGMRES) with the MADP configuration of Sec. 4.4:
 
   level l preconditioner  Prec_l(v):
       v_hat = Z_l^T v                                   (restriction)
       if l+1 is the coarsest level L:
-          v_t = one FGMRES step on E_{l+1} v_t = v_hat, preconditioned by the
+          v_t = m FGMRES steps on E_{l+1} v_t = v_hat, preconditioned by the
                 CSLP of level l+1 approximated by GMRES (tol 0.1,
                 at most floor(6 N^(1/4)) steps)
       else:
           v_t = FGMRES on E_{l+1} v_t = v_hat preconditioned by Prec_{l+1},
-                to relative tolerance 0.3 on level 2, one step on levels >= 3
+                to relative tolerance 0.3 on level 2, m steps on levels >= 3
       t  = Z_l v_t                                      (interpolation)
       r~ = v - A_l t
       r  = CSLP_l^-1 r~   (one multigrid V-cycle on levels 1-2, GMRES below)
@@ -27,6 +27,14 @@ are the re-discretised Galerkin-derived stencils (Sec. 3.3).  The optional
 coarsest solve by a dense direct solve, and `cslp_override` replaces the CSLP
 approximation of a level by a given map; both exist only for the deflation
 identities of Sec. 3.1 (tests).
+
+Variants of the same algorithm (Sec. 3.2, the cycle type, and Sec. 4.4-4.5):
+`coarse_steps` is m, the fixed number of FGMRES steps on every coarse level
+that has no tolerance (1: V-cycle, the MADP setting; 2: W-cycle);
+`tol_levels` is the deepest level that iterates to `tol_level2` instead (2: MADP;
+1: every coarse level takes m steps; 3 or 4: the tolerance also on the third
+and fourth levels, the variant of the per-level tolerance table of Sec. 4.5).
+The coarsest level always takes m steps.  MADP-v3 is tol_level2 = 0.1.
 """
 import time
 
@@ -55,8 +63,9 @@ class Level:
 class MADP:
     def __init__(self, nx, ny, h, k, levels=3, beta=(1.0, 0.5), tol_level2=0.3,
                  tol_cslp=0.1, maxit_coef=6.0, level2_maxit=100, nu_pre=1, nu_post=1,
-                 log=None, galerkin_coarse=False, cslp_override=None):
-        assert levels >= 2
+                 log=None, galerkin_coarse=False, cslp_override=None, coarse_steps=1,
+                 tol_levels=2):
+        assert levels >= 2 and coarse_steps >= 1 and tol_levels >= 1
         f = 2 ** (levels - 1)
         if (nx - 1) % f or (ny - 1) % f:
             raise ValueError("(n-1) must be divisible by 2^(levels-1)")
@@ -64,6 +73,7 @@ class MADP:
         self.beta = beta
         self.tol_level2, self.tol_cslp = tol_level2, tol_cslp
         self.maxit_coef, self.level2_maxit = maxit_coef, level2_maxit
+        self.coarse_steps, self.tol_levels = coarse_steps, tol_levels
         self.log = log if log is not None else CountLog("record")
         self.galerkin_coarse = galerkin_coarse
         self.cslp_override = dict(cslp_override or {})
@@ -111,12 +121,12 @@ class MADP:
             return sla.solve(lev.A.toarray(), v_hat)
         if c == self.L:
             x, _, _ = fgmres(lambda v: lev.A @ v, v_hat, lambda v: self.cslp(c, v),
-                             tol=None, maxit=1)
+                             tol=None, maxit=self.coarse_steps)
             return x
-        if c == 2:
+        if c <= self.tol_levels:
             tol, maxit = self.tol_level2, self.level2_maxit
         else:
-            tol, maxit = None, 1
+            tol, maxit = None, self.coarse_steps
         x, _, _ = fgmres(lambda v: lev.A @ v, v_hat, lambda v: self.precond(c, v),
                          tol=tol, maxit=maxit, log=self.log, kind="level%d" % c)
         return x

@@ -1,6 +1,6 @@
 """Multigrid V-cycle approximating the CSLP inverse (oracle; test infrastructure).
 
-Sec. 3.2 and Sec. 4.3 of the paper replace the Krylov approximation of the CSLP
+Sec. 3.2 and Sec. 4.4 of the paper replace the Krylov approximation of the CSLP
 inverse on the first and second levels by one multigrid V-cycle with complex
 shift beta2 = 0.5 and defer the settings to the authors' earlier matrix-free
 multigrid.  Those settings are not printed, so this module fixes a reading

@@ -44,7 +44,8 @@ TIMING_CLASSES = {HM_TK_CGS_DOT: "cgs_dot", HM_TK_CGS_UPDATE: "cgs_update_norm",
 EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_precond_apply",
             "hm_fgmres_solve", "hm_apply_operator", "hm_level_shape", "hm_set_replay",
             "hm_get_counts", "hm_reset_counts", "hm_set_timing", "hm_get_timing",
-            "hm_destroy_problem", "hm_status_string", "hm_last_error"]
+            "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
+            "hm_status_string", "hm_last_error"]
 
 
 class HmConfig(ctypes.Structure):
@@ -55,7 +56,8 @@ class HmConfig(ctypes.Structure):
                 ("maxit_coef", ctypes.c_double), ("outer_restart", ctypes.c_int),
                 ("outer_maxit", ctypes.c_int), ("level2_maxit", ctypes.c_int),
                 ("mg_nu_pre", ctypes.c_int), ("mg_nu_post", ctypes.c_int),
-                ("precision", ctypes.c_int), ("reserved", ctypes.c_int * 8)]
+                ("precision", ctypes.c_int), ("coarse_steps", ctypes.c_int),
+                ("tol_levels", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
 
     def replace(self, **kw):
         c = HmConfig()
@@ -103,6 +105,9 @@ def _load():
         "hm_get_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D),
                               ctypes.POINTER(ctypes.c_long)]),
         "hm_destroy_problem": (I, [P]),
+        "hm_matfree_apply": (I, [I, I, D, P, P, P, P]),
+        "hm_csr_assemble": (I, [I, I, D, P, P, P, P, P]),
+        "hm_csr_spmv": (I, [I, P, P, P, P, P, P]),
         "hm_status_string": (ctypes.c_char_p, [I]),
         "hm_last_error": (ctypes.c_char_p, []),
     }
@@ -276,6 +281,56 @@ def get_timing(prob):
                                   ctypes.byref(n)))
         out[name] = (ms.value, by.value, n.value)
     return out
+
+
+def _f64(x, n, name):
+    if not (x.is_cuda and x.dtype == torch.float64 and x.numel() == n and x.is_contiguous()):
+        raise ValueError("%s must be a contiguous float64 GPU tensor with %d entries" % (name, n))
+    return x
+
+
+def _i32(x, n, name):
+    if not (x.is_cuda and x.dtype == torch.int32 and x.numel() == n and x.is_contiguous()):
+        raise ValueError("%s must be a contiguous int32 GPU tensor with %d entries" % (name, n))
+    return x
+
+
+def matfree_apply(nx, ny, h, k, u, out=None, stream=None):
+    """v = A u with the 5-point Sommerfeld Helmholtz stencil, no stored matrix."""
+    n = nx * ny
+    _f64(k, n, "k")
+    _c128(u, n, "u")
+    v = torch.empty_like(u) if out is None else _c128(out, n, "out")
+    _check(_lib.hm_matfree_apply(int(nx), int(ny), float(h), _ptr(k), _ptr(u), _ptr(v),
+                                 _stream(stream)))
+    return v
+
+
+def csr_assemble(nx, ny, h, k, stream=None):
+    """(row_ptr, col_idx, vals) of the same operator, five entries per row."""
+    n = nx * ny
+    _f64(k, n, "k")
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=k.device)
+    col_idx = torch.empty(5 * n, dtype=torch.int32, device=k.device)
+    vals = torch.empty(5 * n, dtype=torch.complex128, device=k.device)
+    _check(_lib.hm_csr_assemble(int(nx), int(ny), float(h), _ptr(k), _ptr(row_ptr),
+                                _ptr(col_idx), _ptr(vals), _stream(stream)))
+    return row_ptr, col_idx, vals
+
+
+def csr_spmv(row_ptr, col_idx, vals, x, out=None, stream=None):
+    """y = A x for a CSR matrix with int32 indices and complex128 values."""
+    nrows = row_ptr.numel() - 1
+    _i32(row_ptr, nrows + 1, "row_ptr")
+    nnz = col_idx.numel()
+    _i32(col_idx, nnz, "col_idx")
+    _c128(vals, nnz, "vals")
+    _c128(x, x.numel(), "x")
+    y = torch.empty(nrows, dtype=torch.complex128, device=x.device) if out is None \
+        else _c128(out, nrows, "out")
+    _check(_lib.hm_csr_spmv(int(nrows), _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(x),
+                            _ptr(y), _stream(stream)))
+    return y
 
 
 def destroy_problem(prob):

@@ -771,9 +771,68 @@ __global__ void __launch_bounds__(NT) k_max_final(const c128* __restrict__ parti
   out[0] = mk(m, 0.0);
 }
 
+// CSR of the five-point operator: row p = y*nx + x, entries at rowptr[p] = 5p.
+// A neighbour outside the grid is the Sommerfeld ghost mirror + 2iHk u_centre:
+// its coupling moves onto the mirrored inside neighbour (doubling it) and the
+// 2iHk part is already in the diagonal; the freed slot keeps a zero.
+__global__ void __launch_bounds__(NT) k_csr5_assemble(OpDesc<double> d, const double* __restrict__ k,
+                                                      int* __restrict__ rowptr,
+                                                      int* __restrict__ colidx,
+                                                      c128* __restrict__ vals) {
+  const size_t p = (size_t)blockIdx.x * NT + threadIdx.x;
+  const size_t n = (size_t)d.nx * d.ny;
+  if (p > n) return;
+  rowptr[p] = (int)(5 * p);
+  if (p == n) return;
+  const int x = (int)(p % d.nx), y = (int)(p / d.nx);
+  const double off = -d.scale * d.inv_H2;
+  // slots: centre, west, east, south, north
+  const int col[5] = {(int)p, (int)p - 1, (int)p + 1, (int)p - d.nx, (int)p + d.nx};
+  const bool in[5] = {true, x > 0, x < d.nx - 1, y > 0, y < d.ny - 1};
+  const int mirror[5] = {0, 2, 1, 4, 3};
+  double c[5] = {0, 0, 0, 0, 0};
+  for (int q = 1; q < 5; ++q) c[in[q] ? q : mirror[q]] += off;
+  const size_t base = 5 * p;
+  vals[base] = five_point_diag(d, k, x, y);
+  colidx[base] = col[0];
+  for (int q = 1; q < 5; ++q) {
+    colidx[base + q] = in[q] ? col[q] : (int)p;
+    vals[base + q] = mk(c[q], 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_csr_spmv(int nrows, const int* __restrict__ rowptr,
+                                                 const int* __restrict__ colidx,
+                                                 const c128* __restrict__ vals,
+                                                 const c128* __restrict__ x, c128* __restrict__ y) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  if (r >= nrows) return;
+  double re = 0, im = 0;
+  for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) {
+    const c128 a = vals[q];
+    const c128 v = x[colidx[q]];
+    re += a.re * v.re - a.im * v.im;
+    im += a.re * v.im + a.im * v.re;
+  }
+  y[r] = mk(re, im);
+}
+
 }  // namespace
 
 // ============================ launchers ======================================
+
+hipError_t launch_csr5_assemble(const OpDesc<double>& d, const double* k, int* rowptr, int* colidx,
+                                c128* vals, hipStream_t s) {
+  const size_t n = (size_t)d.nx * d.ny;
+  k_csr5_assemble<<<blocks1d(n + 1), NT, 0, s>>>(d, k, rowptr, colidx, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_spmv(int nrows, const int* rowptr, const int* colidx, const c128* vals,
+                           const c128* x, c128* y, hipStream_t s) {
+  k_csr_spmv<<<blocks1d((size_t)nrows), NT, 0, s>>>(nrows, rowptr, colidx, vals, x, y);
+  return hipGetLastError();
+}
 
 // blocks of the tiled wide stencil: 8 equal ranges of tiles (one per XCD)
 static unsigned wide_blocks(int nx, int ny) {

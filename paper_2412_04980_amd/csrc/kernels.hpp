@@ -98,6 +98,17 @@ hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, 
 // out = unit vectors: out[j*n + i] = (i == j)
 hipError_t launch_identity(c128* out, int n, hipStream_t s);
 
+// ---- stored-matrix comparison (CSR) ---------------------------------------
+// CSR of the five-point operator d (R = 1) with exactly five entries per row in
+// the order centre, west, east, south, north; a neighbour outside the grid
+// contributes through its mirror (Sommerfeld ghost), its own slot holds a zero
+// pointing at the row itself.
+hipError_t launch_csr5_assemble(const OpDesc<double>& d, const double* k, int* rowptr, int* colidx,
+                                c128* vals, hipStream_t s);
+// y = A x for a CSR matrix (one thread per row)
+hipError_t launch_csr_spmv(int nrows, const int* rowptr, const int* colidx, const c128* vals,
+                           const c128* x, c128* y, hipStream_t s);
+
 // ---- reductions (double accumulation; results on the device) --------------
 struct RedBuf {
   c128* partials;   // >= kMaxChunks * (max dots) entries

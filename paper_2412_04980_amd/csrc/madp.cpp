@@ -1,6 +1,6 @@
 // Host orchestration of the MADP preconditioner and FGMRES on the GPU.
 //
-// The paper's method (Algorithm 1 with the MADP configuration of Sec. 4.3):
+// The paper's method (Algorithm 1 with the MADP configuration of Sec. 4.4):
 //   Prec_l(v): v_hat = Z^T v; v_t ~ E^-1 v_hat (level-2 FGMRES to tolerance
 //   0.3, or one FGMRES step with Krylov CSLP on the coarsest level);
 //   t = Z v_t; r~ = v - A t; r ~ M^-1 r~ (one V-cycle on levels 1-2, GMRES
@@ -579,17 +579,20 @@ static int fgmres_level(hm_problem* p, int c, const cx<T>* b, cx<T>* x, double t
   return steps;
 }
 
-// Coarse problem E_c x = b of level c (Algorithm 1, lines "restriction" to
-// "interpolation"): level-2 FGMRES to tol_level2, one step elsewhere.
+// Levels 2..tol_levels above the coarsest iterate to tol_level2; every other
+// coarse level takes coarse_steps FGMRES steps (the cycle type, Sec. 3.2).
+static bool tol_level(const hm_config& c, int L, int l) {
+  return l >= 2 && l < L && l <= c.tol_levels;
+}
+
+// Coarse problem E_c x = b of level c (Algorithm 1, restriction to
+// interpolation).  Only level-2 solves are recorded / replayed (kind 0).
 template <typename T>
 static void coarse_solve(hm_problem* p, int c, const cx<T>* b, cx<T>* x) {
-  if (c == p->L) {
-    fgmres_level<T>(p, c, b, x, -1.0, 1, -1);
-  } else if (c == 2) {
-    fgmres_level<T>(p, c, b, x, p->cfg.tol_level2, p->cfg.level2_maxit, K_LEVEL2);
-  } else {
-    fgmres_level<T>(p, c, b, x, -1.0, 1, -1);
-  }
+  if (tol_level(p->cfg, p->L, c))
+    fgmres_level<T>(p, c, b, x, p->cfg.tol_level2, p->cfg.level2_maxit, c == 2 ? K_LEVEL2 : -1);
+  else
+    fgmres_level<T>(p, c, b, x, -1.0, p->cfg.coarse_steps, -1);
 }
 
 template <typename T, typename Tn>
@@ -735,6 +738,8 @@ static bool validate(const hm_config* c, std::string* why) {
   if (c->mg_nu_pre < 1 || c->mg_nu_post < 0) return bad("smoothing steps");
   if (!(c->tol_outer > 0) || !(c->tol_level2 > 0) || !(c->tol_cslp > 0) || !(c->maxit_coef > 0))
     return bad("tolerances");
+  if (c->coarse_steps < 1 || c->coarse_steps > 16) return bad("coarse_steps must be in [1, 16]");
+  if (c->tol_levels < 1 || c->tol_levels > 6) return bad("tol_levels must be in [1, 6]");
   for (int r : c->reserved)
     if (r != 0) return bad("reserved fields must be zero");
   return true;
@@ -775,7 +780,7 @@ static void plan(hm_problem* p, Carver& cv) {
       set_wide(D.M32, nx, ny, c.h, l, sig_m);
     }
     if (l >= 2) {
-      D.fg.cap = (l == 2 && p->L > 2) ? c.level2_maxit : 1;
+      D.fg.cap = tol_level(c, p->L, l) ? c.level2_maxit : c.coarse_steps;
       D.fg.N = D.N;
       D.fg.V = cv.take<char>((size_t)(D.fg.cap + 1) * D.N * es);
       D.fg.X = cv.take<char>((size_t)D.fg.cap * D.N * es);
@@ -1125,6 +1130,7 @@ void hm_default_config(hm_config* c, int nx, int ny, double h) {
   c->outer_restart = 30; c->outer_maxit = 300; c->level2_maxit = 100;
   c->mg_nu_pre = 1; c->mg_nu_post = 1;
   c->precision = HM_FP64;
+  c->coarse_steps = 1; c->tol_levels = 2;
 }
 
 size_t hm_workspace_bytes(const hm_config* cfg) {
@@ -1284,6 +1290,58 @@ hm_status hm_destroy_problem(hm_problem* p) {
   if (p->host_coef) (void)hipHostFree(p->host_coef);
   delete p;
   return HM_OK;
+}
+
+static bool matvec_grid_ok(int nx, int ny, double h) {
+  if (nx < 3 || ny < 3 || !(h > 0) || !std::isfinite(h)) {
+    g_last_error = "matvec: need nx, ny >= 3 and h > 0";
+    return false;
+  }
+  if ((long long)nx * ny * 5 > 2147483647LL) {
+    g_last_error = "matvec: 5*nx*ny exceeds the 32-bit index range";
+    return false;
+  }
+  return true;
+}
+
+hm_status hm_matfree_apply(int nx, int ny, double h, const double* k_dev, const void* u_dev,
+                           void* v_dev, void* stream) {
+  if (!matvec_grid_ok(nx, ny, h)) return HM_ERR_ARG;
+  if (!k_dev || !u_dev || !v_dev) return HM_ERR_ARG;
+  return guard([&]() -> hm_status {
+    OpDesc<double> d;
+    set_five_point(d, nx, ny, h, 1.0, cd(1.0, 0.0));
+    HM_CHECK(launch_stencil(d, ST_APPLY, (const c128*)u_dev, k_dev, (const c128*)nullptr,
+                            (c128*)v_dev, 0.0, (hipStream_t)stream));
+    return HM_OK;
+  });
+}
+
+hm_status hm_csr_assemble(int nx, int ny, double h, const double* k_dev, int* row_ptr_dev,
+                          int* col_idx_dev, void* vals_dev, void* stream) {
+  if (!matvec_grid_ok(nx, ny, h)) return HM_ERR_ARG;
+  if (!k_dev || !row_ptr_dev || !col_idx_dev || !vals_dev) return HM_ERR_ARG;
+  return guard([&]() -> hm_status {
+    OpDesc<double> d;
+    set_five_point(d, nx, ny, h, 1.0, cd(1.0, 0.0));
+    HM_CHECK(launch_csr5_assemble(d, k_dev, row_ptr_dev, col_idx_dev, (c128*)vals_dev,
+                                  (hipStream_t)stream));
+    return HM_OK;
+  });
+}
+
+hm_status hm_csr_spmv(int nrows, const int* row_ptr_dev, const int* col_idx_dev,
+                      const void* vals_dev, const void* x_dev, void* y_dev, void* stream) {
+  if (nrows < 0 || !row_ptr_dev || !col_idx_dev || !vals_dev || !x_dev || !y_dev) {
+    g_last_error = "csr_spmv: bad arguments";
+    return HM_ERR_ARG;
+  }
+  if (nrows == 0) return HM_OK;
+  return guard([&]() -> hm_status {
+    HM_CHECK(launch_csr_spmv(nrows, row_ptr_dev, col_idx_dev, (const c128*)vals_dev,
+                             (const c128*)x_dev, (c128*)y_dev, (hipStream_t)stream));
+    return HM_OK;
+  });
 }
 
 hm_status hm_set_timing(hm_problem* p, unsigned mask, int every) {

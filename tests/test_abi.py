@@ -44,7 +44,9 @@ def test_workspace_bytes_validation():
     import paper_2412_04980_amd as hm
     assert hm.workspace_bytes(hm.default_config(129, 129, 1 / 128)) > 0
     for bad in (dict(nx=130), dict(levels=1), dict(levels=7), dict(h=-1.0), dict(bc=1),
-                dict(precision=5), dict(outer_restart=0), dict(tol_outer=0.0)):
+                dict(precision=5), dict(outer_restart=0), dict(tol_outer=0.0),
+                dict(coarse_steps=0), dict(coarse_steps=17), dict(tol_levels=0),
+                dict(tol_levels=7)):
         c = hm.default_config(129, 129, 1 / 128)
         for key, val in bad.items():
             setattr(c, key, val)
@@ -66,7 +68,33 @@ def test_workspace_grows_with_grid_and_mixed_is_smaller():
     assert mix < f64
 
 
+def test_variant_fields_size_the_coarse_workspaces():
+    """A W-cycle (coarse_steps = 2) needs two basis vectors on the coarse levels,
+    a tolerance on level 3 (tol_levels = 3) the level2_maxit cap there."""
+    import paper_2412_04980_amd as hm
+    c = hm.default_config(129, 129, 1 / 128, levels=4)
+    assert (c.coarse_steps, c.tol_levels) == (1, 2)
+    base = hm.workspace_bytes(c)
+    w = hm.workspace_bytes(hm.default_config(129, 129, 1 / 128, levels=4, coarse_steps=2))
+    t = hm.workspace_bytes(hm.default_config(129, 129, 1 / 128, levels=4, tol_levels=3))
+    assert base < w < t
+
+
 def test_status_strings():
     import paper_2412_04980_amd as hm
     assert hm.status_string(0) == "ok"
     assert hm.status_string(-2) == "workspace too small"
+
+
+def test_matvec_entry_points_reject_bad_sizes_on_the_host():
+    """The matvec entry points check sizes before any device work."""
+    import paper_2412_04980_amd as hm
+    lib = hm._lib
+    nul = ctypes.c_void_p(0)
+    for nx, ny, h in ((2, 5, 0.1), (5, 2, 0.1), (5, 5, 0.0), (30000, 30000, 1e-4)):
+        assert lib.hm_matfree_apply(nx, ny, h, nul, nul, nul, nul) == hm.HM_ERR_ARG
+        assert lib.hm_csr_assemble(nx, ny, h, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
+    # valid sizes, missing pointers
+    assert lib.hm_matfree_apply(5, 5, 0.1, nul, nul, nul, nul) == hm.HM_ERR_ARG
+    assert lib.hm_csr_spmv(-1, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
+    assert lib.hm_csr_spmv(4, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG

@@ -123,6 +123,6 @@ def test_config0_iteration_count_in_paper_range():
     m = MADP(p.nx, p.ny, p.h, p.k, levels=3)
     u, info = m.solve(p.rhs())
     assert info["rel_res_true"] <= 1e-6
-    # the paper's MADP runs take 10-19 outer steps (its tables of Sec. 4.3);
+    # the paper's MADP runs take 10-19 outer steps (its tables of Sec. 4.4 and 4.5);
     # a trend check, not an exact pin
     assert 5 <= info["outer_iters"] <= 20
