@@ -62,6 +62,10 @@ def parse():
                     help="matrix-free versus CSR matvec of the finest operator on grids "
                          "17^2 .. 16385^2 (100 consecutive products per form and size)")
     ap.add_argument("--matvec-max-side", type=int, default=16385)
+    ap.add_argument("--complexity", action="store_true",
+                    help="five-level MADP on the wedge stand-in at kh = 0.1745, grids "
+                         "145x241 (10 Hz) .. 4609x7681 (320 Hz), FP64 and mixed")
+    ap.add_argument("--complexity-max-nx", type=int, default=4609)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size, to calibrate hardware byte counters)")
@@ -272,6 +276,58 @@ def matvec_bench(args, reps=100):
     print(json.dumps(out), flush=True)
 
 
+# Five-level wedge solves at kh = 0.1745 (the complexity study of Sec. 4.5):
+# (nx, frequency); the domain is 600 m x 1000 m, so ny = (nx - 1) * 5 / 3 + 1.
+COMPLEXITY_SIZES = [(145, 10.0), (289, 20.0), (577, 40.0), (1153, 80.0), (2305, 160.0),
+                    (4609, 320.0)]
+
+
+def complexity_bench(args):
+    import torch
+
+    import paper_2412_04980_amd as hm
+    import workloads
+    dev = torch.device("cuda:0")
+    rows = []
+    for nx, f in COMPLEXITY_SIZES:
+        if nx > args.complexity_max_nx:
+            break
+        p = workloads.wedge(f=f, h=600.0 / (nx - 1))
+        k = torch.from_numpy(p.k).to(dev)
+        b = torch.from_numpy(p.rhs()).to(dev)
+        row = {"nx": p.nx, "ny": p.ny, "unknowns": p.nx * p.ny, "f_hz": f}
+        for label, prec in (("fp64", hm.HM_FP64), ("mixed", hm.HM_MIXED_FP32)):
+            prob = hm.create_problem(hm.default_config(p.nx, p.ny, p.h, levels=5, precision=prec),
+                                     k)
+            try:
+                u = torch.empty_like(b)
+                hm.fgmres_solve(prob, b, out=u)           # warm-up (graph capture, caches)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = hm.fgmres_solve(prob, b, out=u)
+                torch.cuda.synchronize()
+                sec = time.perf_counter() - t0
+            finally:
+                prob.close()
+            row[label] = {"seconds": sec, "outer_iters": info["outer_iters"],
+                          "level2_iters_total": info["level2_iters_total"],
+                          "rel_res_true": info["rel_res_true"]}
+            log("%dx%d f=%g %s: %.3f s, outer %d, level-2 %d, rel_res %.2e" % (
+                p.nx, p.ny, f, label, sec, info["outer_iters"], info["level2_iters_total"],
+                info["rel_res_true"]))
+        rows.append(row)
+        del k, b, u
+        torch.cuda.empty_cache()
+    big = rows[-1]
+    out = {"metric": "five-level MADP solve time, wedge stand-in at kh = 0.1745",
+           "value": big["fp64"]["seconds"], "unit": "s per solve (largest grid, FP64)",
+           "n_gpus": 1, "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "wedge stand-in, 5 levels, kh = 0.1745, %dx%d .. %dx%d" % (
+               rows[0]["nx"], rows[0]["ny"], big["nx"], big["ny"])},
+           "table": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -290,6 +346,9 @@ def main():
         return
     if args.matvec:
         matvec_bench(args)
+        return
+    if args.complexity:
+        complexity_bench(args)
         return
     dev = torch.device("cuda:0")
     if args.copy_calibration:

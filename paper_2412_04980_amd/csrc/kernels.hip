@@ -128,6 +128,26 @@ __device__ __forceinline__ cx<T> wide_diag(const OpDesc<T>& d, const T* __restri
   return mk(re, im);
 }
 
+// XCD-aware order of BX x BY tiles for a 1-D grid of xcd_blocks() blocks.
+// Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
+// XCD j takes the j-th contiguous range of tiles in row-major order, so the
+// tiles above and below a tile run on the same XCD close in time and the halo
+// rows they share are read from that XCD's L2 rather than again from HBM.
+__device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& tx, int& ty) {
+  const int nt = ntx * nty;
+  const int per = (nt + 7) / 8;
+  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= nt) return false;
+  ty = tile / ntx;
+  tx = tile - ty * ntx;
+  return true;
+}
+
+inline unsigned xcd_blocks(int nx, int ny) {
+  const size_t nt = (size_t)((nx + BX - 1) / BX) * ((ny + BY - 1) / BY);
+  return (unsigned)(8 * ((nt + 7) / 8));
+}
+
 template <typename T, int R>
 __device__ __forceinline__ bool is_boundary(const OpDesc<T>& d, int x, int y) {
   return x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1;
@@ -142,8 +162,10 @@ __global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __rest
                                                 cx<T>* __restrict__ out, T omega,
                                                 const c128* __restrict__ scal,
                                                 cx<T>* __restrict__ vout) {
-  const int x = blockIdx.x * BX + threadIdx.x;
-  const int y = blockIdx.y * BY + threadIdx.y;
+  int tx, ty;
+  if (!xcd_tile((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, tx, ty)) return;
+  const int x = tx * BX + threadIdx.x;
+  const int y = ty * BY + threadIdx.y;
   if (x >= d.nx || y >= d.ny) return;
   const size_t p = (size_t)y * d.nx + x;
   cx<T> au;
@@ -801,20 +823,49 @@ __global__ void __launch_bounds__(NT) k_csr5_assemble(OpDesc<double> d, const do
   }
 }
 
+// CSR SpMV in the "CSR-stream" form: when the NT rows of a block hold at most
+// kCsrStage entries, the block forms the products vals[q] * x[col[q]] for its
+// contiguous entry range with coalesced loads into LDS, and each thread then
+// sums its row from LDS; a block with more entries falls back to one thread
+// per row reading its entries directly.
+constexpr int kCsrStage = 2048;
+
 __global__ void __launch_bounds__(NT) k_csr_spmv(int nrows, const int* __restrict__ rowptr,
                                                  const int* __restrict__ colidx,
                                                  const c128* __restrict__ vals,
                                                  const c128* __restrict__ x, c128* __restrict__ y) {
-  const int r = blockIdx.x * NT + threadIdx.x;
-  if (r >= nrows) return;
-  double re = 0, im = 0;
-  for (int q = rowptr[r]; q < rowptr[r + 1]; ++q) {
-    const c128 a = vals[q];
-    const c128 v = x[colidx[q]];
-    re += a.re * v.re - a.im * v.im;
-    im += a.re * v.im + a.im * v.re;
+  __shared__ c128 prod[kCsrStage];
+  const int r0 = blockIdx.x * NT;
+  const int r1 = min(r0 + NT, nrows);
+  const int r = r0 + (int)threadIdx.x;
+  const int q0 = rowptr[r0], q1 = rowptr[r1];
+  int a = 0, b = 0;
+  if (r < nrows) {
+    a = rowptr[r];
+    b = rowptr[r + 1];
   }
-  y[r] = mk(re, im);
+  double re = 0, im = 0;
+  if (q1 - q0 <= kCsrStage) {          // uniform over the block
+#pragma unroll 4
+    for (int i = threadIdx.x; i < q1 - q0; i += NT) {
+      const c128 v = vals[q0 + i];
+      const c128 xv = x[colidx[q0 + i]];
+      prod[i] = mk(v.re * xv.re - v.im * xv.im, v.re * xv.im + v.im * xv.re);
+    }
+    __syncthreads();
+    for (int q = a; q < b; ++q) {
+      re += prod[q - q0].re;
+      im += prod[q - q0].im;
+    }
+  } else {
+    for (int q = a; q < b; ++q) {
+      const c128 v = vals[q];
+      const c128 xv = x[colidx[q]];
+      re += v.re * xv.re - v.im * xv.im;
+      im += v.re * xv.im + v.im * xv.re;
+    }
+  }
+  if (r < nrows) y[r] = mk(re, im);
 }
 
 }  // namespace
@@ -843,7 +894,7 @@ static unsigned wide_blocks(int nx, int ny) {
 template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
                           cx<T>* out, T omega, hipStream_t s) {
-  const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
+  const dim3 g(xcd_blocks(d.nx, d.ny)), blk(BX, BY);
   const dim3 gw(wide_blocks(d.nx, d.ny));
 #define HM_ST(R, M)                                                                           \
   if constexpr (R == 1) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega, nullptr,    \
@@ -865,7 +916,7 @@ hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T*
 template <typename T>
 hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k, const c128* scal,
                                  cx<T>* vout, cx<T>* out, hipStream_t s) {
-  const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
+  const dim3 g(xcd_blocks(d.nx, d.ny)), blk(BX, BY);
   const dim3 gw(wide_blocks(d.nx, d.ny));
   if (d.R == 1)
     k_stencil<T, 1, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);

@@ -172,3 +172,28 @@ def test_config3_layered_mixed_solve_true_residual():
     assert info["status"] == hm.HM_OK
     assert true_residual(p, host(u)) <= 1e-6
     assert info["mg_coarse_iters_total"] > 0
+
+
+@pytest.mark.parametrize("f,nx", [(10.0, 145), (20.0, 289)])
+def test_wedge_five_levels_vs_oracle(f, nx):
+    """Five-level MADP on the wedge stand-in at kh = 0.1745 (the setting of the
+    complexity study, Sec. 4.5): both sides solve; the oracle's counts, 9 (2 per
+    outer step) and 10 (about 3), sit beside the paper's 10 (2) and 11 (3)."""
+    from oracle.madp import MADP
+    p = workloads.wedge(f=f, h=600.0 / (nx - 1))
+    o = MADP(p.nx, p.ny, p.h, p.k, levels=5)
+    u_ref, info_ref = o.solve(p.rhs())
+    cfg = hm.default_config(p.nx, p.ny, p.h, levels=5)
+    prob = hm.create_problem(cfg, gpu(p.k))
+    try:
+        u, info = hm.fgmres_solve(prob, gpu(p.rhs()))
+    finally:
+        prob.close()
+    err = np.linalg.norm(host(u) - u_ref) / np.linalg.norm(u_ref)
+    print("wedge 5-level %dx%d outer gpu=%d oracle=%d level2 gpu=%d oracle=%d err=%.2e" % (
+        p.nx, p.ny, info["outer_iters"], info_ref["outer_iters"], info["level2_iters_total"],
+        info_ref["level2_iters_total"], err))
+    assert info["status"] == hm.HM_OK
+    assert true_residual(p, host(u)) <= 1e-6
+    assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+    assert err <= 1e-5
