@@ -66,6 +66,9 @@ def parse():
                     help="five-level MADP on the wedge stand-in at kh = 0.1745, grids "
                          "145x241 (10 Hz) .. 4609x7681 (320 Hz), FP64 and mixed")
     ap.add_argument("--complexity-max-nx", type=int, default=4609)
+    ap.add_argument("--variants", action="store_true",
+                    help="the method variants (MADP-v3, W-cycle, fixed steps, tolerance on "
+                         "level 3, 4 levels) on the benchmark workload, FP64")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size, to calibrate hardware byte counters)")
@@ -328,6 +331,55 @@ def complexity_bench(args):
     print(json.dumps(out), flush=True)
 
 
+VARIANTS = [("MADP", {}),
+            ("MADP-v3 (level-2 tol 0.1)", {"tol_level2": 0.1}),
+            ("W-cycle (m = 2 on coarse levels)", {"coarse_steps": 2}),
+            ("fixed m = 1 on every coarse level", {"tol_levels": 1}),
+            ("4 levels", {"levels": 4}),
+            ("4 levels, W-cycle", {"levels": 4, "coarse_steps": 2}),
+            ("4 levels, tol 0.3 on levels 2-3", {"levels": 4, "tol_levels": 3})]
+
+
+def variants_bench(args):
+    import torch
+
+    import paper_2412_04980_amd as hm
+    import workloads
+    dev = torch.device("cuda:0")
+    problem = workloads.config(args.config)
+    k = torch.from_numpy(problem.k).to(dev)
+    b = torch.from_numpy(problem.rhs(0)).to(dev)
+    rows = []
+    for name, kw in VARIANTS:
+        cfg = hm.default_config(problem.nx, problem.ny, problem.h, **kw)
+        prob = hm.create_problem(cfg, k)
+        try:
+            u = torch.empty_like(b)
+            hm.fgmres_solve(prob, b, out=u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = hm.fgmres_solve(prob, b, out=u)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+        finally:
+            prob.close()
+        torch.cuda.empty_cache()
+        rows.append({"variant": name, "settings": kw, "seconds": sec,
+                     "outer_iters": info["outer_iters"],
+                     "level2_iters_total": info["level2_iters_total"],
+                     "cslp_iters_total": info["cslp_iters_total"],
+                     "rel_res_true": info["rel_res_true"]})
+        log("%-36s %.3f s  outer %d  level-2 %d  Krylov CSLP %d  rel_res %.2e" % (
+            name, sec, info["outer_iters"], info["level2_iters_total"], info["cslp_iters_total"],
+            info["rel_res_true"]))
+    out = {"metric": "solve time per method variant", "value": rows[0]["seconds"],
+           "unit": "s per solve (MADP)", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": problem.name, "nx": problem.nx, "ny": problem.ny},
+           "table": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -349,6 +401,9 @@ def main():
         return
     if args.complexity:
         complexity_bench(args)
+        return
+    if args.variants:
+        variants_bench(args)
         return
     dev = torch.device("cuda:0")
     if args.copy_calibration:

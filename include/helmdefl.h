@@ -54,7 +54,14 @@ typedef enum {
   HM_ERR_STATE = -4       /* call not valid in the problem's current state        */
 } hm_status;
 
-typedef enum { HM_BC_SOMMERFELD = 0 } hm_bc;   /* all four sides (Sec. 2.1) */
+/* Boundary condition on all four sides (Sec. 2.1).  HM_BC_DIRICHLET is the
+ * homogeneous condition u = 0: boundary nodes keep their place in the grid with
+ * decoupled rows d_b u_b (d_b = s_l 4 / h_l^2), no other row reads them, the
+ * coarse-level stencils use the ghost value 2 u_b - u_m = -u_m with ghost
+ * wavenumber 2 k_b - k_m one step outside (eq. ghost_Dirichlt, Sec. 3.3), and
+ * every grid transfer is masked to the interior.  Right-hand sides must vanish
+ * on the boundary; the solution then does too. */
+typedef enum { HM_BC_SOMMERFELD = 0, HM_BC_DIRICHLET = 1 } hm_bc;
 
 typedef enum {
   HM_FP64 = 0,        /* every step in complex128                                     */

@@ -35,6 +35,8 @@ that has no tolerance (1: V-cycle, the MADP setting; 2: W-cycle);
 1: every coarse level takes m steps; 3 or 4: the tolerance also on the third
 and fourth levels, the variant of the per-level tolerance table of Sec. 4.5).
 The coarsest level always takes m steps.  MADP-v3 is tol_level2 = 0.1.
+`bc` selects Sommerfeld (default) or homogeneous Dirichlet boundaries on every
+level (reading R24, oracle.operators).
 """
 import time
 
@@ -48,15 +50,15 @@ from .multigrid import VCycle, krylov_maxit
 
 
 class Level:
-    def __init__(self, l, nx, ny, h, k, beta):
+    def __init__(self, l, nx, ny, h, k, beta, bc=op.SOMMERFELD):
         self.l, self.nx, self.ny = l, nx, ny
         self.N = nx * ny
         self.h_l = h * 2 ** (l - 1)
         self.s_l = float(stencils.level_scale(l))
         self.k = k
         sigma = complex(beta[0], beta[1])
-        self.A = op.level_operator(nx, ny, h, l, k, 1.0)     # A_1 or E_l
-        self.M = op.level_operator(nx, ny, h, l, k, sigma)   # CSLP of the level
+        self.A = op.level_operator(nx, ny, h, l, k, 1.0, bc=bc)     # A_1 or E_l
+        self.M = op.level_operator(nx, ny, h, l, k, sigma, bc=bc)   # CSLP of the level
         self.Z = None                                         # to level l+1
 
 
@@ -64,7 +66,7 @@ class MADP:
     def __init__(self, nx, ny, h, k, levels=3, beta=(1.0, 0.5), tol_level2=0.3,
                  tol_cslp=0.1, maxit_coef=6.0, level2_maxit=100, nu_pre=1, nu_post=1,
                  log=None, galerkin_coarse=False, cslp_override=None, coarse_steps=1,
-                 tol_levels=2):
+                 tol_levels=2, bc=op.SOMMERFELD):
         assert levels >= 2 and coarse_steps >= 1 and tol_levels >= 1
         f = 2 ** (levels - 1)
         if (nx - 1) % f or (ny - 1) % f:
@@ -82,10 +84,10 @@ class MADP:
         self.levels = [None]                                  # 1-based
         k = np.asarray(k, dtype=np.float64).ravel()
         for l in range(1, levels + 1):
-            self.levels.append(Level(l, nx, ny, h, k, beta))
+            self.levels.append(Level(l, nx, ny, h, k, beta, bc))
             if l < levels:
                 nxc, nyc = op.coarse_size(nx, 2), op.coarse_size(ny, 2)
-                self.levels[l].Z = op.deflation_z(nxc, nyc)
+                self.levels[l].Z = op.deflation_z(nxc, nyc, bc)
                 k = op.inject(k, nx, ny)
                 nx, ny = nxc, nyc
         if galerkin_coarse:
@@ -98,7 +100,7 @@ class MADP:
             lev = self.levels[l]
             self.mg[l] = VCycle(lev.nx, lev.ny, lev.h_l, lev.k, lev.M, sigma, lev.s_l,
                                 nu_pre=nu_pre, nu_post=nu_post, tol_cslp=tol_cslp,
-                                maxit_coef=maxit_coef, log=self.log)
+                                maxit_coef=maxit_coef, log=self.log, bc=bc)
         self.setup_seconds = time.perf_counter() - t0
 
     # -- CSLP^-1 on level l ------------------------------------------------

@@ -67,7 +67,8 @@ class VCycle:
     """
 
     def __init__(self, nx, ny, H0, k, top_operator, sigma, scale, kmax=None,
-                 nu_pre=1, nu_post=1, tol_cslp=0.1, maxit_coef=6.0, log=None):
+                 nu_pre=1, nu_post=1, tol_cslp=0.1, maxit_coef=6.0, log=None,
+                 bc=op.SOMMERFELD):
         kmax = float(np.max(k)) if kmax is None else kmax
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.tol_cslp, self.maxit_coef = tol_cslp, maxit_coef
@@ -78,9 +79,9 @@ class VCycle:
             nxc, nyc = op.coarse_size(nx, 2), op.coarse_size(ny, 2)
             kc = op.inject(k, nx, ny)
             Hc = 2 * self.levels[-1].H
-            Mc = op.five_point(nxc, nyc, Hc, kc, sigma, scale)
-            self.R.append(op.full_weighting(nx, ny))
-            self.P.append(op.bilinear_prolongation(nxc, nyc))
+            Mc = op.five_point(nxc, nyc, Hc, kc, sigma, scale, bc=bc)
+            self.R.append(op.full_weighting(nx, ny, bc=bc))
+            self.P.append(op.bilinear_prolongation(nxc, nyc, bc=bc))
             self.levels.append(MGLevel(nxc, nyc, Hc, kc, Mc, smoothing_weight(kmax, Hc)))
             nx, ny, k = nxc, nyc, kc
         last = self.levels[-1]

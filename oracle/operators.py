@@ -24,6 +24,16 @@ Readings of the paper this module fixes:
   * Multigrid transfers: full weighting (1/16)[1 2 1; 2 4 2; 1 2 1] with
     out-of-grid fine values zero, bilinear interpolation, wavenumber by
     injection (reading R10).
+
+Dirichlet boundaries (Sec. 2.1, eq. ghost_Dirichlt; Sec. 3.3 boundary paragraph),
+reading R24: homogeneous, u = 0 on every boundary node.  The boundary nodes stay
+in the grid but are decoupled: a boundary row is d_b u_b with d_b = s_l 4 / h_l^2,
+and no other row reads a boundary value (it is zero).  A stencil point one step
+outside the grid in exactly one direction is the ghost 2 u_b - u_m = -u_m with
+wavenumber k_g = 2 k_b - k_m (b the boundary node, m its interior neighbour);
+points further out are zero.  Every transfer is masked to the interior:
+Z_D = D_f Z D_c, R_D = D_c R D_f, P_D = D_f P D_c with D the 0/1 interior masks,
+so vectors that vanish on the boundary keep vanishing at every level.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -31,6 +41,20 @@ import scipy.sparse as sp
 from . import stencils
 
 _NEIGHBOURS = ((-1, 0), (1, 0), (0, -1), (0, 1))
+
+
+SOMMERFELD, DIRICHLET = "sommerfeld", "dirichlet"
+
+
+def interior_mask(nx, ny):
+    """1.0 on nodes off the boundary, 0.0 on boundary nodes (row-major)."""
+    m = np.zeros((ny, nx))
+    m[1:-1, 1:-1] = 1.0
+    return m.ravel()
+
+
+def _mask_rows_cols(M, rows_mask, cols_mask):
+    return (sp.diags(rows_mask) @ M @ sp.diags(cols_mask)).tocsr()
 
 
 def coarse_size(n, factor):
@@ -45,14 +69,16 @@ def inject(field, nx, ny):
     return np.ascontiguousarray(f[::2, ::2]).ravel()
 
 
-def five_point(nx, ny, H, k, sigma, scale=1.0):
+def five_point(nx, ny, H, k, sigma, scale=1.0, bc=SOMMERFELD):
     """scale * ( H^-2 (4u - sum of 4 neighbours) - sigma k^2 u ) with a Sommerfeld
     ghost point behind every boundary side (Sec. 2.1, eqs. helm operator h and
     ghost_sommerfeld; with sigma = beta1 + i beta2 it is the CSLP, Sec. 3.1).
 
     `k` is the nodal wavenumber (not squared).  Rows of corner nodes receive a
-    ghost from both directions.
+    ghost from both directions.  bc = "dirichlet": reading R24 (module docstring).
     """
+    if bc == DIRICHLET:
+        return _five_point_dirichlet(nx, ny, H, k, sigma, scale)
     k = np.asarray(k, dtype=np.float64).reshape(ny, nx)
     jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     idx = jj * nx + ii
@@ -76,15 +102,81 @@ def five_point(nx, ny, H, k, sigma, scale=1.0):
                          shape=(N, N)).tocsr()
 
 
-def wide_stencil(nx, ny, h, level, k, sigma):
+def _five_point_dirichlet(nx, ny, H, k, sigma, scale):
+    k = np.asarray(k, dtype=np.float64).ravel()
+    m = interior_mask(nx, ny).astype(bool)
+    N = nx * ny
+    rows, cols, vals = [], [], []
+    idx = np.arange(N)
+    ii, jj = idx % nx, idx // nx
+    # interior rows: centre and the interior neighbours (boundary values are zero)
+    rows.append(idx[m]); cols.append(idx[m])
+    vals.append(scale * (4.0 / H**2 - sigma * k[m] ** 2) + 0j)
+    for di, dj in _NEIGHBOURS:
+        ni, nj = ii + di, jj + dj
+        ok = m.copy()
+        ok[m] = m[(nj * nx + ni)[m]]
+        rows.append(idx[ok]); cols.append((nj * nx + ni)[ok])
+        vals.append(np.full(ok.sum(), -scale / H**2, dtype=np.complex128))
+    # boundary rows: d_b u_b
+    rows.append(idx[~m]); cols.append(idx[~m])
+    vals.append(np.full((~m).sum(), scale * 4.0 / H**2, dtype=np.complex128))
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(N, N)).tocsr()
+
+
+def _wide_dirichlet(nx, ny, h, level, k, sigma):
+    L, K = stencils.stencils_2d_float(level)
+    r = L.shape[0] // 2
+    hl = h * 2 ** (level - 1)
+    sl = float(stencils.level_scale(level))
+    k2d = np.asarray(k, dtype=np.float64).reshape(ny, nx)
+    N = nx * ny
+    interior = interior_mask(nx, ny).reshape(ny, nx).astype(bool)
+    rows, cols, vals = [], [], []
+    for j in range(1, ny - 1):
+        for i in range(1, nx - 1):
+            I = j * nx + i
+            for b in range(-r, r + 1):
+                for a in range(-r, r + 1):
+                    lap, wav = L[b + r, a + r] / h**2, K[b + r, a + r]
+                    x, y = i + a, j + b
+                    xin, yin = 0 <= x < nx, 0 <= y < ny
+                    if xin and yin:
+                        if interior[y, x]:
+                            rows.append(I); cols.append(y * nx + x)
+                            vals.append(lap - sigma * wav * k2d[y, x] ** 2)
+                        continue
+                    if yin and x in (-1, nx):          # ghost in x: -u_m, k_g = 2k_b - k_m
+                        xb, xm = (0, 1) if x < 0 else (nx - 1, nx - 2)
+                        if interior[y, xm]:
+                            kg = 2 * k2d[y, xb] - k2d[y, xm]
+                            rows.append(I); cols.append(y * nx + xm)
+                            vals.append(-(lap - sigma * wav * kg**2))
+                    elif xin and y in (-1, ny):        # ghost in y
+                        yb, ym = (0, 1) if y < 0 else (ny - 1, ny - 2)
+                        if interior[ym, x]:
+                            kg = 2 * k2d[yb, x] - k2d[ym, x]
+                            rows.append(I); cols.append(ym * nx + x)
+                            vals.append(-(lap - sigma * wav * kg**2))
+    bnd = np.flatnonzero(~interior.ravel())
+    rows.extend(bnd.tolist()); cols.extend(bnd.tolist())
+    vals.extend([sl * 4.0 / hl**2] * len(bnd))
+    return sp.coo_matrix((np.asarray(vals, dtype=np.complex128), (rows, cols)),
+                         shape=(N, N)).tocsr()
+
+
+def wide_stencil(nx, ny, h, level, k, sigma, bc=SOMMERFELD):
     """Re-discretised coarse operator of deflation level `level` >= 2 (Sec. 3.3).
 
     h is the FINEST spacing (the printed stencils are in units of h^-2); the
     level spacing is h_l = 2^(l-1) h.  Interior/near-boundary rows:
         sum_{a,b} ( h^-2 L[b,a] - sigma K[b,a] k^2_{I+(a,b)} ) u_{I+(a,b)}
     with the ghost/zero rule for points outside the grid; boundary rows are
-    s_l * five_point at spacing h_l.
+    s_l * five_point at spacing h_l.  bc = "dirichlet": reading R24.
     """
+    if bc == DIRICHLET:
+        return _wide_dirichlet(nx, ny, h, level, k, sigma)
     L, K = stencils.stencils_2d_float(level)
     r = L.shape[0] // 2
     hl = h * 2 ** (level - 1)
@@ -139,12 +231,12 @@ def wide_stencil(nx, ny, h, level, k, sigma):
     return (Dc @ W + D @ B).tocsr()
 
 
-def level_operator(nx, ny, h, level, k, sigma):
+def level_operator(nx, ny, h, level, k, sigma, bc=SOMMERFELD):
     """Operator of deflation level `level`: the 5-point operator on the finest
     level, the Galerkin-derived wide stencil on coarser levels."""
     if level == 1:
-        return five_point(nx, ny, h, k, sigma, 1.0)
-    return wide_stencil(nx, ny, h, level, k, sigma)
+        return five_point(nx, ny, h, k, sigma, 1.0, bc=bc)
+    return wide_stencil(nx, ny, h, level, k, sigma, bc=bc)
 
 
 def _bezier_1d(nc):
@@ -160,9 +252,14 @@ def _bezier_1d(nc):
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
 
 
-def deflation_z(nxc, nyc):
-    """Z from the coarse grid (nxc x nyc) to the fine grid: p (x) p, truncated."""
-    return sp.kron(_bezier_1d(nyc), _bezier_1d(nxc)).tocsr().astype(np.complex128)
+def deflation_z(nxc, nyc, bc=SOMMERFELD):
+    """Z from the coarse grid (nxc x nyc) to the fine grid: p (x) p, truncated;
+    masked to the interior for Dirichlet boundaries (reading R24)."""
+    Z = sp.kron(_bezier_1d(nyc), _bezier_1d(nxc)).tocsr().astype(np.complex128)
+    if bc == DIRICHLET:
+        nxf, nyf = 2 * (nxc - 1) + 1, 2 * (nyc - 1) + 1
+        Z = _mask_rows_cols(Z, interior_mask(nxf, nyf), interior_mask(nxc, nyc))
+    return Z
 
 
 def _bilinear_1d(nc):
@@ -177,9 +274,14 @@ def _bilinear_1d(nc):
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
 
 
-def bilinear_prolongation(nxc, nyc):
-    """Bilinear interpolation coarse -> fine (multigrid prolongation)."""
-    return sp.kron(_bilinear_1d(nyc), _bilinear_1d(nxc)).tocsr().astype(np.complex128)
+def bilinear_prolongation(nxc, nyc, bc=SOMMERFELD):
+    """Bilinear interpolation coarse -> fine (multigrid prolongation); masked to
+    the interior for Dirichlet boundaries."""
+    P = sp.kron(_bilinear_1d(nyc), _bilinear_1d(nxc)).tocsr().astype(np.complex128)
+    if bc == DIRICHLET:
+        nxf, nyf = 2 * (nxc - 1) + 1, 2 * (nyc - 1) + 1
+        P = _mask_rows_cols(P, interior_mask(nxf, nyf), interior_mask(nxc, nyc))
+    return P
 
 
 def _full_weighting_1d(nf):
@@ -192,8 +294,13 @@ def _full_weighting_1d(nf):
     return sp.csr_matrix((vals, (rows, cols)), shape=(nc, nf))
 
 
-def full_weighting(nxf, nyf):
+def full_weighting(nxf, nyf, bc=SOMMERFELD):
     """Full-weighting restriction fine -> coarse with weights (1/16)[1 2 1;2 4 2;1 2 1]
     centred at fine node 2J; fine nodes outside the grid contribute zero.  The
-    2-D weights are the outer product of the 1-D weights [1, 2, 1]/4."""
-    return sp.kron(_full_weighting_1d(nyf), _full_weighting_1d(nxf)).tocsr().astype(np.complex128)
+    2-D weights are the outer product of the 1-D weights [1, 2, 1]/4.  Masked to
+    the interior for Dirichlet boundaries."""
+    R = sp.kron(_full_weighting_1d(nyf), _full_weighting_1d(nxf)).tocsr().astype(np.complex128)
+    if bc == DIRICHLET:
+        nxc, nyc = coarse_size(nxf, 2), coarse_size(nyf, 2)
+        R = _mask_rows_cols(R, interior_mask(nxc, nyc), interior_mask(nxf, nyf))
+    return R

@@ -28,9 +28,56 @@ inline unsigned blocks1d(size_t n) {
 // Ghost-extended value at grid position (x, y), which may lie outside:
 // inside -> u, k^2;  one step out in exactly one direction -> Sommerfeld ghost
 // u_m + i (2H) k_b u_b with k^2 = 0;  otherwise 0.
+// Dirichlet (d.bc == 1): boundary nodes read as zero; one step outside in
+// exactly one direction -> ghost 2 u_b - u_m = -u_m with wavenumber 2 k_b - k_m
+// (zero when the mirror u_m is itself a boundary node); otherwise 0.
+template <typename T>
+__device__ __forceinline__ void ext_val_dirichlet(const OpDesc<T>& d, const cx<T>* __restrict__ u,
+                                                  const T* __restrict__ k, int x, int y, cx<T>& uv,
+                                                  T& k2) {
+  const int nx = d.nx, ny = d.ny;
+  const bool xin = (unsigned)x < (unsigned)nx;
+  const bool yin = (unsigned)y < (unsigned)ny;
+  uv = mk(T(0), T(0));
+  k2 = T(0);
+  if (xin && yin) {
+    const size_t p = (size_t)y * nx + x;
+    const T kk = k[p];
+    k2 = kk * kk;
+    if (x > 0 && y > 0 && x < nx - 1 && y < ny - 1) uv = u[p];
+    return;
+  }
+  if (yin && (x == -1 || x == nx)) {
+    const int xb = x < 0 ? 0 : nx - 1;
+    const int xm = x < 0 ? 1 : nx - 2;
+    const size_t row = (size_t)y * nx;
+    const T kg = T(2) * k[row + xb] - k[row + xm];
+    k2 = kg * kg;
+    if (y > 0 && y < ny - 1) {
+      const cx<T> um = u[row + xm];
+      uv = mk(-um.re, -um.im);
+    }
+    return;
+  }
+  if (xin && (y == -1 || y == ny)) {
+    const int yb = y < 0 ? 0 : ny - 1;
+    const int ym = y < 0 ? 1 : ny - 2;
+    const T kg = T(2) * k[(size_t)yb * nx + x] - k[(size_t)ym * nx + x];
+    k2 = kg * kg;
+    if (x > 0 && x < nx - 1) {
+      const cx<T> um = u[(size_t)ym * nx + x];
+      uv = mk(-um.re, -um.im);
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void ext_val(const OpDesc<T>& d, const cx<T>* __restrict__ u,
                                         const T* __restrict__ k, int x, int y, cx<T>& uv, T& k2) {
+  if (d.bc) {
+    ext_val_dirichlet(d, u, k, x, y, uv, k2);
+    return;
+  }
   const int nx = d.nx, ny = d.ny;
   const bool xin = (unsigned)x < (unsigned)nx;
   const bool yin = (unsigned)y < (unsigned)ny;
@@ -85,6 +132,7 @@ __device__ __forceinline__ cx<T> five_point_diag(const OpDesc<T>& d, const T* __
   const T kk = k[(size_t)y * d.nx + x];
   const T k2 = kk * kk;
   const int nout = (x == 0) + (x == d.nx - 1) + (y == 0) + (y == d.ny - 1);
+  if (d.bc && nout) return mk(d.scale * T(4) * d.inv_H2, T(0));   // Dirichlet boundary row
   // scale*(4/H^2 - sigma k^2) - i scale/H^2 * 2H k * nout
   return mk(d.scale * (T(4) * d.inv_H2 - d.sig_re * k2),
             d.scale * (-d.sig_im * k2 - d.inv_H2 * d.two_H * kk * T(nout)));
@@ -123,7 +171,24 @@ __device__ __forceinline__ cx<T> wide_diag(const OpDesc<T>& d, const T* __restri
   const T lx2 = d.L[R * W + (R + 2)];
   const T ly2 = d.L[(R + 2) * W + R];
   T re = d.L[R * W + R] - d.sig_re * d.K[R * W + R] * k2;
-  const T im = -d.sig_im * d.K[R * W + R] * k2;
+  T im = -d.sig_im * d.K[R * W + R] * k2;
+  if (d.bc) {
+    // Dirichlet ghost -u_m with wavenumber k_g = 2 k_b - k_m: the tap lands on
+    // the node with coefficient -(L - sigma K k_g^2)
+    const T kx2 = d.K[R * W + (R + 2)], ky2 = d.K[(R + 2) * W + R];
+    const size_t row = (size_t)y * d.nx;
+    auto refl = [&](T lc, T kc, T kb, T km) {
+      const T kg = T(2) * kb - km;
+      re -= lc - d.sig_re * kc * kg * kg;
+      im += d.sig_im * kc * kg * kg;
+    };
+    if (x == 1) refl(lx2, kx2, k[row], k[row + 1]);
+    if (x == d.nx - 2) refl(lx2, kx2, k[row + d.nx - 1], k[row + d.nx - 2]);
+    if (y == 1) refl(ly2, ky2, k[x], k[(size_t)d.nx + x]);
+    if (y == d.ny - 2)
+      refl(ly2, ky2, k[(size_t)(d.ny - 1) * d.nx + x], k[(size_t)(d.ny - 2) * d.nx + x]);
+    return mk(re, im);
+  }
   re += lx2 * T((x == 1) + (x == d.nx - 2)) + ly2 * T((y == 1) + (y == d.ny - 2));
   return mk(re, im);
 }
@@ -170,7 +235,9 @@ __global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __rest
   const size_t p = (size_t)y * d.nx + x;
   cx<T> au;
   bool bnd = true;
-  if constexpr (R == 1) {
+  if (d.bc && is_boundary<T, R>(d, x, y)) {
+    au = (d.scale * T(4) * d.inv_H2) * u[p];          // Dirichlet boundary row d_b u_b
+  } else if constexpr (R == 1) {
     au = five_point_row(d, u, k, x, y);
   } else {
     bnd = is_boundary<T, R>(d, x, y);
@@ -197,7 +264,7 @@ __global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __rest
 }
 
 // Wide (5x5 / 7x7) stencil with the ghost-extended input tile staged in LDS.
-// Block = 64 x 4 threads, tile = 64 x 16 outputs; each thread produces WT_R
+// Block = 64 x 4 threads, tile = 64 x 8 outputs; each thread produces WT_R = 2
 // vertically adjacent outputs and keeps one stencil row in registers while it
 // is reused by the outputs that need it (fewer LDS reads per output).
 constexpr int WT_X = 64;
@@ -285,10 +352,15 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
     if (y >= d.ny) break;
     const size_t p = (size_t)y * d.nx + x;
     const int cy = ly0 + o + R, cxl = tx + R;
-    const cx<T> uc = su[cy][cxl];
+    cx<T> uc = su[cy][cxl];
     cx<T> au;
     const bool bnd = x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1;
-    if (bnd) {
+    if (bnd && d.bc) {
+      // Dirichlet boundary row d_b u_b; the tile holds zero there, so read u
+      uc = u[p];
+      if constexpr (MODE == ST_SCALED) uc = sc * uc;
+      au = (d.scale * T(4) * d.inv_H2) * uc;
+    } else if (bnd) {
       const T k2 = sk[cy][cxl];
       cx<T> s = mk(T(4) * uc.re, T(4) * uc.im);
       s = s - su[cy][cxl - 1];
@@ -333,123 +405,228 @@ __global__ void __launch_bounds__(NT) k_jacobi0(OpDesc<T> d, const T* __restrict
 
 // ---- transfers -------------------------------------------------------------
 
-__device__ __constant__ double kPz[5] = {0.125, 0.5, 0.75, 0.5, 0.125};
-
-template <typename Ti, typename To>
-__global__ void __launch_bounds__(NT) k_restrict_z(const cx<Ti>* __restrict__ f, int nxf, int nyf,
-                                                   cx<To>* __restrict__ c, int nxc, int nyc) {
-  const int I = blockIdx.x * BX + threadIdx.x;
-  const int J = blockIdx.y * BY + threadIdx.y;
-  if (I >= nxc || J >= nyc) return;
-  To re = 0, im = 0;
-#pragma unroll
-  for (int t = -2; t <= 2; ++t) {
-    const int y = 2 * J + t;
-    if ((unsigned)y >= (unsigned)nyf) continue;
-    To rr = 0, ri = 0;
-#pragma unroll
-    for (int s = -2; s <= 2; ++s) {
-      const int x = 2 * I + s;
-      if ((unsigned)x >= (unsigned)nxf) continue;
-      const cx<Ti> v = f[(size_t)y * nxf + x];
-      rr += (To)kPz[s + 2] * (To)v.re;
-      ri += (To)kPz[s + 2] * (To)v.im;
-    }
-    re += (To)kPz[t + 2] * rr;
-    im += (To)kPz[t + 2] * ri;
-  }
-  c[(size_t)J * nxc + I] = mk(re, im);
+// With dir != 0 (Dirichlet boundaries) every transfer is masked to the
+// interior: boundary values of the input count as zero and boundary values of
+// the output are zero, so boundary-free vectors stay boundary-free.
+__device__ __forceinline__ bool on_bnd(int x, int y, int nx, int ny) {
+  return x == 0 || y == 0 || x == nx - 1 || y == ny - 1;
 }
 
-// 1-D interpolation weights of Z for fine index i: coarse J0..J0+cnt-1
-__device__ __forceinline__ int z_weights(int i, int nc, int* js, double* ws) {
-  int cnt = 0;
-  if ((i & 1) == 0) {
-    const int I = i >> 1;
-    if (I - 1 >= 0) { js[cnt] = I - 1; ws[cnt++] = 0.125; }
-    js[cnt] = I; ws[cnt++] = 0.75;
-    if (I + 1 < nc) { js[cnt] = I + 1; ws[cnt++] = 0.125; }
-  } else {
-    const int I = i >> 1;
-    js[cnt] = I; ws[cnt++] = 0.5;
-    if (I + 1 < nc) { js[cnt] = I + 1; ws[cnt++] = 0.5; }
-  }
-  return cnt;
-}
+// ---- row-streaming transfers ------------------------------------------------
+// One-thread-per-output transfers read their 3x3 / 5x5 neighbourhoods with
+// stride-2 loads and stay far below the HBM rate.  These versions stream rows:
+// a block is four waves side by side, each owning 64 coarse columns, and walks
+// down TR coarse rows.  Every lane loads its own fine pair (2I, 2I+1) or coarse
+// value with coalesced loads, takes its neighbours' values across lanes
+// (lanes 0 and 63 load the values beyond the wave), filters horizontally and
+// combines rows vertically in registers, with the next rows' loads issued
+// before the current rows are processed.  Summation order (horizontal, then
+// vertical) is that of the separable weights.  Blocks go in the XCD-aware
+// tile order.
+constexpr int TR = 8;               // coarse rows per block
+constexpr int TCOLS = 256;          // coarse columns per block (4 waves x 64)
 
-template <typename Ti, typename To>
-__global__ void __launch_bounds__(NT) k_prolong_z(const cx<Ti>* __restrict__ c, int nxc, int nyc,
-                                                  cx<To>* __restrict__ f, int nxf, int nyf) {
-  const int x = blockIdx.x * BX + threadIdx.x;
-  const int y = blockIdx.y * BY + threadIdx.y;
-  if (x >= nxf || y >= nyf) return;
-  int jx[3], jy[3];
-  double wx[3], wy[3];
-  const int cxn = z_weights(x, nxc, jx, wx);
-  const int cyn = z_weights(y, nyc, jy, wy);
-  To re = 0, im = 0;
-  for (int b = 0; b < cyn; ++b) {
-    To rr = 0, ri = 0;
-    for (int a = 0; a < cxn; ++a) {
-      const cx<Ti> v = c[(size_t)jy[b] * nxc + jx[a]];
-      rr += (To)wx[a] * (To)v.re;
-      ri += (To)wx[a] * (To)v.im;
-    }
-    re += (To)wy[b] * rr;
-    im += (To)wy[b] * ri;
-  }
-  f[(size_t)y * nxf + x] = mk(re, im);
+inline unsigned sep_blocks(int nxc, int nyc) {
+  const size_t nt = (size_t)((nxc + TCOLS - 1) / TCOLS) * ((nyc + TR - 1) / TR);
+  return (unsigned)(8 * ((nt + 7) / 8));
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_restrict_fw(const cx<T>* __restrict__ f, int nxf, int nyf,
-                                                    cx<T>* __restrict__ c, int nxc, int nyc) {
-  const int I = blockIdx.x * BX + threadIdx.x;
-  const int J = blockIdx.y * BY + threadIdx.y;
-  if (I >= nxc || J >= nyc) return;
-  const T w[3] = {T(0.25), T(0.5), T(0.25)};
-  T re = 0, im = 0;
-#pragma unroll
-  for (int b = -1; b <= 1; ++b) {
-    const int y = 2 * J + b;
-    if ((unsigned)y >= (unsigned)nyf) continue;
-    T rr = 0, ri = 0;
-#pragma unroll
-    for (int a = -1; a <= 1; ++a) {
-      const int x = 2 * I + a;
-      if ((unsigned)x >= (unsigned)nxf) continue;
-      const cx<T> v = f[(size_t)y * nxf + x];
-      rr += w[a + 1] * v.re;
-      ri += w[a + 1] * v.im;
-    }
-    re += w[b + 1] * rr;
-    im += w[b + 1] * ri;
-  }
-  c[(size_t)J * nxc + I] = mk(re, im);
+__device__ __forceinline__ cx<T> lane_val(const cx<T>& v, int src) {
+  return mk(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
+}
+
+// fine row values owned by one lane: its pair (2I, 2I+1) and, for lane 0, the
+// pair (2I-2, 2I-1) before the wave; for lane 63, the value 2I+2 after it
+template <typename T>
+struct FinePair {
+  cx<T> a, b, ea, eb;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> masked_load(const cx<T>* __restrict__ f, int x, int y, int nx,
+                                             int ny, int lo) {
+  if (x >= lo && x < nx - lo && y >= lo && y < ny - lo) return f[(size_t)y * nx + x];
+  return mk(T(0), T(0));
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_prolong_bilinear_add(const cx<T>* __restrict__ c, int nxc,
-                                                             int nyc, cx<T>* __restrict__ f, int nxf,
-                                                             int nyf) {
-  const int x = blockIdx.x * BX + threadIdx.x;
-  const int y = blockIdx.y * BY + threadIdx.y;
-  if (x >= nxf || y >= nyf) return;
-  const int I = x >> 1, J = y >> 1;
-  const bool ox = x & 1, oy = y & 1;
-  cx<T> e;
-  if (!ox && !oy) {
-    e = c[(size_t)J * nxc + I];
-  } else if (ox && !oy) {
-    e = T(0.5) * (c[(size_t)J * nxc + I] + c[(size_t)J * nxc + I + 1]);
-  } else if (!ox && oy) {
-    e = T(0.5) * (c[(size_t)J * nxc + I] + c[(size_t)(J + 1) * nxc + I]);
-  } else {
-    e = T(0.25) * ((c[(size_t)J * nxc + I] + c[(size_t)J * nxc + I + 1]) +
-                   (c[(size_t)(J + 1) * nxc + I] + c[(size_t)(J + 1) * nxc + I + 1]));
+__device__ __forceinline__ FinePair<T> load_fine_pair(const cx<T>* __restrict__ f, int I, int y,
+                                                      int nxf, int nyf, int lo, int lane) {
+  FinePair<T> r;
+  r.a = masked_load(f, 2 * I, y, nxf, nyf, lo);
+  r.b = masked_load(f, 2 * I + 1, y, nxf, nyf, lo);
+  r.ea = mk(T(0), T(0));
+  r.eb = mk(T(0), T(0));
+  if (lane == 0) {
+    r.ea = masked_load(f, 2 * I - 2, y, nxf, nyf, lo);
+    r.eb = masked_load(f, 2 * I - 1, y, nxf, nyf, lo);
+  } else if (lane == 63) {
+    r.ea = masked_load(f, 2 * I + 2, y, nxf, nyf, lo);
   }
-  const size_t p = (size_t)y * nxf + x;
-  f[p] = f[p] + e;
+  return r;
+}
+
+// horizontal filter of one fine row at coarse column I:
+//   H = 2: (f[2I-2] + 4 f[2I-1] + 6 f[2I] + 4 f[2I+1] + f[2I+2]) / 8
+//   H = 1: (f[2I-1] + 2 f[2I] + f[2I+1]) / 4
+template <typename Ti, typename To, int H>
+__device__ __forceinline__ cx<To> hfilter(const FinePair<Ti>& r, int lane) {
+  cx<Ti> pa = lane_val(r.a, lane - 1), pb = lane_val(r.b, lane - 1), na = lane_val(r.a, lane + 1);
+  if (lane == 0) { pa = r.ea; pb = r.eb; }
+  if (lane == 63) na = r.ea;
+  if constexpr (H == 2) {
+    return mk(To(0.125) * (To)pa.re + To(0.5) * (To)pb.re + To(0.75) * (To)r.a.re +
+                  To(0.5) * (To)r.b.re + To(0.125) * (To)na.re,
+              To(0.125) * (To)pa.im + To(0.5) * (To)pb.im + To(0.75) * (To)r.a.im +
+                  To(0.5) * (To)r.b.im + To(0.125) * (To)na.im);
+  } else {
+    return mk(To(0.25) * (To)pb.re + To(0.5) * (To)r.a.re + To(0.25) * (To)r.b.re,
+              To(0.25) * (To)pb.im + To(0.5) * (To)r.a.im + To(0.25) * (To)r.b.im);
+  }
+}
+
+// Restriction fine -> coarse: H = 2 is Z^T (p = [1 4 6 4 1]/8 per dimension),
+// H = 1 full weighting ([1 2 1]/4 per dimension).
+template <typename Ti, typename To, int H>
+__global__ void __launch_bounds__(NT) k_restrict_rows(const cx<Ti>* __restrict__ f, int nxf, int nyf,
+                                                      cx<To>* __restrict__ c, int nxc, int nyc,
+                                                      int dir) {
+  int tx, ty;
+  if (!xcd_tile((nxc + TCOLS - 1) / TCOLS, (nyc + TR - 1) / TR, tx, ty)) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int I = tx * TCOLS + w * 64 + lane;
+  const int J0 = ty * TR;
+  const int lo = dir ? 1 : 0;
+  const To vw[5] = {To(0.125), To(0.5), To(0.75), To(0.5), To(0.125)};
+  const To fw[3] = {To(0.25), To(0.5), To(0.25)};
+  // window of horizontally filtered fine rows 2J - H .. 2J + H
+  cx<To> win[2 * H + 1];
+#pragma unroll
+  for (int t = 0; t < 2 * H - 1; ++t)            // rows 2 J0 - H .. 2 J0 + H - 2
+    win[t + 2] = hfilter<Ti, To, H>(load_fine_pair(f, I, 2 * J0 - H + t, nxf, nyf, lo, lane), lane);
+  FinePair<Ti> cur0 = load_fine_pair(f, I, 2 * J0 + H - 1, nxf, nyf, lo, lane);
+  FinePair<Ti> cur1 = load_fine_pair(f, I, 2 * J0 + H, nxf, nyf, lo, lane);
+#pragma unroll 1
+  for (int q = 0; q < TR; ++q) {
+    const int J = J0 + q;
+    FinePair<Ti> nxt0 = cur0, nxt1 = cur1;
+    if (q + 1 < TR) {                            // next rows in flight
+      nxt0 = load_fine_pair(f, I, 2 * J + H + 1, nxf, nyf, lo, lane);
+      nxt1 = load_fine_pair(f, I, 2 * J + H + 2, nxf, nyf, lo, lane);
+    }
+#pragma unroll
+    for (int t = 0; t < 2 * H - 1; ++t) win[t] = win[t + 2];
+    win[2 * H - 1] = hfilter<Ti, To, H>(cur0, lane);
+    win[2 * H] = hfilter<Ti, To, H>(cur1, lane);
+    To re = To(0), im = To(0);
+#pragma unroll
+    for (int t = 0; t <= 2 * H; ++t) {
+      const To wt = H == 2 ? vw[t] : fw[t];
+      re += wt * win[t].re;
+      im += wt * win[t].im;
+    }
+    if (I < nxc && J < nyc) {
+      cx<To> out = mk(re, im);
+      if (dir && on_bnd(I, J, nxc, nyc)) out = mk(To(0), To(0));
+      c[(size_t)J * nxc + I] = out;
+    }
+    cur0 = nxt0;
+    cur1 = nxt1;
+  }
+}
+
+// Prolongation coarse -> fine.  ZDEF: deflation interpolation Z written to f
+// (fine 2I: (c[I-1] + 6 c[I] + c[I+1]) / 8, fine 2I+1: (c[I] + c[I+1]) / 2 per
+// dimension); otherwise bilinear interpolation added to f.  Each lane
+// produces the fine pair (2I, 2I+1) of its coarse column I.
+template <typename T>
+__device__ __forceinline__ void load_coarse(const cx<T>* __restrict__ c, int I, int J, int nxc,
+                                            int nyc, int lo, int lane, cx<T>& own, cx<T>& edge) {
+  own = masked_load(c, I, J, nxc, nyc, lo);
+  edge = mk(T(0), T(0));
+  if (lane == 0) edge = masked_load(c, I - 1, J, nxc, nyc, lo);
+  else if (lane == 63) edge = masked_load(c, I + 1, J, nxc, nyc, lo);
+}
+
+template <typename Ti, typename To, bool ZDEF>
+__device__ __forceinline__ void hinterp(const cx<Ti>& own, const cx<Ti>& edge, int lane,
+                                        cx<To>& ev, cx<To>& od) {
+  cx<Ti> pv = lane_val(own, lane - 1), nv = lane_val(own, lane + 1);
+  if (lane == 0) pv = edge;
+  if (lane == 63) nv = edge;
+  if constexpr (ZDEF) {
+    ev = mk(To(0.125) * (To)pv.re + To(0.75) * (To)own.re + To(0.125) * (To)nv.re,
+            To(0.125) * (To)pv.im + To(0.75) * (To)own.im + To(0.125) * (To)nv.im);
+  } else {
+    ev = mk((To)own.re, (To)own.im);
+  }
+  od = mk(To(0.5) * (To)own.re + To(0.5) * (To)nv.re, To(0.5) * (To)own.im + To(0.5) * (To)nv.im);
+}
+
+template <typename Ti, typename To, bool ZDEF>
+__global__ void __launch_bounds__(NT) k_prolong_rows(const cx<Ti>* __restrict__ c, int nxc, int nyc,
+                                                     cx<To>* __restrict__ f, int nxf, int nyf,
+                                                     int dir) {
+  int tx, ty;
+  if (!xcd_tile((nxc + TCOLS - 1) / TCOLS, (nyc + TR - 1) / TR, tx, ty)) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int I = tx * TCOLS + w * 64 + lane;
+  const int J0 = ty * TR;
+  const int lo = dir ? 1 : 0;
+  // horizontal interpolants of coarse rows J-1, J, J+1: [row][even / odd]
+  cx<To> hv[3][2];
+  cx<Ti> own, edge;
+  load_coarse(c, I, J0 - 1, nxc, nyc, lo, lane, own, edge);
+  hinterp<Ti, To, ZDEF>(own, edge, lane, hv[1][0], hv[1][1]);
+  load_coarse(c, I, J0, nxc, nyc, lo, lane, own, edge);
+  hinterp<Ti, To, ZDEF>(own, edge, lane, hv[2][0], hv[2][1]);
+  cx<Ti> cown, cedge;
+  load_coarse(c, I, J0 + 1, nxc, nyc, lo, lane, cown, cedge);
+#pragma unroll 1
+  for (int q = 0; q < TR; ++q) {
+    const int J = J0 + q;
+    cx<Ti> nown = cown, nedge = cedge;
+    if (q + 1 < TR) load_coarse(c, I, J + 2, nxc, nyc, lo, lane, nown, nedge);
+    hv[0][0] = hv[1][0]; hv[0][1] = hv[1][1];
+    hv[1][0] = hv[2][0]; hv[1][1] = hv[2][1];
+    hinterp<Ti, To, ZDEF>(cown, cedge, lane, hv[2][0], hv[2][1]);
+    if (I < nxc && J < nyc) {
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {        // fine rows 2J, 2J+1
+        const int y = 2 * J + par;
+        if (y >= nyf) break;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {   // fine columns 2I, 2I+1
+          const int x = 2 * I + side;
+          if (x >= nxf) break;
+          cx<To> v;
+          if (par == 0) {
+            if constexpr (ZDEF) {
+              v = mk(To(0.125) * hv[0][side].re + To(0.75) * hv[1][side].re +
+                         To(0.125) * hv[2][side].re,
+                     To(0.125) * hv[0][side].im + To(0.75) * hv[1][side].im +
+                         To(0.125) * hv[2][side].im);
+            } else {
+              v = hv[1][side];
+            }
+          } else {
+            v = mk(To(0.5) * hv[1][side].re + To(0.5) * hv[2][side].re,
+                   To(0.5) * hv[1][side].im + To(0.5) * hv[2][side].im);
+          }
+          const size_t p = (size_t)y * nxf + x;
+          const bool fb = dir && on_bnd(x, y, nxf, nyf);
+          if constexpr (ZDEF) {
+            f[p] = fb ? mk(To(0), To(0)) : v;
+          } else {
+            if (!fb) f[p] = f[p] + v;
+          }
+        }
+      }
+    }
+    cown = nown;
+    cedge = nedge;
+  }
 }
 
 template <typename Ti, typename To>
@@ -654,7 +831,8 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
 
 // out[i] = sum_c partials[i*nchunks + c]; sqrt_re: out = sqrt(re)
 __global__ void __launch_bounds__(NT) k_final(const c128* __restrict__ partials, int nchunks,
-                                              c128* __restrict__ out, int sqrt_re) {
+                                              c128* __restrict__ out, int sqrt_re,
+                                              c128* __restrict__ host_out) {
   __shared__ double sh[2 * NT / 64];
   const int i = blockIdx.x;
   double re = 0, im = 0;
@@ -664,7 +842,11 @@ __global__ void __launch_bounds__(NT) k_final(const c128* __restrict__ partials,
     im += v.im;
   }
   const c128 s = block_sum(re, im, sh);
-  if (threadIdx.x == 0) out[i] = sqrt_re ? mk(sqrt(s.re), 0.0) : s;
+  if (threadIdx.x == 0) {
+    const c128 v = sqrt_re ? mk(sqrt(s.re), 0.0) : s;
+    out[i] = v;
+    if (host_out) host_out[i] = v;      // pinned host mirror, read after an event
+  }
 }
 
 template <typename T>
@@ -941,30 +1123,33 @@ hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>*
 }
 
 template <typename Ti, typename To>
-hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, hipStream_t s) {
+hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, int dir,
+                             hipStream_t s) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_restrict_z<Ti, To><<<grid2d(nxc, nyc), dim3(BX, BY), 0, s>>>(f, nxf, nyf, c, nxc, nyc);
+  k_restrict_rows<Ti, To, 2><<<sep_blocks(nxc, nyc), NT, 0, s>>>(f, nxf, nyf, c, nxc, nyc, dir);
   return hipGetLastError();
 }
 
 template <typename Ti, typename To>
-hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, hipStream_t s) {
+hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, int dir,
+                            hipStream_t s) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_prolong_z<Ti, To><<<grid2d(nxf, nyf), dim3(BX, BY), 0, s>>>(c, nxc, nyc, f, nxf, nyf);
+  k_prolong_rows<Ti, To, true><<<sep_blocks(nxc, nyc), NT, 0, s>>>(c, nxc, nyc, f, nxf, nyf, dir);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, hipStream_t s) {
+hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, int dir, hipStream_t s) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_restrict_fw<T><<<grid2d(nxc, nyc), dim3(BX, BY), 0, s>>>(f, nxf, nyf, c, nxc, nyc);
+  k_restrict_rows<T, T, 1><<<sep_blocks(nxc, nyc), NT, 0, s>>>(f, nxf, nyf, c, nxc, nyc, dir);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, hipStream_t s) {
+hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, int dir,
+                                       hipStream_t s) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_prolong_bilinear_add<T><<<grid2d(nxf, nyf), dim3(BX, BY), 0, s>>>(c, nxc, nyc, f, nxf, nyf);
+  k_prolong_rows<T, T, false><<<sep_blocks(nxc, nyc), NT, 0, s>>>(c, nxc, nyc, f, nxf, nyf, dir);
   return hipGetLastError();
 }
 
@@ -1068,9 +1253,10 @@ hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T
 }
 
 template <typename T>
-hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s) {
+hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s,
+                                 c128* host_out) {
   if (m <= 0) return hipSuccess;
-  k_final<<<m, NT, 0, s>>>(rb.partials, multidot_chunks(n, m, rb), out, 0);
+  k_final<<<m, NT, 0, s>>>(rb.partials, multidot_chunks(n, m, rb), out, 0, host_out);
   return hipGetLastError();
 }
 
@@ -1087,7 +1273,7 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
                            size_t n, RedBuf rb, c128* out, hipStream_t s) {
   const size_t clen = chunk_len(n, rb.nchunks);
   k_mgs_step<T><<<rb.nchunks, NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials);
-  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, next ? 0 : 1);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, next ? 0 : 1, nullptr);
   return hipGetLastError();
 }
 
@@ -1116,8 +1302,9 @@ hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m
   return hipGetLastError();
 }
 
-hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s) {
-  k_final<<<1, NT, 0, s>>>(rb.partials, update_chunks(n, rb), out, 1);
+hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,
+                                    c128* host_out) {
+  k_final<<<1, NT, 0, s>>>(rb.partials, update_chunks(n, rb), out, 1, host_out);
   return hipGetLastError();
 }
 
@@ -1133,7 +1320,7 @@ template <typename T>
 hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream_t s) {
   const size_t clen = chunk_len(n, rb.nchunks);
   k_norm2<T><<<rb.nchunks, NT, 0, s>>>(x, n, clen, rb.partials);
-  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 1);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 1, nullptr);
   return hipGetLastError();
 }
 
@@ -1147,7 +1334,7 @@ hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipS
 hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s) {
   const size_t clen = chunk_len(n, rb.nchunks);
   k_check_k<<<rb.nchunks, NT, 0, s>>>(k, n, clen, rb.partials);
-  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 0);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 0, nullptr);
   return hipGetLastError();
 }
 
@@ -1157,8 +1344,9 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
                                         const cx<T>*, cx<T>*, T, hipStream_t);                       \
   template hipError_t launch_jacobi0<T>(const OpDesc<T>&, const T*, const cx<T>*, cx<T>*, T,         \
                                         hipStream_t);                                               \
-  template hipError_t launch_restrict_fw<T>(const cx<T>*, int, int, cx<T>*, hipStream_t);          \
-  template hipError_t launch_prolong_bilinear_add<T>(const cx<T>*, int, int, cx<T>*, hipStream_t); \
+  template hipError_t launch_restrict_fw<T>(const cx<T>*, int, int, cx<T>*, int, hipStream_t);     \
+  template hipError_t launch_prolong_bilinear_add<T>(const cx<T>*, int, int, cx<T>*, int,         \
+                                                     hipStream_t);                                  \
   template hipError_t launch_add<T>(const cx<T>*, const cx<T>*, cx<T>*, size_t, hipStream_t);      \
   template hipError_t launch_scale_dev<T>(const cx<T>*, cx<T>*, const c128*, int, size_t,          \
                                           hipStream_t);                                             \
@@ -1170,7 +1358,7 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
                                          c128*, hipStream_t);                                       \
   template hipError_t launch_multidot_partial<T>(const cx<T>*, size_t, int, const cx<T>*, size_t,  \
                                                  RedBuf, int, hipStream_t);                         \
-  template hipError_t launch_multidot_final<T>(int, size_t, RedBuf, c128*, hipStream_t);           \
+  template hipError_t launch_multidot_final<T>(int, size_t, RedBuf, c128*, hipStream_t, c128*);           \
   template hipError_t launch_cgs_update_partial<T>(cx<T>*, const cx<T>*, size_t, int, const c128*, \
                                                    size_t, RedBuf, int, hipStream_t);               \
   template hipError_t launch_stencil_scaled<T>(const OpDesc<T>&, const cx<T>*, const T*,            \
@@ -1185,8 +1373,8 @@ HM_INST_T(double)
 #undef HM_INST_T
 
 #define HM_INST_2(A, B)                                                                          \
-  template hipError_t launch_restrict_z<A, B>(const cx<A>*, int, int, cx<B>*, hipStream_t);     \
-  template hipError_t launch_prolong_z<A, B>(const cx<A>*, int, int, cx<B>*, hipStream_t);      \
+  template hipError_t launch_restrict_z<A, B>(const cx<A>*, int, int, cx<B>*, int, hipStream_t); \
+  template hipError_t launch_prolong_z<A, B>(const cx<A>*, int, int, cx<B>*, int, hipStream_t);  \
   template hipError_t launch_inject<A, B>(const A*, int, int, B*, hipStream_t);                 \
   template hipError_t launch_convert_real<A, B>(const A*, B*, size_t, hipStream_t);             \
   template hipError_t launch_convert<A, B>(const cx<A>*, cx<B>*, size_t, hipStream_t);

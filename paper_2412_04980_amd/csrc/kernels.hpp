@@ -32,6 +32,7 @@ struct OpDesc {
   // K[b][a] = m[a] m[b]
   T t1[7];
   T m1[7];
+  int bc;     // 0 Sommerfeld ghosts, 1 homogeneous Dirichlet (boundary rows d_b u_b)
 };
 
 enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_JACOBI = 2 };
@@ -55,20 +56,24 @@ template <typename T>
 hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x, T omega,
                           hipStream_t s);
 
+// Transfers take dir = 1 for Dirichlet boundaries: boundary values of the input
+// count as zero and boundary values of the output are zero (interior masks on
+// both sides); dir = 0 for Sommerfeld.
 // Deflation restriction Z^T: fine (nxf x nyf) -> coarse; weights p (x) p,
 // p = [1 4 6 4 1]/8 at fine offsets -2..2 around 2J; outside values zero.
 template <typename Ti, typename To>
-hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, hipStream_t s);
+hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, int dir, hipStream_t s);
 // Deflation interpolation Z: coarse -> fine (transpose of the above).
 template <typename Ti, typename To>
-hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, hipStream_t s);
+hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, int dir, hipStream_t s);
 
 // Full-weighting restriction (1/16)[1 2 1;2 4 2;1 2 1], fine -> coarse.
 template <typename T>
-hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, hipStream_t s);
+hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, int dir, hipStream_t s);
 // x_fine += bilinear interpolation of e_coarse.
 template <typename T>
-hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, hipStream_t s);
+hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, int dir,
+                                       hipStream_t s);
 // Injection of a real nodal field: c(J) = f(2J).
 template <typename Ti, typename To>
 hipError_t launch_inject(const Ti* f, int nxf, int nyf, To* c, hipStream_t s);
@@ -124,8 +129,10 @@ int reduction_chunks(size_t n);
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
                                    RedBuf rb, int reverse, hipStream_t s);
+// host_out (optional): pinned host memory that receives a copy of out
 template <typename T>
-hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s);
+hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s,
+                                 c128* host_out = nullptr);
 template <typename T>
 hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n, RedBuf rb,
                            c128* out, hipStream_t s);
@@ -139,7 +146,8 @@ template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                      size_t n, RedBuf rb, int reverse, hipStream_t s);
 // sum of the partials written by launch_cgs_update_partial over a vector of length n
-hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s);
+hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,
+                                    c128* host_out = nullptr);
 template <typename T>
 hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                   size_t n, RedBuf rb, c128* out, hipStream_t s);

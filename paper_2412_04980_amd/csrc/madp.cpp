@@ -189,9 +189,10 @@ inline int krylov_maxit(size_t N, double coef) {
 static const int kDenseMax = 512;
 
 template <typename T>
-static void set_five_point(OpDesc<T>& d, int nx, int ny, double H, double scale, cd sigma) {
+static void set_five_point(OpDesc<T>& d, int nx, int ny, double H, double scale, cd sigma, int bc) {
   std::memset(&d, 0, sizeof(d));
   d.nx = nx; d.ny = ny; d.R = 1;
+  d.bc = bc;
   d.inv_H2 = (T)(1.0 / (H * H));
   d.two_H = (T)(2.0 * H);
   d.scale = (T)scale;
@@ -200,13 +201,13 @@ static void set_five_point(OpDesc<T>& d, int nx, int ny, double H, double scale,
 }
 
 template <typename T>
-static void set_wide(OpDesc<T>& d, int nx, int ny, double h, int level, cd sigma) {
+static void set_wide(OpDesc<T>& d, int nx, int ny, double h, int level, cd sigma, int bc) {
   int R = 0;
   std::vector<double> lap, wav;
   coarse_tables(level, &R, lap, wav);
   const double hl = h * std::ldexp(1.0, level - 1);
   const double sl = std::ldexp(1.0, 2 * (level - 1));
-  set_five_point(d, nx, ny, hl, sl, sigma);
+  set_five_point(d, nx, ny, hl, sl, sigma, bc);
   d.R = R;
   const double h2 = h * h;
   for (size_t i = 0; i < lap.size(); ++i) {
@@ -396,13 +397,12 @@ static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& w
     timed(p, HM_TK_CGS_DOT, (j + 2) * es * N, [&] {
       return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), 0, p->s);
     });
-    HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s));
+    c128* hcol = p->host_H + (size_t)j * ld;      // pinned mirror of the column
+    HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s, hcol));
     timed(p, HM_TK_CGS_UPDATE, (j + 3) * es * N, [&] {
       return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), 1, p->s);
     });
-    HM_CHECK(launch_update_norm_final(N, rbuf(p, N), col + j + 1, p->s));
-    HM_CHECK(hipMemcpyAsync(p->host_H + (size_t)j * ld, col, sizeof(c128) * (j + 2),
-                            hipMemcpyDeviceToHost, p->s));
+    HM_CHECK(launch_update_norm_final(N, rbuf(p, N), col + j + 1, p->s, hcol + j + 1));
     HM_CHECK(hipEventRecord(p->col_ev[j & 1], p->s));
   };
   LSQ lsq;
@@ -453,9 +453,9 @@ static const cx<T>* mg_cycle(hm_problem* p, DefLevel& D, int q, const cx<T>* b) 
   cx<T>* r = (cx<T>*)m.r;
   HM_CHECK(launch_stencil<T>(op, ST_RESID, x, k, b, r, T(0), p->s));
   MGLevel& mc = H.lv[q + 1];
-  HM_CHECK(launch_restrict_fw<T>(r, m.nx, m.ny, (cx<T>*)mc.b, p->s));
+  HM_CHECK(launch_restrict_fw<T>(r, m.nx, m.ny, (cx<T>*)mc.b, p->cfg.bc, p->s));
   const cx<T>* e = mg_cycle<T>(p, D, q + 1, (const cx<T>*)mc.b);
-  HM_CHECK(launch_prolong_bilinear_add<T>(e, m.nx, m.ny, x, p->s));
+  HM_CHECK(launch_prolong_bilinear_add<T>(e, m.nx, m.ny, x, p->cfg.bc, p->s));
   for (int s = 0; s < p->cfg.mg_nu_post; ++s) {
     HM_CHECK(launch_stencil<T>(op, ST_JACOBI, x, k, b, y, om, p->s));
     std::swap(x, y);
@@ -599,9 +599,9 @@ template <typename T, typename Tn>
 static void coarse_branch(hm_problem* p, int l, const cx<T>* v) {
   DefLevel& D = p->lev[l];
   DefLevel& C = p->lev[l + 1];
-  HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, (cx<Tn>*)C.rhs, p->s));
+  HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, (cx<Tn>*)C.rhs, p->cfg.bc, p->s));
   coarse_solve<Tn>(p, l + 1, (const cx<Tn>*)C.rhs, (cx<Tn>*)C.sol);
-  HM_CHECK(launch_prolong_z<Tn, T>((const cx<Tn>*)C.sol, D.nx, D.ny, (cx<T>*)D.t, p->s));
+  HM_CHECK(launch_prolong_z<Tn, T>((const cx<Tn>*)C.sol, D.nx, D.ny, (cx<T>*)D.t, p->cfg.bc, p->s));
 }
 
 // Prec_l(v) = M_l^-1 (v - A_l t) + t,  t = Z E^-1 Z^T v   (A-DEF1, Sec. 3.1)
@@ -731,7 +731,7 @@ static bool validate(const hm_config* c, std::string* why) {
   if ((c->nx - 1) % f || (c->ny - 1) % f) return bad("(n-1) must be divisible by 2^(levels-1)");
   if ((c->nx - 1) / f + 1 < 3 || (c->ny - 1) / f + 1 < 3) return bad("coarsest level below 3 nodes");
   if (!(c->h > 0) || !std::isfinite(c->h)) return bad("h must be positive");
-  if (c->bc != HM_BC_SOMMERFELD) return bad("only Sommerfeld boundaries are supported");
+  if (c->bc != HM_BC_SOMMERFELD && c->bc != HM_BC_DIRICHLET) return bad("unknown boundary condition");
   if (!std::isfinite(c->beta1) || !std::isfinite(c->beta2)) return bad("beta not finite");
   if (c->precision != HM_FP64 && c->precision != HM_MIXED_FP32) return bad("precision");
   if (c->outer_restart < 1 || c->outer_maxit < 1 || c->level2_maxit < 1) return bad("step caps");
@@ -769,15 +769,15 @@ static void plan(hm_problem* p, Carver& cv) {
     D.k64 = cv.take<double>(D.N);
     if (!D.dbl) D.k32 = cv.take<float>(D.N);
     if (l == 1) {
-      set_five_point(D.A64, nx, ny, c.h, 1.0, cd(1, 0));
-      set_five_point(D.M64, nx, ny, c.h, 1.0, sig_m);
-      set_five_point(D.A32, nx, ny, c.h, 1.0, cd(1, 0));
-      set_five_point(D.M32, nx, ny, c.h, 1.0, sig_m);
+      set_five_point(D.A64, nx, ny, c.h, 1.0, cd(1, 0), c.bc);
+      set_five_point(D.M64, nx, ny, c.h, 1.0, sig_m, c.bc);
+      set_five_point(D.A32, nx, ny, c.h, 1.0, cd(1, 0), c.bc);
+      set_five_point(D.M32, nx, ny, c.h, 1.0, sig_m, c.bc);
     } else {
-      set_wide(D.A64, nx, ny, c.h, l, cd(1, 0));
-      set_wide(D.M64, nx, ny, c.h, l, sig_m);
-      set_wide(D.A32, nx, ny, c.h, l, cd(1, 0));
-      set_wide(D.M32, nx, ny, c.h, l, sig_m);
+      set_wide(D.A64, nx, ny, c.h, l, cd(1, 0), c.bc);
+      set_wide(D.M64, nx, ny, c.h, l, sig_m, c.bc);
+      set_wide(D.A32, nx, ny, c.h, l, cd(1, 0), c.bc);
+      set_wide(D.M32, nx, ny, c.h, l, sig_m, c.bc);
     }
     if (l >= 2) {
       D.fg.cap = tol_level(c, p->L, l) ? c.level2_maxit : c.coarse_steps;
@@ -808,8 +808,8 @@ static void plan(hm_problem* p, Carver& cv) {
           m.op64 = D.M64;
           m.op32 = D.M32;
         } else {
-          set_five_point(m.op64, mx, my, Hs, D.sl, sig_m);
-          set_five_point(m.op32, mx, my, Hs, D.sl, sig_m);
+          set_five_point(m.op64, mx, my, Hs, D.sl, sig_m, c.bc);
+          set_five_point(m.op32, mx, my, Hs, D.sl, sig_m, c.bc);
           m.k = cv.take<double>(m.N);
           if (!D.dbl) m.k32 = cv.take<float>(m.N);
           m.b = cv.take<char>(m.N * es);
@@ -1021,12 +1021,12 @@ static void op_transfer(hm_problem* p, int l, int which, const c128* in, c128* o
   if (which == HM_OP_ZT) {
     const cx<T>* v = to_level<T>(p, in, D.N, p->pin_v);
     cx<Tn>* o = out_level<Tn>(out, p->pin_x);
-    HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, o, p->s));
+    HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, o, p->cfg.bc, p->s));
     from_level<Tn>(p, o, out, C.N);
   } else {
     const cx<Tn>* v = to_level<Tn>(p, in, C.N, p->pin_v);
     cx<T>* o = out_level<T>(out, p->pin_x);
-    HM_CHECK(launch_prolong_z<Tn, T>(v, D.nx, D.ny, o, p->s));
+    HM_CHECK(launch_prolong_z<Tn, T>(v, D.nx, D.ny, o, p->cfg.bc, p->s));
     from_level<T>(p, o, out, D.N);
   }
 }
@@ -1080,13 +1080,13 @@ static void op_level(hm_problem* p, int l, int sub, int which, const c128* in, c
     }
     case HM_OP_MG_RESTRICT: {
       const MGLevel& m = D.mg.lv[sub];
-      HM_CHECK(launch_restrict_fw<T>(v, m.nx, m.ny, o, p->s));
+      HM_CHECK(launch_restrict_fw<T>(v, m.nx, m.ny, o, p->cfg.bc, p->s));
       break;
     }
     case HM_OP_MG_PROLONG: {
       const MGLevel& m = D.mg.lv[sub];
       HM_CHECK(launch_zero<T>(o, m.N, p->s));
-      HM_CHECK(launch_prolong_bilinear_add<T>(v, m.nx, m.ny, o, p->s));
+      HM_CHECK(launch_prolong_bilinear_add<T>(v, m.nx, m.ny, o, p->cfg.bc, p->s));
       break;
     }
     default: throw ArgError("unknown operator");
@@ -1310,7 +1310,7 @@ hm_status hm_matfree_apply(int nx, int ny, double h, const double* k_dev, const 
   if (!k_dev || !u_dev || !v_dev) return HM_ERR_ARG;
   return guard([&]() -> hm_status {
     OpDesc<double> d;
-    set_five_point(d, nx, ny, h, 1.0, cd(1.0, 0.0));
+    set_five_point(d, nx, ny, h, 1.0, cd(1.0, 0.0), HM_BC_SOMMERFELD);
     HM_CHECK(launch_stencil(d, ST_APPLY, (const c128*)u_dev, k_dev, (const c128*)nullptr,
                             (c128*)v_dev, 0.0, (hipStream_t)stream));
     return HM_OK;
@@ -1323,7 +1323,7 @@ hm_status hm_csr_assemble(int nx, int ny, double h, const double* k_dev, int* ro
   if (!k_dev || !row_ptr_dev || !col_idx_dev || !vals_dev) return HM_ERR_ARG;
   return guard([&]() -> hm_status {
     OpDesc<double> d;
-    set_five_point(d, nx, ny, h, 1.0, cd(1.0, 0.0));
+    set_five_point(d, nx, ny, h, 1.0, cd(1.0, 0.0), HM_BC_SOMMERFELD);
     HM_CHECK(launch_csr5_assemble(d, k_dev, row_ptr_dev, col_idx_dev, (c128*)vals_dev,
                                   (hipStream_t)stream));
     return HM_OK;

@@ -43,8 +43,8 @@ def test_default_config_is_madp():
 def test_workspace_bytes_validation():
     import paper_2412_04980_amd as hm
     assert hm.workspace_bytes(hm.default_config(129, 129, 1 / 128)) > 0
-    for bad in (dict(nx=130), dict(levels=1), dict(levels=7), dict(h=-1.0), dict(bc=1),
-                dict(precision=5), dict(outer_restart=0), dict(tol_outer=0.0),
+    for bad in (dict(nx=130), dict(levels=1), dict(levels=7), dict(h=-1.0),
+                dict(precision=5), dict(outer_restart=0), dict(tol_outer=0.0), dict(bc=2),
                 dict(coarse_steps=0), dict(coarse_steps=17), dict(tol_levels=0),
                 dict(tol_levels=7)):
         c = hm.default_config(129, 129, 1 / 128)
