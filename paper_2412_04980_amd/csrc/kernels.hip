@@ -139,29 +139,6 @@ __device__ __forceinline__ cx<T> five_point_diag(const OpDesc<T>& d, const T* __
 }
 
 template <typename T, int R>
-__device__ __forceinline__ cx<T> wide_row(const OpDesc<T>& d, const cx<T>* __restrict__ u,
-                                          const T* __restrict__ k, int x, int y) {
-  constexpr int W = 2 * R + 1;
-  T acc_re = 0, acc_im = 0;
-#pragma unroll
-  for (int b = -R; b <= R; ++b) {
-#pragma unroll
-    for (int a = -R; a <= R; ++a) {
-      cx<T> uv;
-      T k2;
-      ext_val(d, u, k, x + a, y + b, uv, k2);
-      const T lc = d.L[(b + R) * W + (a + R)];
-      const T kc = d.K[(b + R) * W + (a + R)] * k2;
-      const T cre = lc - d.sig_re * kc;
-      const T cim = -d.sig_im * kc;
-      acc_re += cre * uv.re - cim * uv.im;
-      acc_im += cre * uv.im + cim * uv.re;
-    }
-  }
-  return mk(acc_re, acc_im);
-}
-
-template <typename T, int R>
 __device__ __forceinline__ cx<T> wide_diag(const OpDesc<T>& d, const T* __restrict__ k, int x, int y) {
   constexpr int W = 2 * R + 1;
   const T kk = k[(size_t)y * d.nx + x];
@@ -193,7 +170,7 @@ __device__ __forceinline__ cx<T> wide_diag(const OpDesc<T>& d, const T* __restri
   return mk(re, im);
 }
 
-// XCD-aware order of BX x BY tiles for a 1-D grid of xcd_blocks() blocks.
+// XCD-aware order of tiles for a 1-D grid of 8 * ceil(tiles / 8) blocks.
 // Blocks are dispatched round-robin over the 8 XCDs (block b on XCD b % 8);
 // XCD j takes the j-th contiguous range of tiles in row-major order, so the
 // tiles above and below a tile run on the same XCD close in time and the halo
@@ -208,11 +185,6 @@ __device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& tx, int& ty) {
   return true;
 }
 
-inline unsigned xcd_blocks(int nx, int ny) {
-  const size_t nt = (size_t)((nx + BX - 1) / BX) * ((ny + BY - 1) / BY);
-  return (unsigned)(8 * ((nt + 7) / 8));
-}
-
 template <typename T, int R>
 __device__ __forceinline__ bool is_boundary(const OpDesc<T>& d, int x, int y) {
   return x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1;
@@ -220,47 +192,87 @@ __device__ __forceinline__ bool is_boundary(const OpDesc<T>& d, int x, int y) {
 
 constexpr int ST_SCALED = 3;   // out = Op(s u), vout = s u, s = 1 / scal[0].re
 
-template <typename T, int R, int MODE>
-__global__ void __launch_bounds__(NT) k_stencil(OpDesc<T> d, const cx<T>* __restrict__ u,
+// Output of one 5-point row for the stencil modes (Dirichlet boundary rows
+// are d_b u_b; everything else goes through the ghost-extended values).
+template <typename T, int MODE>
+__device__ __forceinline__ void five_point_emit(const OpDesc<T>& d, const cx<T>* __restrict__ u,
                                                 const T* __restrict__ k,
                                                 const cx<T>* __restrict__ b,
-                                                cx<T>* __restrict__ out, T omega,
-                                                const c128* __restrict__ scal,
-                                                cx<T>* __restrict__ vout) {
-  int tx, ty;
-  if (!xcd_tile((d.nx + BX - 1) / BX, (d.ny + BY - 1) / BY, tx, ty)) return;
-  const int x = tx * BX + threadIdx.x;
-  const int y = ty * BY + threadIdx.y;
-  if (x >= d.nx || y >= d.ny) return;
+                                                cx<T>* __restrict__ out, T omega, T sc,
+                                                cx<T>* __restrict__ vout, int x, int y, cx<T> au) {
   const size_t p = (size_t)y * d.nx + x;
-  cx<T> au;
-  bool bnd = true;
-  if (d.bc && is_boundary<T, R>(d, x, y)) {
-    au = (d.scale * T(4) * d.inv_H2) * u[p];          // Dirichlet boundary row d_b u_b
-  } else if constexpr (R == 1) {
-    au = five_point_row(d, u, k, x, y);
-  } else {
-    bnd = is_boundary<T, R>(d, x, y);
-    au = bnd ? five_point_row(d, u, k, x, y) : wide_row<T, R>(d, u, k, x, y);
-  }
   if constexpr (MODE == ST_APPLY) {
     out[p] = au;
   } else if constexpr (MODE == ST_SCALED) {
-    const T sc = (T)(1.0 / scal[0].re);
     out[p] = sc * au;
     vout[p] = sc * u[p];
   } else if constexpr (MODE == ST_RESID) {
     out[p] = b[p] - au;
   } else {
-    cx<T> dg;
-    if constexpr (R == 1) {
-      dg = five_point_diag(d, k, x, y);
-    } else {
-      dg = bnd ? five_point_diag(d, k, x, y) : wide_diag<T, R>(d, k, x, y);
-    }
     const cx<T> r = b[p] - au;
-    out[p] = u[p] + omega * cdiv(r, dg);
+    out[p] = u[p] + omega * cdiv(r, five_point_diag(d, k, x, y));
   }
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> five_point_any(const OpDesc<T>& d, const cx<T>* __restrict__ u,
+                                                const T* __restrict__ k, int x, int y) {
+  if (d.bc && (x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1))
+    return (d.scale * T(4) * d.inv_H2) * u[(size_t)y * d.nx + x];   // Dirichlet d_b u_b
+  return five_point_row(d, u, k, x, y);
+}
+
+// 5-point operator in all stencil modes.  Block = 64 x 4 threads, tile = 64 x 8
+// nodes in the XCD-aware order; each thread takes two vertically adjacent nodes,
+// which share their middle neighbours (four vertical loads for two outputs) and
+// give every thread twice the independent loads in flight.  Nodes whose
+// neighbours are all plain grid values take the direct path; the others (the
+// boundary band) go through the ghost-extended values.
+constexpr int FP_ROWS = 2;
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(NT) k_five_point(OpDesc<T> d, const cx<T>* __restrict__ u,
+                                                   const T* __restrict__ k,
+                                                   const cx<T>* __restrict__ b,
+                                                   cx<T>* __restrict__ out, T omega,
+                                                   const c128* __restrict__ scal,
+                                                   cx<T>* __restrict__ vout) {
+  int tx, ty;
+  if (!xcd_tile((d.nx + BX - 1) / BX, (d.ny + BY * FP_ROWS - 1) / (BY * FP_ROWS), tx, ty)) return;
+  const int nx = d.nx, ny = d.ny;
+  const int x = tx * BX + threadIdx.x;
+  const int y = ty * BY * FP_ROWS + threadIdx.y * FP_ROWS;
+  if (x >= nx || y >= ny) return;
+  T sc = T(1);
+  if constexpr (MODE == ST_SCALED) sc = (T)(1.0 / scal[0].re);
+  const int e = d.bc ? 2 : 1;        // Dirichlet: neighbours on the boundary read as zero
+  if (x >= e && x <= nx - 1 - e && y >= e && y + 1 <= ny - 1 - e) {
+    const size_t p0 = (size_t)y * nx + x, p1 = p0 + nx;
+    const cx<T> us = u[p0 - nx], u0 = u[p0], u1 = u[p1], un = u[p1 + nx];
+    const cx<T> w0 = u[p0 - 1], e0 = u[p0 + 1], w1 = u[p1 - 1], e1 = u[p1 + 1];
+    const T k0 = k[p0], k1 = k[p1];
+    cx<T> s0 = mk(T(4) * u0.re, T(4) * u0.im);
+    s0 = s0 - w0; s0 = s0 - e0; s0 = s0 - us; s0 = s0 - u1;
+    cx<T> s1 = mk(T(4) * u1.re, T(4) * u1.im);
+    s1 = s1 - w1; s1 = s1 - e1; s1 = s1 - u0; s1 = s1 - un;
+    const T q0 = k0 * k0, q1 = k1 * k1;
+    const cx<T> a0 = d.scale * (d.inv_H2 * s0 - mk(d.sig_re * q0, d.sig_im * q0) * u0);
+    const cx<T> a1 = d.scale * (d.inv_H2 * s1 - mk(d.sig_re * q1, d.sig_im * q1) * u1);
+    five_point_emit<T, MODE>(d, u, k, b, out, omega, sc, vout, x, y, a0);
+    five_point_emit<T, MODE>(d, u, k, b, out, omega, sc, vout, x, y + 1, a1);
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < FP_ROWS; ++r) {
+    if (y + r >= ny) break;
+    five_point_emit<T, MODE>(d, u, k, b, out, omega, sc, vout, x, y + r,
+                             five_point_any(d, u, k, x, y + r));
+  }
+}
+
+inline unsigned five_point_blocks(int nx, int ny) {
+  const size_t nt = (size_t)((nx + BX - 1) / BX) * ((ny + BY * FP_ROWS - 1) / (BY * FP_ROWS));
+  return (unsigned)(8 * ((nt + 7) / 8));
 }
 
 // Wide (5x5 / 7x7) stencil with the ghost-extended input tile staged in LDS.
@@ -1076,11 +1088,11 @@ static unsigned wide_blocks(int nx, int ny) {
 template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
                           cx<T>* out, T omega, hipStream_t s) {
-  const dim3 g(xcd_blocks(d.nx, d.ny)), blk(BX, BY);
+  const dim3 g(five_point_blocks(d.nx, d.ny)), blk(BX, BY);
   const dim3 gw(wide_blocks(d.nx, d.ny));
 #define HM_ST(R, M)                                                                           \
-  if constexpr (R == 1) k_stencil<T, R, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega, nullptr,    \
-                                                            nullptr);                          \
+  if constexpr (R == 1) k_five_point<T, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega, nullptr,    \
+                                                             nullptr);                         \
   else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega, nullptr, nullptr)
 #define HM_STR(R)                              \
   if (mode == ST_APPLY) HM_ST(R, ST_APPLY);    \
@@ -1098,10 +1110,10 @@ hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T*
 template <typename T>
 hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k, const c128* scal,
                                  cx<T>* vout, cx<T>* out, hipStream_t s) {
-  const dim3 g(xcd_blocks(d.nx, d.ny)), blk(BX, BY);
+  const dim3 g(five_point_blocks(d.nx, d.ny)), blk(BX, BY);
   const dim3 gw(wide_blocks(d.nx, d.ny));
   if (d.R == 1)
-    k_stencil<T, 1, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
+    k_five_point<T, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
   else if (d.R == 2)
     k_wide_tiled<T, 2, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
   else if (d.R == 3)
