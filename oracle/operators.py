@@ -102,6 +102,40 @@ def five_point(nx, ny, H, k, sigma, scale=1.0, bc=SOMMERFELD):
                          shape=(N, N)).tocsr()
 
 
+def five_point_rows(nx, ny, H, k, sigma, rows, x, scale=1.0, bc=SOMMERFELD):
+    """Selected rows of five_point(...) @ x, each computed from its definition
+    (the stencil with the ghost of eq. ghost_sommerfeld, or the Dirichlet rule
+    of reading R24) without assembling the matrix: for grids too large to
+    assemble, where outputs are checked at sampled nodes."""
+    rows = np.asarray(rows, dtype=np.int64)
+    k = np.asarray(k).ravel()
+    x = np.asarray(x).ravel()
+    i, j = rows % nx, rows // nx
+    def val(ii, jj):
+        ok = (ii >= 0) & (ii < nx) & (jj >= 0) & (jj < ny)
+        out = np.zeros(len(rows), dtype=np.complex128)
+        out[ok] = x[(jj * nx + ii)[ok]]
+        return out, ok
+    uc = x[rows]
+    if bc == DIRICHLET:
+        bnd = (i == 0) | (j == 0) | (i == nx - 1) | (j == ny - 1)
+        s = 4.0 * uc
+        for di, dj in _NEIGHBOURS:
+            ii, jj = i + di, j + dj
+            v, _ = val(ii, jj)
+            nb = (ii == 0) | (jj == 0) | (ii == nx - 1) | (jj == ny - 1)
+            s = s - np.where(nb, 0.0, v)
+        inner = scale * (s / H**2 - sigma * k[rows] ** 2 * uc)
+        return np.where(bnd, scale * 4.0 / H**2 * uc, inner)
+    s = 4.0 * uc
+    for di, dj in _NEIGHBOURS:
+        v, ok = val(i + di, j + dj)
+        mirror, _ = val(i - di, j - dj)
+        ghost = mirror + 2j * H * k[rows] * uc          # u_g = u_m + 2 i H k_b u_b
+        s = s - np.where(ok, v, ghost)
+    return scale * (s / H**2 - sigma * k[rows] ** 2 * uc)
+
+
 def _five_point_dirichlet(nx, ny, H, k, sigma, scale):
     k = np.asarray(k, dtype=np.float64).ravel()
     m = interior_mask(nx, ny).astype(bool)

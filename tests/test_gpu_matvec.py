@@ -9,7 +9,10 @@ operator (Appendix B of the paper; the matvec comparison table).
   * hm_csr_spmv of a general CSR matrix (variable row lengths, empty rows)
     against a host product;
   * at the largest benchmarked workload (4097 x 4097) the two GPU forms against
-    the oracle's A @ x on every row.
+    the oracle's A @ x on every row;
+  * at the largest grid of the matvec sweep (16385 x 16385) the two forms
+    against each other on every row and against the oracle's per-row
+    evaluation on sampled rows.
 """
 import numpy as np
 import pytest
@@ -115,3 +118,32 @@ def test_matvec_forms_at_4097():
     torch.cuda.synchronize()
     assert relerr(host(v), ref) <= 1e-13
     assert relerr(host(y), ref) <= 1e-13
+
+
+def test_matvec_forms_at_16385_sampled():
+    """The largest grid of the matvec sweep (268,468,225 rows): both GPU forms
+    agree with each other on every row and with the oracle's per-row
+    evaluation on 4096 sampled rows plus the four corners and edge midpoints."""
+    nx = ny = 16385
+    n = nx * ny
+    h = 1.0 / (nx - 1)
+    rng = np.random.default_rng(11)
+    k = rng.uniform(20.0, 60.0, n)
+    x = np.empty(n, dtype=np.complex128)
+    x.real = rng.standard_normal(n)
+    x.imag = rng.standard_normal(n)
+    kd, xd = gpu(k), gpu(x)
+    v = hm.matfree_apply(nx, ny, h, kd, xd)
+    rp, ci, va = hm.csr_assemble(nx, ny, h, kd)
+    y = hm.csr_spmv(rp, ci, va, xd)
+    del rp, ci, va
+    torch.cuda.synchronize()
+    scale = float(v.abs().max())
+    assert float((v - y).abs().max()) <= 1e-13 * scale
+    rows = np.concatenate([rng.integers(0, n, 4096),
+                           [0, nx - 1, n - nx, n - 1, nx // 2, n - nx // 2 - 1,
+                            (ny // 2) * nx, (ny // 2) * nx + nx - 1]])
+    ref = op.five_point_rows(nx, ny, h, k, 1.0, rows, x)
+    idx = torch.from_numpy(rows).to(DEV)
+    assert np.max(np.abs(host(v[idx]) - ref)) <= 1e-13 * scale
+    assert np.max(np.abs(host(y[idx]) - ref)) <= 1e-13 * scale

@@ -135,3 +135,16 @@ def test_wide_stencil_consistent_with_scaled_continuous_operator():
     jj = np.arange(n3 * n3) // n3
     interior = (ii >= 3) & (ii <= n3 - 4) & (jj >= 3) & (jj <= n3 - 4)
     assert np.allclose(Wu[interior], cont[interior], rtol=2e-2)
+
+
+@pytest.mark.parametrize("bc", ["sommerfeld", "dirichlet"])
+def test_five_point_rows_match_the_assembled_matrix(bc):
+    """The per-row evaluation used for sampled checks on grids too large to
+    assemble equals the assembled operator on every row of a small grid."""
+    nx, ny, H = 11, 8, 0.1
+    rng = np.random.default_rng(3)
+    k = rng.uniform(1.0, 4.0, nx * ny)
+    x = rng.standard_normal(nx * ny) + 1j * rng.standard_normal(nx * ny)
+    A = op.five_point(nx, ny, H, k, 1.0 + 0.5j, bc=bc)
+    got = op.five_point_rows(nx, ny, H, k, 1.0 + 0.5j, np.arange(nx * ny), x, bc=bc)
+    assert np.allclose(got, A @ x, rtol=0, atol=1e-12 * np.abs(A @ x).max())
