@@ -13,6 +13,12 @@ dominant kernel class measured with HIP events inside the timed region, and
 the CPU oracle baseline (a bounded sample scaled to one solve).
 
     python bench.py [--steps K] [--warmup W] [--config I] [--no-mixed] [--no-cpu-baseline]
+
+Other measurements, each one JSON line of its own:
+    --serving      the request stream (Poisson arrivals, random media, 257^2..2049^2)
+    --matvec       matrix-free vs CSR product of the finest operator, 17^2..16385^2
+    --complexity   five-level MADP on the wedge stand-in at kh = 0.1745, 145x241..4609x7681
+    --variants     MADP-v3, W-cycle, fixed steps and deeper hierarchies on the bench workload
 """
 import argparse
 import json
@@ -46,7 +52,7 @@ def measured_traffic(kernel_class):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=1, help="workload index (0-3)")
     ap.add_argument("--no-mixed", action="store_true")
@@ -145,7 +151,14 @@ def cpu_baseline(problem, info, counts_l3):
         log("oracle level-1 V-cycle: %.2f s" % t_v1)
     n_l3 = len(counts_l3)
     t_solve = n_l3 * t_l3 + info["outer_iters"] * t_v1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cpu": model, "host_cores": os.cpu_count(),
             "sample": "oracle (FP64, SciPy CSR, 1 BLAS thread) on this workload: one "
                       "coarsest-level CSLP GMRES of %d steps (%.2f s) and one level-1 "
                       "V-cycle (%.2f s), projected to one solve as %d x GMRES + %d x "
@@ -473,6 +486,10 @@ def main():
                                      "GBps": v["GBps"],
                                      "timed_launches": v["launches"]}
                                  for c, v in classes.items()}
+        # algorithmic bytes of the timed classes (the Krylov passes, the stencils of
+        # the Krylov loops and the MGS steps) per solve over the solve time
+        est_bytes = sum(v["bytes"] for v in classes.values()) * TIMING_EVERY / args.steps
+        res["timed_classes_effective_GBps"] = est_bytes / (total / args.steps) / 1e9
     if not args.no_mixed:
         cfgm = hm.default_config(problem.nx, problem.ny, problem.h, precision=hm.HM_MIXED_FP32)
         probm = hm.create_problem(cfgm, k)
