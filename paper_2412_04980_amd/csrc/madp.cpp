@@ -408,9 +408,17 @@ static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& w
   LSQ lsq;
   lsq.init(maxit, beta);
   int steps = 0;
+  double est1 = -1.0, est2 = -1.0;   // estimates after steps j-1 and j-2
   if (maxit > 0) enqueue_step(0);
   for (int j = 0; j < maxit; ++j) {
-    if (j + 1 < maxit) enqueue_step(j + 1);
+    // Step j+1 goes in before step j's column is read, unless step j is expected
+    // to meet the tolerance: the estimates fall about geometrically, so
+    // est_j ~ est_{j-1}^2 / est_{j-2}.  A step enqueued past convergence is
+    // wasted work; a wrong guess only costs one wait for the host.
+    bool ahead = j + 1 < maxit;
+    if (ahead && tol >= 0 && est1 > 0 && est2 > 0 && est1 * (est1 / est2) <= tol * beta)
+      ahead = false;
+    if (ahead) enqueue_step(j + 1);
     HM_CHECK(hipEventSynchronize(p->col_ev[j & 1]));
     const c128* hc = p->host_H + (size_t)j * ld;
     const double est = lsq.add(j, hc);
@@ -418,6 +426,9 @@ static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& w
     const bool broke = hc[j + 1].re <= 1e-14 * beta;
     if (broke) break;
     if (tol >= 0 && est <= tol * beta) break;
+    if (!ahead && j + 1 < maxit) enqueue_step(j + 1);
+    est2 = est1;
+    est1 = est;
   }
   std::vector<c128> y;
   lsq.solve(steps, y);
