@@ -201,6 +201,41 @@ hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes,
 
 hm_status hm_destroy_problem(hm_problem* p);
 
+/* ---- Lockstep batches: several problems of one configuration per launch -----
+ * A batch holds nb (1..16) problems that share one configuration (grid, h,
+ * levels, precision, tolerances) but each have their own wavenumber field and
+ * right-hand side: several sources in one medium, or several media of one
+ * size.  hm_batch_solve runs MADP-FGMRES (Algorithm 1 with the Sec. 4.4
+ * configuration, as hm_fgmres_solve) for all members together: every kernel
+ * launch sweeps the same level for all members still iterating (one launch,
+ * members along the grid's third dimension), while each member keeps its own
+ * Krylov least-squares problems and stopping tests on the host.  A member that
+ * has met a tolerance drops out of the launches of that solve, so each
+ * member's result and step counts are exactly those of hm_fgmres_solve on its
+ * own, bit for bit.
+ *   hm_batch_workspace_bytes: device bytes for nb members (0 if cfg is invalid
+ *     or nb is out of range).
+ *   hm_create_batch: k_dev[i] is member i's nodal wavenumber (device, nx*ny
+ *     doubles, read during the call); workspace as for hm_create_problem, sized
+ *     by hm_batch_workspace_bytes.  Synchronises `stream`.  Errors as
+ *     hm_create_problem, plus HM_ERR_ARG for nb outside 1..16.
+ *   hm_batch_solve: b_dev[i], u_dev[i] are member i's right-hand side and
+ *     solution (device, nx*ny complex128, b_dev[i] != u_dev[i]); info: nb
+ *     records or NULL.  Returns HM_NOT_CONVERGED if any member misses the
+ *     tolerance (all solutions written).  Synchronises `stream`.
+ *   hm_batch_member: member i as a problem handle (counts, replay, timing;
+ *     the batch's kernel timing is kept by member 0), or NULL.  Owned by the
+ *     batch; it may also be solved on its own with hm_fgmres_solve.
+ *   hm_destroy_batch: frees the batch and its members, not the workspace. */
+typedef struct hm_batch hm_batch;
+size_t hm_batch_workspace_bytes(const hm_config* cfg, int nb);
+hm_status hm_create_batch(const hm_config* cfg, int nb, const double* const* k_dev,
+                          void* workspace, size_t workspace_bytes, void* stream, hm_batch** out);
+hm_status hm_batch_solve(hm_batch* bt, const void* const* b_dev, void* const* u_dev,
+                         hm_solve_info* info, void* stream);
+hm_problem* hm_batch_member(hm_batch* bt, int i);
+hm_status hm_destroy_batch(hm_batch* bt);
+
 /* ---- Matrix-free versus stored-matrix matvec (Appendix B, Table of the
  * matrix-free / CSR comparison) ----------------------------------------------
  * Both forms compute v = A u for the finest-level operator of eq. (helm

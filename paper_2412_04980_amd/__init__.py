@@ -13,6 +13,10 @@ the stream.  The entry points carry the names of the C ABI in include/helmdefl.h
     y = apply_operator(prob, level, which, x, sub=0)
     destroy_problem(prob)
 
+    bt = create_batch(cfg, [k0, k1, k2])     # one configuration, several media
+    us, infos = batch_solve(bt, [b0, b1, b2])  # lockstep: one launch per sweep
+    destroy_batch(bt)
+
 The library is loaded from libhelmdefl.so next to this file (built by
 paper_2412_04980_amd.build); importing this module fails loudly when it is
 missing.  There is no CPU fallback.
@@ -45,7 +49,10 @@ EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_
             "hm_fgmres_solve", "hm_apply_operator", "hm_level_shape", "hm_set_replay",
             "hm_get_counts", "hm_reset_counts", "hm_set_timing", "hm_get_timing",
             "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
-            "hm_status_string", "hm_last_error"]
+            "hm_batch_workspace_bytes", "hm_create_batch", "hm_batch_solve", "hm_batch_member",
+            "hm_destroy_batch", "hm_status_string", "hm_last_error"]
+
+MAX_BATCH = 16
 
 
 class HmConfig(ctypes.Structure):
@@ -108,6 +115,13 @@ def _load():
         "hm_matfree_apply": (I, [I, I, D, P, P, P, P]),
         "hm_csr_assemble": (I, [I, I, D, P, P, P, P, P]),
         "hm_csr_spmv": (I, [I, P, P, P, P, P, P]),
+        "hm_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(HmConfig), I]),
+        "hm_create_batch": (I, [ctypes.POINTER(HmConfig), I, ctypes.POINTER(P), P,
+                                ctypes.c_size_t, P, ctypes.POINTER(P)]),
+        "hm_batch_solve": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P),
+                               ctypes.POINTER(HmSolveInfo), P]),
+        "hm_batch_member": (P, [P, I]),
+        "hm_destroy_batch": (I, [P]),
         "hm_status_string": (ctypes.c_char_p, [I]),
         "hm_last_error": (ctypes.c_char_p, []),
     }
@@ -155,16 +169,18 @@ def workspace_bytes(cfg):
 class Problem:
     """A problem hierarchy resident in a caller-owned (torch) workspace."""
 
-    def __init__(self, handle, cfg, workspace, device):
+    def __init__(self, handle, cfg, workspace, device, owned=True):
         self.handle = handle
         self.cfg = cfg
         self.workspace = workspace
         self.device = device
+        self.owned = owned          # False: a batch member, freed with its batch
         self.N = cfg.nx * cfg.ny
 
     def close(self):
         if self.handle:
-            _lib.hm_destroy_problem(self.handle)
+            if self.owned:
+                _lib.hm_destroy_problem(self.handle)
             self.handle = None
             self.workspace = None
 
@@ -335,6 +351,83 @@ def csr_spmv(row_ptr, col_idx, vals, x, out=None, stream=None):
 
 def destroy_problem(prob):
     prob.close()
+
+
+def batch_workspace_bytes(cfg, nb):
+    n = _lib.hm_batch_workspace_bytes(ctypes.byref(cfg), int(nb))
+    if n == 0:
+        raise HelmDeflError(HM_ERR_ARG, _lib.hm_last_error().decode())
+    return n
+
+
+class BatchProblem:
+    """nb problems of one configuration solved in lockstep (hm_create_batch)."""
+
+    def __init__(self, handle, cfg, nb, workspace, device):
+        self.handle = handle
+        self.cfg = cfg
+        self.nb = nb
+        self.workspace = workspace
+        self.device = device
+        self.N = cfg.nx * cfg.ny
+        self.members = [Problem(ctypes.c_void_p(_lib.hm_batch_member(handle, i)), cfg, workspace,
+                                device, owned=False) for i in range(nb)]
+
+    def close(self):
+        if self.handle:
+            for m in self.members:
+                m.close()
+            _lib.hm_destroy_batch(self.handle)
+            self.handle = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_batch(cfg, ks, stream=None, workspace=None):
+    """ks: one nodal wavenumber per member (float64 GPU tensors, nx*ny each)."""
+    nb = len(ks)
+    n = cfg.nx * cfg.ny
+    ks = [_f64(k.contiguous(), n, "k[%d]" % i) for i, k in enumerate(ks)]
+    nbytes = batch_workspace_bytes(cfg, nb)
+    if workspace is None:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=ks[0].device)
+    base = workspace.data_ptr()
+    off = (-base) % 256
+    arr = (ctypes.c_void_p * nb)(*[k.data_ptr() for k in ks])
+    handle = ctypes.c_void_p()
+    _check(_lib.hm_create_batch(ctypes.byref(cfg), nb, arr, ctypes.c_void_p(base + off),
+                                ctypes.c_size_t(workspace.numel() - off), _stream(stream),
+                                ctypes.byref(handle)))
+    return BatchProblem(handle, cfg, nb, workspace, ks[0].device)
+
+
+def batch_solve(bt, bs, outs=None, stream=None):
+    """Solves member i's system with right-hand side bs[i]; returns (solutions,
+    infos), infos[i] as for fgmres_solve with the batch status under "status"."""
+    if len(bs) != bt.nb or (outs is not None and len(outs) != bt.nb):
+        raise ValueError("need one right-hand side (and output) per member")
+    bs = [_c128(b, bt.N, "b[%d]" % i) for i, b in enumerate(bs)]
+    us = [torch.empty_like(b) for b in bs] if outs is None else \
+        [_c128(u, bt.N, "out[%d]" % i) for i, u in enumerate(outs)]
+    barr = (ctypes.c_void_p * bt.nb)(*[b.data_ptr() for b in bs])
+    uarr = (ctypes.c_void_p * bt.nb)(*[u.data_ptr() for u in us])
+    infos = (HmSolveInfo * bt.nb)()
+    st = _check(_lib.hm_batch_solve(bt.handle, barr, uarr, infos, _stream(stream)))
+    out = []
+    for i in range(bt.nb):
+        d = infos[i].as_dict()
+        d["status"] = st
+        out.append(d)
+    return us, out
+
+
+def destroy_batch(bt):
+    bt.close()
 
 
 def status_string(status):

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -24,6 +25,24 @@ inline unsigned blocks1d(size_t n) {
   size_t b = (n + NT - 1) / NT;
   return (unsigned)(b > 0 ? b : 1);
 }
+
+// Grid of a batched launch: the members are the z dimension.
+inline dim3 zgrid(unsigned x, const Batch& z) { return dim3(x, 1, (unsigned)z.n); }
+inline dim3 zgrid(dim3 g, const Batch& z) { return dim3(g.x, g.y, (unsigned)z.n); }
+
+// The member a block works on: block z takes member slot[z], whose buffers lie
+// slot * stride bytes after member 0's (dz on the device, hz in pinned host
+// memory).  Null pointers (absent operands) stay null.
+// The offset is applied as byte-pointer arithmetic on the argument itself (no
+// integer round trip), so the compiler still sees a global, non-aliasing
+// pointer: global (not flat) memory instructions and scalar loads of uniform data.
+template <typename P>
+__device__ __forceinline__ P* at_member(P* p, long long stride, const Batch& z) {
+  using C = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  const long long off = (long long)z.slot[blockIdx.z] * stride;
+  return p ? reinterpret_cast<P*>(reinterpret_cast<C*>(p) + off) : p;
+}
+#define HM_MEMBER(ptr) ptr = at_member(ptr, z.dz, z)
 
 // Ghost-extended value at grid position (x, y), which may lie outside:
 // inside -> u, k^2;  one step out in exactly one direction -> Sommerfeld ghost
@@ -236,9 +255,11 @@ __global__ void __launch_bounds__(NT) k_five_point(OpDesc<T> d, const cx<T>* __r
                                                    const cx<T>* __restrict__ b,
                                                    cx<T>* __restrict__ out, T omega,
                                                    const c128* __restrict__ scal,
-                                                   cx<T>* __restrict__ vout) {
+                                                   cx<T>* __restrict__ vout, Batch z) {
   int tx, ty;
   if (!xcd_tile((d.nx + BX - 1) / BX, (d.ny + BY * FP_ROWS - 1) / (BY * FP_ROWS), tx, ty)) return;
+  HM_MEMBER(u); HM_MEMBER(k); HM_MEMBER(b); HM_MEMBER(out); HM_MEMBER(scal); HM_MEMBER(vout);
+  if (z.use_omega) omega = (T)z.omega[blockIdx.z];
   const int nx = d.nx, ny = d.ny;
   const int x = tx * BX + threadIdx.x;
   const int y = ty * BY * FP_ROWS + threadIdx.y * FP_ROWS;
@@ -289,7 +310,7 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
                                                    const cx<T>* __restrict__ b,
                                                    cx<T>* __restrict__ out, T omega,
                                                    const c128* __restrict__ scal,
-                                                   cx<T>* __restrict__ vout) {
+                                                   cx<T>* __restrict__ vout, Batch z) {
   constexpr int W = 2 * R + 1;
   constexpr int SX = WT_X + 2 * R;
   constexpr int SY = WT_Y + 2 * R;
@@ -302,6 +323,8 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
   const int per = (ntx * nty + 7) / 8;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= ntx * nty) return;
+  HM_MEMBER(u); HM_MEMBER(k); HM_MEMBER(b); HM_MEMBER(out); HM_MEMBER(scal); HM_MEMBER(vout);
+  if (z.use_omega) omega = (T)z.omega[blockIdx.z];
   const int x0 = (tile % ntx) * WT_X, y0 = (tile / ntx) * WT_Y;
   const int tid = threadIdx.y * BX + threadIdx.x;
   T sc = T(1);
@@ -401,10 +424,12 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
 template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_jacobi0(OpDesc<T> d, const T* __restrict__ k,
                                                 const cx<T>* __restrict__ b, cx<T>* __restrict__ x_out,
-                                                T omega) {
+                                                T omega, Batch z) {
   const int x = blockIdx.x * BX + threadIdx.x;
   const int y = blockIdx.y * BY + threadIdx.y;
   if (x >= d.nx || y >= d.ny) return;
+  HM_MEMBER(k); HM_MEMBER(b); HM_MEMBER(x_out);
+  if (z.use_omega) omega = (T)z.omega[blockIdx.z];
   const size_t p = (size_t)y * d.nx + x;
   cx<T> dg;
   if constexpr (R == 1) {
@@ -503,9 +528,10 @@ __device__ __forceinline__ cx<To> hfilter(const FinePair<Ti>& r, int lane) {
 template <typename Ti, typename To, int H>
 __global__ void __launch_bounds__(NT) k_restrict_rows(const cx<Ti>* __restrict__ f, int nxf, int nyf,
                                                       cx<To>* __restrict__ c, int nxc, int nyc,
-                                                      int dir) {
+                                                      int dir, Batch z) {
   int tx, ty;
   if (!xcd_tile((nxc + TCOLS - 1) / TCOLS, (nyc + TR - 1) / TR, tx, ty)) return;
+  HM_MEMBER(f); HM_MEMBER(c);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int I = tx * TCOLS + w * 64 + lane;
   const int J0 = ty * TR;
@@ -579,9 +605,10 @@ __device__ __forceinline__ void hinterp(const cx<Ti>& own, const cx<Ti>& edge, i
 template <typename Ti, typename To, bool ZDEF>
 __global__ void __launch_bounds__(NT) k_prolong_rows(const cx<Ti>* __restrict__ c, int nxc, int nyc,
                                                      cx<To>* __restrict__ f, int nxf, int nyf,
-                                                     int dir) {
+                                                     int dir, Batch z) {
   int tx, ty;
   if (!xcd_tile((nxc + TCOLS - 1) / TCOLS, (nyc + TR - 1) / TR, tx, ty)) return;
+  HM_MEMBER(c); HM_MEMBER(f);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int I = tx * TCOLS + w * 64 + lane;
   const int J0 = ty * TR;
@@ -661,23 +688,27 @@ __global__ void __launch_bounds__(NT) k_convert_real(const Ti* __restrict__ a, T
 
 template <typename Ti, typename To>
 __global__ void __launch_bounds__(NT) k_convert(const cx<Ti>* __restrict__ a, cx<To>* __restrict__ b,
-                                                size_t n) {
+                                                size_t n, Batch z) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  HM_MEMBER(a); HM_MEMBER(b);
   if (i < n) b[i] = cvt<To>(a[i]);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_add(const cx<T>* __restrict__ a, const cx<T>* __restrict__ b,
-                                            cx<T>* __restrict__ out, size_t n) {
+                                            cx<T>* __restrict__ out, size_t n, Batch z) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  HM_MEMBER(a); HM_MEMBER(b); HM_MEMBER(out);
   if (i < n) out[i] = a[i] + b[i];
 }
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_scale_dev(const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
-                                                  const c128* __restrict__ scal, int inv, size_t n) {
+                                                  const c128* __restrict__ scal, int inv, size_t n,
+                                                  Batch z) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
+  HM_MEMBER(x); HM_MEMBER(y); HM_MEMBER(scal);
   const c128 sc = scal[0];
   if (inv) {
     const T s = (T)(1.0 / sc.re);
@@ -688,17 +719,22 @@ __global__ void __launch_bounds__(NT) k_scale_dev(const cx<T>* __restrict__ x, c
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_zero(cx<T>* __restrict__ x, size_t n) {
+__global__ void __launch_bounds__(NT) k_zero(cx<T>* __restrict__ x, size_t n, Batch z) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  HM_MEMBER(x);
   if (i < n) x[i] = mk(T(0), T(0));
 }
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_combine(const cx<T>* __restrict__ V, size_t ldv, int m,
-                                                const c128* __restrict__ coef, double sign,
-                                                cx<T>* __restrict__ out, int accumulate, size_t n) {
+                                                const c128* __restrict__ coef, size_t coef_ld,
+                                                double sign, cx<T>* __restrict__ out,
+                                                int accumulate, size_t n, Batch z) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
+  HM_MEMBER(V); HM_MEMBER(out);
+  coef += (size_t)z.slot[blockIdx.z] * coef_ld;
+  if (m < 0) m = z.cnt[blockIdx.z];
   double re = 0, im = 0;
 #pragma unroll 8
   for (int j = 0; j < m; ++j) {
@@ -719,9 +755,11 @@ __global__ void __launch_bounds__(NT) k_combine(const cx<T>* __restrict__ V, siz
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_dense_matvec(const cx<T>* __restrict__ A, int n,
-                                                     const cx<T>* __restrict__ x, cx<T>* __restrict__ y) {
+                                                     const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
+                                                     Batch z) {
   const int i = blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
+  HM_MEMBER(A); HM_MEMBER(x); HM_MEMBER(y);
   double re = 0, im = 0;
   for (int j = 0; j < n; ++j) {
     const cx<T> a = A[(size_t)i * n + j];
@@ -789,8 +827,9 @@ template <typename T>
 __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, size_t ldv, int m,
                                                  const cx<T>* __restrict__ w, size_t n, size_t clen,
                                                  c128* __restrict__ partials, int nchunks,
-                                                 int reverse) {
+                                                 int reverse, Batch z) {
   __shared__ double sh[NT / 64][2 * G];
+  HM_MEMBER(V); HM_MEMBER(w); HM_MEMBER(partials);
   // XCD-aware block order: workgroups are dispatched round-robin over the 8
   // XCDs, so blocks b, b + 8, b + 16, ... share an L2.  All groups of one chunk
   // go to the same XCD in consecutive order: the chunk of w comes from HBM once
@@ -844,8 +883,10 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
 // out[i] = sum_c partials[i*nchunks + c]; sqrt_re: out = sqrt(re)
 __global__ void __launch_bounds__(NT) k_final(const c128* __restrict__ partials, int nchunks,
                                               c128* __restrict__ out, int sqrt_re,
-                                              c128* __restrict__ host_out) {
+                                              c128* __restrict__ host_out, Batch z) {
   __shared__ double sh[2 * NT / 64];
+  HM_MEMBER(partials); HM_MEMBER(out);
+  host_out = at_member(host_out, z.hz, z);
   const int i = blockIdx.x;
   double re = 0, im = 0;
   for (int c = threadIdx.x; c < nchunks; c += NT) {
@@ -865,8 +906,9 @@ template <typename T>
 __global__ void __launch_bounds__(NT) k_mgs_step(cx<T>* __restrict__ w, const cx<T>* __restrict__ prev,
                                                  const c128* __restrict__ hprev,
                                                  const cx<T>* __restrict__ next, size_t n, size_t clen,
-                                                 c128* __restrict__ partials) {
+                                                 c128* __restrict__ partials, Batch z) {
   __shared__ double sh[2 * NT / 64];
+  HM_MEMBER(w); HM_MEMBER(prev); HM_MEMBER(hprev); HM_MEMBER(next); HM_MEMBER(partials);
   const size_t lo = (size_t)blockIdx.x * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   double re = 0, im = 0;
@@ -896,8 +938,10 @@ template <typename T>
 __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, const cx<T>* __restrict__ V,
                                                         size_t ldv, int m, const c128* __restrict__ h,
                                                         size_t n, size_t clen,
-                                                        c128* __restrict__ partials, int reverse) {
+                                                        c128* __restrict__ partials, int reverse,
+                                                        Batch z) {
   __shared__ double sh[2 * NT / 64];
+  HM_MEMBER(w); HM_MEMBER(V); HM_MEMBER(h); HM_MEMBER(partials);
   const int chunk = reverse ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
@@ -935,8 +979,9 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_norm2(const cx<T>* __restrict__ x, size_t n, size_t clen,
-                                              c128* __restrict__ partials) {
+                                              c128* __restrict__ partials, Batch z) {
   __shared__ double sh[2 * NT / 64];
+  HM_MEMBER(x); HM_MEMBER(partials);
   const size_t lo = (size_t)blockIdx.x * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   double acc = 0;
@@ -1087,13 +1132,13 @@ static unsigned wide_blocks(int nx, int ny) {
 
 template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
-                          cx<T>* out, T omega, hipStream_t s) {
-  const dim3 g(five_point_blocks(d.nx, d.ny)), blk(BX, BY);
-  const dim3 gw(wide_blocks(d.nx, d.ny));
+                          cx<T>* out, T omega, hipStream_t s, const Batch& z) {
+  const dim3 g = zgrid(five_point_blocks(d.nx, d.ny), z), blk(BX, BY);
+  const dim3 gw = zgrid(wide_blocks(d.nx, d.ny), z);
 #define HM_ST(R, M)                                                                           \
   if constexpr (R == 1) k_five_point<T, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega, nullptr,    \
-                                                             nullptr);                         \
-  else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega, nullptr, nullptr)
+                                                             nullptr, z);                      \
+  else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega, nullptr, nullptr, z)
 #define HM_STR(R)                              \
   if (mode == ST_APPLY) HM_ST(R, ST_APPLY);    \
   else if (mode == ST_RESID) HM_ST(R, ST_RESID); \
@@ -1109,15 +1154,15 @@ hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T*
 
 template <typename T>
 hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k, const c128* scal,
-                                 cx<T>* vout, cx<T>* out, hipStream_t s) {
-  const dim3 g(five_point_blocks(d.nx, d.ny)), blk(BX, BY);
-  const dim3 gw(wide_blocks(d.nx, d.ny));
+                                 cx<T>* vout, cx<T>* out, hipStream_t s, const Batch& z) {
+  const dim3 g = zgrid(five_point_blocks(d.nx, d.ny), z), blk(BX, BY);
+  const dim3 gw = zgrid(wide_blocks(d.nx, d.ny), z);
   if (d.R == 1)
-    k_five_point<T, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
+    k_five_point<T, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout, z);
   else if (d.R == 2)
-    k_wide_tiled<T, 2, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
+    k_wide_tiled<T, 2, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout, z);
   else if (d.R == 3)
-    k_wide_tiled<T, 3, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout);
+    k_wide_tiled<T, 3, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout, z);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1125,43 +1170,48 @@ hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k,
 
 template <typename T>
 hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x, T omega,
-                          hipStream_t s) {
-  const dim3 g = grid2d(d.nx, d.ny), blk(BX, BY);
-  if (d.R == 1) k_jacobi0<T, 1><<<g, blk, 0, s>>>(d, k, b, x, omega);
-  else if (d.R == 2) k_jacobi0<T, 2><<<g, blk, 0, s>>>(d, k, b, x, omega);
-  else if (d.R == 3) k_jacobi0<T, 3><<<g, blk, 0, s>>>(d, k, b, x, omega);
+                          hipStream_t s, const Batch& z) {
+  const dim3 g = zgrid(grid2d(d.nx, d.ny), z), blk(BX, BY);
+  if (d.R == 1) k_jacobi0<T, 1><<<g, blk, 0, s>>>(d, k, b, x, omega, z);
+  else if (d.R == 2) k_jacobi0<T, 2><<<g, blk, 0, s>>>(d, k, b, x, omega, z);
+  else if (d.R == 3) k_jacobi0<T, 3><<<g, blk, 0, s>>>(d, k, b, x, omega, z);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <typename Ti, typename To>
 hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, int dir,
-                             hipStream_t s) {
+                             hipStream_t s, const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_restrict_rows<Ti, To, 2><<<sep_blocks(nxc, nyc), NT, 0, s>>>(f, nxf, nyf, c, nxc, nyc, dir);
+  k_restrict_rows<Ti, To, 2><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(f, nxf, nyf, c, nxc,
+                                                                           nyc, dir, z);
   return hipGetLastError();
 }
 
 template <typename Ti, typename To>
 hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, int dir,
-                            hipStream_t s) {
+                            hipStream_t s, const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_prolong_rows<Ti, To, true><<<sep_blocks(nxc, nyc), NT, 0, s>>>(c, nxc, nyc, f, nxf, nyf, dir);
+  k_prolong_rows<Ti, To, true><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(c, nxc, nyc, f, nxf,
+                                                                             nyf, dir, z);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, int dir, hipStream_t s) {
+hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, int dir, hipStream_t s,
+                              const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_restrict_rows<T, T, 1><<<sep_blocks(nxc, nyc), NT, 0, s>>>(f, nxf, nyf, c, nxc, nyc, dir);
+  k_restrict_rows<T, T, 1><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(f, nxf, nyf, c, nxc, nyc,
+                                                                         dir, z);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, int dir,
-                                       hipStream_t s) {
+                                       hipStream_t s, const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_prolong_rows<T, T, false><<<sep_blocks(nxc, nyc), NT, 0, s>>>(c, nxc, nyc, f, nxf, nyf, dir);
+  k_prolong_rows<T, T, false><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(c, nxc, nyc, f, nxf,
+                                                                            nyf, dir, z);
   return hipGetLastError();
 }
 
@@ -1179,40 +1229,44 @@ hipError_t launch_convert_real(const Ti* a, To* b, size_t n, hipStream_t s) {
 }
 
 template <typename Ti, typename To>
-hipError_t launch_convert(const cx<Ti>* a, cx<To>* b, size_t n, hipStream_t s) {
-  k_convert<Ti, To><<<blocks1d(n), NT, 0, s>>>(a, b, n);
+hipError_t launch_convert(const cx<Ti>* a, cx<To>* b, size_t n, hipStream_t s, const Batch& z) {
+  k_convert<Ti, To><<<zgrid(blocks1d(n), z), NT, 0, s>>>(a, b, n, z);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_add(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s) {
-  k_add<T><<<blocks1d(n), NT, 0, s>>>(a, b, out, n);
+hipError_t launch_add(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s,
+                      const Batch& z) {
+  k_add<T><<<zgrid(blocks1d(n), z), NT, 0, s>>>(a, b, out, n, z);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_scale_dev(const cx<T>* x, cx<T>* y, const c128* scal, int inv, size_t n,
-                            hipStream_t s) {
-  k_scale_dev<T><<<blocks1d(n), NT, 0, s>>>(x, y, scal, inv, n);
+                            hipStream_t s, const Batch& z) {
+  k_scale_dev<T><<<zgrid(blocks1d(n), z), NT, 0, s>>>(x, y, scal, inv, n, z);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_zero(cx<T>* x, size_t n, hipStream_t s) {
-  k_zero<T><<<blocks1d(n), NT, 0, s>>>(x, n);
+hipError_t launch_zero(cx<T>* x, size_t n, hipStream_t s, const Batch& z) {
+  k_zero<T><<<zgrid(blocks1d(n), z), NT, 0, s>>>(x, n, z);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, double sign,
-                          cx<T>* out, int accumulate, size_t n, hipStream_t s) {
-  k_combine<T><<<blocks1d(n), NT, 0, s>>>(V, ldv, m, coef, sign, out, accumulate, n);
+hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, size_t coef_ld,
+                          double sign, cx<T>* out, int accumulate, size_t n, hipStream_t s,
+                          const Batch& z) {
+  k_combine<T><<<zgrid(blocks1d(n), z), NT, 0, s>>>(V, ldv, m, coef, coef_ld, sign, out, accumulate,
+                                                    n, z);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s) {
-  k_dense_matvec<T><<<blocks1d((size_t)n), NT, 0, s>>>(A, n, x, y);
+hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s,
+                               const Batch& z) {
+  k_dense_matvec<T><<<zgrid(blocks1d((size_t)n), z), NT, 0, s>>>(A, n, x, y, z);
   return hipGetLastError();
 }
 
@@ -1255,20 +1309,20 @@ static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
 
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
-                                   RedBuf rb, int reverse, hipStream_t s) {
+                                   RedBuf rb, int reverse, hipStream_t s, const Batch& z) {
   if (m <= 0) return hipSuccess;
   const int nch = multidot_chunks(n, m, rb);
   const size_t clen = multidot_chunk_len(n, m);
-  k_multidot<T><<<((m + G - 1) / G) * nch, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch,
-                                                       reverse);
+  k_multidot<T><<<zgrid(((m + G - 1) / G) * nch, z), NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials,
+                                                                 nch, reverse, z);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s,
-                                 c128* host_out) {
+                                 c128* host_out, const Batch& z) {
   if (m <= 0) return hipSuccess;
-  k_final<<<m, NT, 0, s>>>(rb.partials, multidot_chunks(n, m, rb), out, 0, host_out);
+  k_final<<<zgrid(m, z), NT, 0, s>>>(rb.partials, multidot_chunks(n, m, rb), out, 0, host_out, z);
   return hipGetLastError();
 }
 
@@ -1282,10 +1336,11 @@ hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, si
 
 template <typename T>
 hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const cx<T>* next,
-                           size_t n, RedBuf rb, c128* out, hipStream_t s) {
+                           size_t n, RedBuf rb, c128* out, hipStream_t s, c128* host_out,
+                           const Batch& z) {
   const size_t clen = chunk_len(n, rb.nchunks);
-  k_mgs_step<T><<<rb.nchunks, NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials);
-  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, next ? 0 : 1, nullptr);
+  k_mgs_step<T><<<zgrid(rb.nchunks, z), NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials, z);
+  k_final<<<zgrid(1, z), NT, 0, s>>>(rb.partials, rb.nchunks, out, next ? 0 : 1, host_out, z);
   return hipGetLastError();
 }
 
@@ -1307,16 +1362,18 @@ static int update_chunks(size_t n, const RedBuf& rb) {
 
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
-                                     size_t n, RedBuf rb, int reverse, hipStream_t s) {
+                                     size_t n, RedBuf rb, int reverse, hipStream_t s,
+                                     const Batch& z) {
   const int nch = update_chunks(n, rb);
   const size_t clen = update_chunk_len(n);
-  k_cgs_update_norm<T><<<nch, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, reverse);
+  k_cgs_update_norm<T><<<zgrid(nch, z), NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, reverse,
+                                                    z);
   return hipGetLastError();
 }
 
 hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,
-                                    c128* host_out) {
-  k_final<<<1, NT, 0, s>>>(rb.partials, update_chunks(n, rb), out, 1, host_out);
+                                    c128* host_out, const Batch& z) {
+  k_final<<<zgrid(1, z), NT, 0, s>>>(rb.partials, update_chunks(n, rb), out, 1, host_out, z);
   return hipGetLastError();
 }
 
@@ -1329,10 +1386,11 @@ hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, c
 }
 
 template <typename T>
-hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream_t s) {
+hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream_t s,
+                       c128* host_out, const Batch& z) {
   const size_t clen = chunk_len(n, rb.nchunks);
-  k_norm2<T><<<rb.nchunks, NT, 0, s>>>(x, n, clen, rb.partials);
-  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 1, nullptr);
+  k_norm2<T><<<zgrid(rb.nchunks, z), NT, 0, s>>>(x, n, clen, rb.partials, z);
+  k_final<<<zgrid(1, z), NT, 0, s>>>(rb.partials, rb.nchunks, out, 1, host_out, z);
   return hipGetLastError();
 }
 
@@ -1346,50 +1404,59 @@ hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipS
 hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s) {
   const size_t clen = chunk_len(n, rb.nchunks);
   k_check_k<<<rb.nchunks, NT, 0, s>>>(k, n, clen, rb.partials);
-  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 0, nullptr);
+  k_final<<<1, NT, 0, s>>>(rb.partials, rb.nchunks, out, 0, nullptr, Batch());
   return hipGetLastError();
 }
 
 // ---- explicit instantiations ----------------------------------------------------
 #define HM_INST_T(T)                                                                              \
   template hipError_t launch_stencil<T>(const OpDesc<T>&, int, const cx<T>*, const T*,              \
-                                        const cx<T>*, cx<T>*, T, hipStream_t);                       \
+                                        const cx<T>*, cx<T>*, T, hipStream_t, const Batch&);         \
   template hipError_t launch_jacobi0<T>(const OpDesc<T>&, const T*, const cx<T>*, cx<T>*, T,         \
-                                        hipStream_t);                                               \
-  template hipError_t launch_restrict_fw<T>(const cx<T>*, int, int, cx<T>*, int, hipStream_t);     \
+                                        hipStream_t, const Batch&);                                 \
+  template hipError_t launch_restrict_fw<T>(const cx<T>*, int, int, cx<T>*, int, hipStream_t,      \
+                                            const Batch&);                                          \
   template hipError_t launch_prolong_bilinear_add<T>(const cx<T>*, int, int, cx<T>*, int,         \
-                                                     hipStream_t);                                  \
-  template hipError_t launch_add<T>(const cx<T>*, const cx<T>*, cx<T>*, size_t, hipStream_t);      \
+                                                     hipStream_t, const Batch&);                    \
+  template hipError_t launch_add<T>(const cx<T>*, const cx<T>*, cx<T>*, size_t, hipStream_t,       \
+                                    const Batch&);                                                  \
   template hipError_t launch_scale_dev<T>(const cx<T>*, cx<T>*, const c128*, int, size_t,          \
-                                          hipStream_t);                                             \
-  template hipError_t launch_zero<T>(cx<T>*, size_t, hipStream_t);                                 \
-  template hipError_t launch_dense_matvec<T>(const cx<T>*, int, const cx<T>*, cx<T>*, hipStream_t); \
-  template hipError_t launch_combine<T>(const cx<T>*, size_t, int, const c128*, double, cx<T>*,    \
-                                        int, size_t, hipStream_t);                                  \
+                                          hipStream_t, const Batch&);                               \
+  template hipError_t launch_zero<T>(cx<T>*, size_t, hipStream_t, const Batch&);                   \
+  template hipError_t launch_dense_matvec<T>(const cx<T>*, int, const cx<T>*, cx<T>*, hipStream_t, \
+                                             const Batch&);                                         \
+  template hipError_t launch_combine<T>(const cx<T>*, size_t, int, const c128*, size_t, double,    \
+                                        cx<T>*, int, size_t, hipStream_t, const Batch&);            \
   template hipError_t launch_multidot<T>(const cx<T>*, size_t, int, const cx<T>*, size_t, RedBuf,  \
                                          c128*, hipStream_t);                                       \
   template hipError_t launch_multidot_partial<T>(const cx<T>*, size_t, int, const cx<T>*, size_t,  \
-                                                 RedBuf, int, hipStream_t);                         \
-  template hipError_t launch_multidot_final<T>(int, size_t, RedBuf, c128*, hipStream_t, c128*);           \
+                                                 RedBuf, int, hipStream_t, const Batch&);           \
+  template hipError_t launch_multidot_final<T>(int, size_t, RedBuf, c128*, hipStream_t, c128*,     \
+                                               const Batch&);                                       \
   template hipError_t launch_cgs_update_partial<T>(cx<T>*, const cx<T>*, size_t, int, const c128*, \
-                                                   size_t, RedBuf, int, hipStream_t);               \
+                                                   size_t, RedBuf, int, hipStream_t, const Batch&); \
   template hipError_t launch_stencil_scaled<T>(const OpDesc<T>&, const cx<T>*, const T*,            \
-                                               const c128*, cx<T>*, cx<T>*, hipStream_t);           \
+                                               const c128*, cx<T>*, cx<T>*, hipStream_t,            \
+                                               const Batch&);                                       \
   template hipError_t launch_mgs_step<T>(cx<T>*, const cx<T>*, const c128*, const cx<T>*, size_t,  \
-                                         RedBuf, c128*, hipStream_t);                               \
+                                         RedBuf, c128*, hipStream_t, c128*, const Batch&);          \
   template hipError_t launch_cgs_update_norm<T>(cx<T>*, const cx<T>*, size_t, int, const c128*,    \
                                                 size_t, RedBuf, c128*, hipStream_t);                \
-  template hipError_t launch_norm<T>(const cx<T>*, size_t, RedBuf, c128*, hipStream_t);
+  template hipError_t launch_norm<T>(const cx<T>*, size_t, RedBuf, c128*, hipStream_t, c128*,      \
+                                     const Batch&);
 HM_INST_T(float)
 HM_INST_T(double)
 #undef HM_INST_T
 
 #define HM_INST_2(A, B)                                                                          \
-  template hipError_t launch_restrict_z<A, B>(const cx<A>*, int, int, cx<B>*, int, hipStream_t); \
-  template hipError_t launch_prolong_z<A, B>(const cx<A>*, int, int, cx<B>*, int, hipStream_t);  \
+  template hipError_t launch_restrict_z<A, B>(const cx<A>*, int, int, cx<B>*, int, hipStream_t,  \
+                                              const Batch&);                                     \
+  template hipError_t launch_prolong_z<A, B>(const cx<A>*, int, int, cx<B>*, int, hipStream_t,   \
+                                             const Batch&);                                      \
   template hipError_t launch_inject<A, B>(const A*, int, int, B*, hipStream_t);                 \
   template hipError_t launch_convert_real<A, B>(const A*, B*, size_t, hipStream_t);             \
-  template hipError_t launch_convert<A, B>(const cx<A>*, cx<B>*, size_t, hipStream_t);
+  template hipError_t launch_convert<A, B>(const cx<A>*, cx<B>*, size_t, hipStream_t,           \
+                                           const Batch&);
 HM_INST_2(float, float)
 HM_INST_2(double, double)
 HM_INST_2(float, double)

@@ -37,24 +37,42 @@ struct OpDesc {
 
 enum StencilMode { ST_APPLY = 0, ST_RESID = 1, ST_JACOBI = 2 };
 
+// Members of a lockstep batch: problems with the same layout whose device
+// buffers lie dz bytes apart (member i at member 0 + i * dz) and whose pinned
+// host staging lies hz bytes apart.  A launch covers the n members listed in
+// slot (grid z, block z works on member slot[z]); every pointer a launcher
+// takes is member 0's.  The default is the single problem (n = 1, slot 0).
+constexpr int kMaxBatch = 16;
+struct Batch {
+  long long dz = 0;
+  long long hz = 0;
+  int n = 1;
+  unsigned char slot[kMaxBatch] = {};
+  int cnt[kMaxBatch] = {};   // per-member counts (launch_combine with m < 0)
+  // per-member damping weights of the Jacobi sweeps (they follow each member's
+  // wavenumber); used instead of the omega argument when use_omega is set
+  int use_omega = 0;
+  double omega[kMaxBatch] = {};
+};
+
 // out = Op(u)                         (ST_APPLY, b unused)
 // out = b - Op(u)                     (ST_RESID)
 // out = u + omega D^-1 (b - Op(u))    (ST_JACOBI, D = diagonal of Op)
 template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
-                          cx<T>* out, T omega, hipStream_t s);
+                          cx<T>* out, T omega, hipStream_t s, const Batch& z = Batch());
 
 // Scaled apply for Krylov steps: with s = 1 / scal[0].re,
 //   vout = s u   and   out = Op(s u)
 // (normalises the new basis vector and applies the operator in one pass).
 template <typename T>
 hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k, const c128* scal,
-                                 cx<T>* vout, cx<T>* out, hipStream_t s);
+                                 cx<T>* vout, cx<T>* out, hipStream_t s, const Batch& z = Batch());
 
 // x = omega D^-1 b  (first damped-Jacobi sweep from x = 0)
 template <typename T>
 hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x, T omega,
-                          hipStream_t s);
+                          hipStream_t s, const Batch& z = Batch());
 
 // Transfers take dir = 1 for Dirichlet boundaries: boundary values of the input
 // count as zero and boundary values of the output are zero (interior masks on
@@ -62,18 +80,21 @@ hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>*
 // Deflation restriction Z^T: fine (nxf x nyf) -> coarse; weights p (x) p,
 // p = [1 4 6 4 1]/8 at fine offsets -2..2 around 2J; outside values zero.
 template <typename Ti, typename To>
-hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, int dir, hipStream_t s);
+hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, int dir, hipStream_t s,
+                             const Batch& z = Batch());
 // Deflation interpolation Z: coarse -> fine (transpose of the above).
 template <typename Ti, typename To>
-hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, int dir, hipStream_t s);
+hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, int dir, hipStream_t s,
+                            const Batch& z = Batch());
 
 // Full-weighting restriction (1/16)[1 2 1;2 4 2;1 2 1], fine -> coarse.
 template <typename T>
-hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, int dir, hipStream_t s);
+hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, int dir, hipStream_t s,
+                              const Batch& z = Batch());
 // x_fine += bilinear interpolation of e_coarse.
 template <typename T>
 hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, int dir,
-                                       hipStream_t s);
+                                       hipStream_t s, const Batch& z = Batch());
 // Injection of a real nodal field: c(J) = f(2J).
 template <typename Ti, typename To>
 hipError_t launch_inject(const Ti* f, int nxf, int nyf, To* c, hipStream_t s);
@@ -83,23 +104,29 @@ hipError_t launch_convert_real(const Ti* a, To* b, size_t n, hipStream_t s);
 
 // ---- vector kernels ------------------------------------------------------
 template <typename Ti, typename To>
-hipError_t launch_convert(const cx<Ti>* a, cx<To>* b, size_t n, hipStream_t s);
+hipError_t launch_convert(const cx<Ti>* a, cx<To>* b, size_t n, hipStream_t s,
+                          const Batch& z = Batch());
 template <typename T>
-hipError_t launch_add(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s);  // out=a+b
+hipError_t launch_add(const cx<T>* a, const cx<T>* b, cx<T>* out, size_t n, hipStream_t s,
+                      const Batch& z = Batch());  // out = a + b
 // y = scal[0] * x  (scal on the device; `inv` = use 1/scal[0].re instead)
 template <typename T>
 hipError_t launch_scale_dev(const cx<T>* x, cx<T>* y, const c128* scal, int inv, size_t n,
-                            hipStream_t s);
+                            hipStream_t s, const Batch& z = Batch());
 template <typename T>
-hipError_t launch_zero(cx<T>* x, size_t n, hipStream_t s);
-// out = (accumulate ? out : 0) + sign * sum_{i<m} coef[i] * V_i  (coef on the device)
+hipError_t launch_zero(cx<T>* x, size_t n, hipStream_t s, const Batch& z = Batch());
+// out = (accumulate ? out : 0) + sign * sum_{i<m} coef[i] * V_i  (coef on the device).
+// In a batch the coefficients of member slot s start at coef + s * coef_ld (they
+// are not in the members' workspaces) and m < 0 takes member z's count z.cnt[z].
 template <typename T>
-hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, double sign,
-                          cx<T>* out, int accumulate, size_t n, hipStream_t s);
+hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, size_t coef_ld,
+                          double sign, cx<T>* out, int accumulate, size_t n, hipStream_t s,
+                          const Batch& z = Batch());
 
 // y = A x with A a dense n x n row-major matrix (coarsest multigrid solve)
 template <typename T>
-hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s);
+hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s,
+                               const Batch& z = Batch());
 // out = unit vectors: out[j*n + i] = (i == j)
 hipError_t launch_identity(c128* out, int n, hipStream_t s);
 
@@ -128,32 +155,35 @@ int reduction_chunks(size_t n);
 // chunks from the end of the vectors (cache reuse between successive passes).
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
-                                   RedBuf rb, int reverse, hipStream_t s);
+                                   RedBuf rb, int reverse, hipStream_t s, const Batch& z = Batch());
 // host_out (optional): pinned host memory that receives a copy of out
 template <typename T>
 hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s,
-                                 c128* host_out = nullptr);
+                                 c128* host_out = nullptr, const Batch& z = Batch());
 template <typename T>
 hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n, RedBuf rb,
                            c128* out, hipStream_t s);
 // Modified Gram-Schmidt step: if (prev) w -= hprev[0] * prev;  out[0] = (next, w)
-// If next == nullptr: out[0] = ||w||_2 (real part).
+// If next == nullptr: out[0] = ||w||_2 (real part).  host_out as for the multi-dot.
 template <typename T>
 hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const cx<T>* next,
-                           size_t n, RedBuf rb, c128* out, hipStream_t s);
+                           size_t n, RedBuf rb, c128* out, hipStream_t s,
+                           c128* host_out = nullptr, const Batch& z = Batch());
 // Classical Gram-Schmidt update fused with the norm: w -= sum_{i<m} h[i] V_i ; out[0] = ||w||
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
-                                     size_t n, RedBuf rb, int reverse, hipStream_t s);
+                                     size_t n, RedBuf rb, int reverse, hipStream_t s,
+                                     const Batch& z = Batch());
 // sum of the partials written by launch_cgs_update_partial over a vector of length n
 hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,
-                                    c128* host_out = nullptr);
+                                    c128* host_out = nullptr, const Batch& z = Batch());
 template <typename T>
 hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                   size_t n, RedBuf rb, c128* out, hipStream_t s);
-// out[0] = ||x||_2 (real part)
+// out[0] = ||x||_2 (real part); host_out as for the multi-dot
 template <typename T>
-hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream_t s);
+hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream_t s,
+                       c128* host_out = nullptr, const Batch& z = Batch());
 // out[0].re = max of a real field (reduction over chunks)
 hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipStream_t s);
 // Validation of the wavenumber field: out[0] = number of entries that are not

@@ -150,8 +150,9 @@ struct MGHier {
   KrylovWS gm;                // coarsest GMRES otherwise
   int maxit = 0;
   // with a dense coarsest solve the whole cycle is a fixed kernel sequence on
-  // fixed buffers: captured once as a HIP graph (input = the level's r~ buffer)
-  hipGraphExec_t graph = nullptr;
+  // fixed buffers: captured as a HIP graph (input = the level's r~ buffer), one
+  // per set of batch members (bit mask) that runs it
+  std::vector<std::pair<unsigned, hipGraphExec_t>> graphs;
   const void* graph_out = nullptr;
 };
 
@@ -261,6 +262,11 @@ struct hm_problem {
   int host_cap = 0;
   c128* host_H = nullptr;      // pinned mirror of a GMRES Hessenberg (lookahead loop)
   size_t host_H_cap = 0;
+  bool own_host = true;        // false: the pinned staging belongs to a batch
+  // batch members: copies of the caller's right-hand side and solution
+  bool batch_io = false;
+  c128* ub = nullptr;
+  c128* uu = nullptr;
   hipEvent_t col_ev[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;   // private stream for graph capture
   // counts
@@ -334,141 +340,288 @@ static void d2h(hm_problem* p, const c128* dev, int n) {
   if (!p->pending.empty()) harvest(p);
 }
 
-static void h2d_coef(hm_problem* p, const std::vector<c128>& y) {
-  if ((int)y.size() > p->coef_cap) throw ArgError("coefficient buffer too small");
-  // the staging buffer may still feed an earlier upload: wait for the stream
+// ---- members solved in lockstep ------------------------------------------------
+// A solve drives one problem, or a batch of problems with the same layout, in
+// lockstep: every launch covers the members still active at that point (the
+// grid's z dimension), and each member keeps its own stopping decisions,
+// Hessenberg least-squares problem and counts on the host, so that its
+// arithmetic is exactly that of a solve on its own.  Member i's device buffers
+// lie i * dz bytes after member 0's and its pinned staging i * hz bytes after
+// member 0's; launches take member 0's pointers and stream.
+struct Ctx {
+  hm_problem* p;                  // member 0
+  std::vector<hm_problem*> mem;   // every member (host state)
+  long long dz = 0, hz = 0;
+  c128* coef = nullptr;           // batch: coefficient rows on the device, coef_ld apart
+  c128* host_coef = nullptr;      // batch: their pinned staging
+  size_t coef_ld = 0;
+  explicit Ctx(hm_problem* one) : p(one), mem{one} {}
+};
+using Act = std::vector<int>;     // members of a launch, ascending
+
+static Batch members(const Ctx& c, const Act& a) {
+  if (a.empty() || a.size() > (size_t)kMaxBatch) throw std::logic_error("bad member set");
+  Batch z;
+  z.dz = c.dz;
+  z.hz = c.hz;
+  z.n = (int)a.size();
+  for (size_t t = 0; t < a.size(); ++t) z.slot[t] = (unsigned char)a[t];
+  return z;
+}
+
+static unsigned mask_of(const Act& a) {
+  unsigned m = 0;
+  for (int i : a) m |= 1u << i;
+  return m;
+}
+
+static void wait_stream(Ctx& c) {
+  HM_CHECK(hipStreamSynchronize(c.p->s));
+  if (!c.p->pending.empty()) harvest(c.p);
+}
+
+// ||x|| of every member of a, on the device (dev_out[0]) and in each member's
+// pinned host[0].
+template <typename T>
+static void member_norms(Ctx& c, const Act& a, const cx<T>* x, size_t N, c128* dev_out) {
+  HM_CHECK(launch_norm<T>(x, N, rbuf(c.p, N), dev_out, c.p->s, c.p->host, members(c, a)));
+  wait_stream(c);
+}
+
+// x (+)= sum_i y_i V_i for the members of a (y[t] belongs to a[t]).
+template <typename T>
+static void combine_members(Ctx& c, const Act& a, const std::vector<std::vector<c128>>& y,
+                            const cx<T>* V, size_t N, cx<T>* x, int accumulate) {
+  hm_problem* p = c.p;
+  // the staging may still feed the previous upload: wait for the stream
   HM_CHECK(hipStreamSynchronize(p->s));
-  std::memcpy(p->host_coef, y.data(), sizeof(c128) * y.size());
-  HM_CHECK(hipMemcpyAsync(p->coef, p->host_coef, sizeof(c128) * y.size(), hipMemcpyHostToDevice,
-                          p->s));
+  Batch z = members(c, a);
+  if (c.mem.size() == 1) {
+    const std::vector<c128>& v = y[0];
+    if ((int)v.size() > p->coef_cap) throw ArgError("coefficient buffer too small");
+    std::memcpy(p->host_coef, v.data(), sizeof(c128) * v.size());
+    HM_CHECK(hipMemcpyAsync(p->coef, p->host_coef, sizeof(c128) * v.size(), hipMemcpyHostToDevice,
+                            p->s));
+    HM_CHECK(launch_combine<T>(V, N, (int)v.size(), p->coef, 0, 1.0, x, accumulate, N, p->s, z));
+    return;
+  }
+  size_t rows = 0;
+  for (size_t t = 0; t < a.size(); ++t) {
+    if (y[t].size() > c.coef_ld) throw ArgError("coefficient buffer too small");
+    std::memcpy(c.host_coef + (size_t)a[t] * c.coef_ld, y[t].data(), sizeof(c128) * y[t].size());
+    z.cnt[t] = (int)y[t].size();
+    rows = (size_t)a[t] + 1;
+  }
+  HM_CHECK(hipMemcpyAsync(c.coef, c.host_coef, sizeof(c128) * rows * c.coef_ld,
+                          hipMemcpyHostToDevice, p->s));
+  HM_CHECK(launch_combine<T>(V, N, -1, c.coef, c.coef_ld, 1.0, x, accumulate, N, p->s, z));
+}
+
+// Host state of one member's Krylov solve.
+struct MemberKrylov {
+  int i = 0;                 // member index
+  double beta = 0, tol = 0;  // initial residual norm; relative tolerance (< 0: none)
+  int maxit = 0, steps = 0;
+  double est1 = -1, est2 = -1;
+  bool ahead = false;
+  LSQ lsq;
+};
+
+// Members of a0 with a nonzero right-hand side (norm in host[0]) and their
+// step limits; replayed counts replace maxit and switch the tolerance off.
+// Members with b = 0 get x = 0 and a count of 0 steps.
+template <typename T>
+static std::vector<MemberKrylov> start_members(Ctx& c, const Act& a0, int kind, int maxit,
+                                               double tol, int cap, cx<T>* x, size_t N) {
+  std::vector<MemberKrylov> st;
+  Act zero;
+  for (int i : a0) {
+    hm_problem* q = c.mem[i];
+    const double beta = q->host[0].re;
+    if (beta == 0.0) {
+      zero.push_back(i);
+      if (kind >= 0) q->rec[kind].push_back(0);
+      continue;
+    }
+    MemberKrylov m;
+    m.i = i;
+    m.beta = beta;
+    m.maxit = maxit;
+    m.tol = tol;
+    if (kind >= 0) {
+      const int forced = forced_count(q, kind);
+      if (forced >= 0) {
+        m.maxit = forced;
+        m.tol = -1;
+      }
+    }
+    if (m.maxit > cap) throw ArgError("Krylov step count exceeds the workspace");
+    m.lsq.init(m.maxit, beta);
+    st.push_back(std::move(m));
+  }
+  if (!zero.empty()) HM_CHECK(launch_zero<T>(x, N, c.p->s, members(c, zero)));
+  return st;
+}
+
+static Act members_of(const std::vector<MemberKrylov>& st, const std::vector<int>& who) {
+  Act a;
+  for (int t : who) a.push_back(st[t].i);
+  return a;
+}
+
+// Solutions x (+)= V y of every member from its least-squares problem; records
+// the step counts under `kind`.
+template <typename T>
+static void finish_members(Ctx& c, std::vector<MemberKrylov>& st, int kind, const cx<T>* V,
+                           size_t N, cx<T>* x, int accumulate) {
+  if (st.empty()) return;
+  Act a;
+  std::vector<std::vector<c128>> y(st.size());
+  for (size_t t = 0; t < st.size(); ++t) {
+    st[t].lsq.solve(st[t].steps, y[t]);
+    a.push_back(st[t].i);
+  }
+  combine_members<T>(c, a, y, V, N, x, accumulate);
+  if (kind >= 0)
+    for (auto& m : st) c.mem[m.i]->rec[kind].push_back(m.steps);
 }
 
 // ---- operator application on a level -----------------------------------------
 template <typename T>
-static void apply_level(hm_problem* p, const DefLevel& L, bool cslp, int mode, const cx<T>* u,
-                        const cx<T>* b, cx<T>* out) {
-  HM_CHECK(launch_stencil<T>(opsel<T>(L, cslp), mode, u, levk<T>(L), b, out, T(0), p->s));
+static void apply_level(Ctx& c, const Act& a, const DefLevel& L, bool cslp, int mode,
+                        const cx<T>* u, const cx<T>* b, cx<T>* out) {
+  HM_CHECK(launch_stencil<T>(opsel<T>(L, cslp), mode, u, levk<T>(L), b, out, T(0), c.p->s,
+                             members(c, a)));
 }
 
 // ---- GMRES with classical Gram-Schmidt (Krylov CSLP) ----------------------------
 // Unpreconditioned GMRES from x = 0 on the operator `op` with wavenumber `k`.
 // The device never waits for the host: step j+1 is enqueued before the host
-// reads the Hessenberg column of step j (copied to pinned memory, waited on
-// with an event), so the host's stopping test overlaps the next step.  When
-// step j meets the tolerance, the speculative step j+1 has only written w,
-// column j+1 and V_{j+2}, none of which the solution uses.
+// reads the Hessenberg columns of step j (written to pinned memory by the
+// reduction kernels, waited on with an event), so the host's stopping tests
+// overlap the next step.  When a member meets its tolerance at step j, its
+// speculative step j+1 has only written w, column j+1 and V_{j+2}, none of
+// which its solution uses.
 template <typename T>
-static int gmres_cgs(hm_problem* p, const OpDesc<T>& op, const T* k, KrylovWS& ws, int maxit,
-                     double tol, int kind, const cx<T>* b, cx<T>* x) {
+static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
+                      int maxit, double tol, int kind, const cx<T>* b, cx<T>* x) {
+  hm_problem* p = c.p;
   const size_t N = ws.N;
   cx<T>* V = (cx<T>*)ws.V;
   cx<T>* w = (cx<T>*)ws.w;
-  HM_CHECK(launch_norm<T>(b, N, rbuf(p, N), ws.h, p->s));
-  d2h(p, ws.h, 1);
-  const double beta = p->host[0].re;
-  if (beta == 0.0) {
-    HM_CHECK(launch_zero<T>(x, N, p->s));
-    p->rec[kind].push_back(0);
-    return 0;
-  }
-  const int forced = forced_count(p, kind);
-  if (forced >= 0) {
-    maxit = forced;
-    tol = -1;
-  }
-  if (maxit > ws.cap) throw ArgError("GMRES step count exceeds the workspace");
+  member_norms<T>(c, a0, b, N, ws.h);
+  std::vector<MemberKrylov> st = start_members<T>(c, a0, kind, maxit, tol, ws.cap, x, N);
+  if (st.empty()) return;
   const size_t ld = (size_t)ws.cap + 2;
-  if ((size_t)maxit * ld > p->host_H_cap) throw ArgError("Hessenberg mirror too small");
+  for (const auto& m : st)
+    if ((size_t)m.maxit * ld > p->host_H_cap) throw ArgError("Hessenberg mirror too small");
   const double es = (double)sizeof(cx<T>);
   const int tk_op = op.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE;
   cx<T>* wb[2] = {w, (cx<T>*)ws.w2};
-  // step j: v_j = src / s_j (s_0 = ||b||, s_j = h_{j,j-1}) written to the basis
-  // in the same pass as w = M v_j; classical Gram-Schmidt with the two sweeps
-  // over the basis in opposite directions (the second starts on the chunks the
-  // first read last, which the caches still hold)
-  auto enqueue_step = [&](int j) {
+  // step j of the members st[t], t in who: v_j = src / s_j (s_0 = ||b||,
+  // s_j = h_{j,j-1}) written to the basis in the same pass as w = M v_j;
+  // classical Gram-Schmidt with the two sweeps over the basis in opposite
+  // directions (the second starts on the chunks the first read last, which the
+  // caches still hold)
+  auto enqueue_step = [&](int j, const std::vector<int>& who) {
+    const Batch z = members(c, members_of(st, who));
+    const double nm = (double)who.size();
     c128* col = ws.H + (size_t)j * ld;
     const cx<T>* src = j == 0 ? b : wb[(j - 1) & 1];
     const c128* sc = j == 0 ? ws.h : ws.H + (size_t)(j - 1) * ld + j;
     cx<T>* wj = wb[j & 1];
-    timed(p, tk_op, 3.5 * es * N, [&] {
-      return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, wj, p->s);
+    timed(p, tk_op, nm * 3.5 * es * N, [&] {
+      return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, wj, p->s, z);
     });
-    timed(p, HM_TK_CGS_DOT, (j + 2) * es * N, [&] {
-      return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), 0, p->s);
+    timed(p, HM_TK_CGS_DOT, nm * (j + 2) * es * N, [&] {
+      return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), 0, p->s, z);
     });
     c128* hcol = p->host_H + (size_t)j * ld;      // pinned mirror of the column
-    HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s, hcol));
-    timed(p, HM_TK_CGS_UPDATE, (j + 3) * es * N, [&] {
-      return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), 1, p->s);
+    HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s, hcol, z));
+    timed(p, HM_TK_CGS_UPDATE, nm * (j + 3) * es * N, [&] {
+      return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), 1, p->s, z);
     });
-    HM_CHECK(launch_update_norm_final(N, rbuf(p, N), col + j + 1, p->s, hcol + j + 1));
+    HM_CHECK(launch_update_norm_final(N, rbuf(p, N), col + j + 1, p->s, hcol + j + 1, z));
     HM_CHECK(hipEventRecord(p->col_ev[j & 1], p->s));
   };
-  LSQ lsq;
-  lsq.init(maxit, beta);
-  int steps = 0;
-  double est1 = -1.0, est2 = -1.0;   // estimates after steps j-1 and j-2
-  if (maxit > 0) enqueue_step(0);
-  for (int j = 0; j < maxit; ++j) {
-    // Step j+1 goes in before step j's column is read, unless step j is expected
-    // to meet the tolerance: the estimates fall about geometrically, so
-    // est_j ~ est_{j-1}^2 / est_{j-2}.  A step enqueued past convergence is
-    // wasted work; a wrong guess only costs one wait for the host.
-    bool ahead = j + 1 < maxit;
-    if (ahead && tol >= 0 && est1 > 0 && est2 > 0 && est1 * (est1 / est2) <= tol * beta)
-      ahead = false;
-    if (ahead) enqueue_step(j + 1);
+  std::vector<int> run;              // members at step j
+  for (size_t t = 0; t < st.size(); ++t)
+    if (st[t].maxit > 0) run.push_back((int)t);
+  if (!run.empty()) enqueue_step(0, run);
+  for (int j = 0; !run.empty(); ++j) {
+    // Step j+1 goes in before step j's columns are read, except for members
+    // expected to meet the tolerance at step j: the estimates fall about
+    // geometrically, so est_j ~ est_{j-1}^2 / est_{j-2}.  A step enqueued past
+    // convergence is wasted work; a wrong guess only costs one wait for the host.
+    std::vector<int> ahead;
+    for (int t : run) {
+      MemberKrylov& m = st[t];
+      bool ah = j + 1 < m.maxit;
+      if (ah && m.tol >= 0 && m.est1 > 0 && m.est2 > 0 && m.est1 * (m.est1 / m.est2) <= m.tol * m.beta)
+        ah = false;
+      m.ahead = ah;
+      if (ah) ahead.push_back(t);
+    }
+    if (!ahead.empty()) enqueue_step(j + 1, ahead);
+    // the event was last recorded after every member's step j
     HM_CHECK(hipEventSynchronize(p->col_ev[j & 1]));
-    const c128* hc = p->host_H + (size_t)j * ld;
-    const double est = lsq.add(j, hc);
-    steps = j + 1;
-    const bool broke = hc[j + 1].re <= 1e-14 * beta;
-    if (broke) break;
-    if (tol >= 0 && est <= tol * beta) break;
-    if (!ahead && j + 1 < maxit) enqueue_step(j + 1);
-    est2 = est1;
-    est1 = est;
+    std::vector<int> next, late;
+    for (int t : run) {
+      MemberKrylov& m = st[t];
+      const c128* hc = c.mem[m.i]->host_H + (size_t)j * ld;
+      const double est = m.lsq.add(j, hc);
+      m.steps = j + 1;
+      const bool broke = hc[j + 1].re <= 1e-14 * m.beta;
+      if (broke || (m.tol >= 0 && est <= m.tol * m.beta) || j + 1 >= m.maxit) continue;
+      next.push_back(t);
+      if (!m.ahead) late.push_back(t);
+      m.est2 = m.est1;
+      m.est1 = est;
+    }
+    if (!late.empty()) enqueue_step(j + 1, late);
+    run.swap(next);
   }
-  std::vector<c128> y;
-  lsq.solve(steps, y);
-  h2d_coef(p, y);
-  HM_CHECK(launch_combine<T>(V, N, steps, p->coef, 1.0, x, 0, N, p->s));
-  p->rec[kind].push_back(steps);
-  return steps;
+  finish_members<T>(c, st, kind, V, N, x, 0);
 }
 
 // ---- multigrid V-cycle for the CSLP of level l -----------------------------------
 template <typename T>
-static const cx<T>* mg_cycle(hm_problem* p, DefLevel& D, int q, const cx<T>* b) {
+static const cx<T>* mg_cycle(Ctx& c, const Act& a, DefLevel& D, int q, const cx<T>* b) {
+  hm_problem* p = c.p;
   MGHier& H = D.mg;
   MGLevel& m = H.lv[q];
+  // the damping weight follows each member's largest wavenumber
+  Batch z = members(c, a);
+  if (c.mem.size() > 1) {
+    z.use_omega = 1;
+    for (size_t t = 0; t < a.size(); ++t) z.omega[t] = c.mem[a[t]]->lev[D.l].mg.lv[q].omega;
+  }
   const OpDesc<T>& op = mgop<T>(m);
   const T* k = mgk<T>(D, q);
   cx<T>* x = (cx<T>*)m.x;
   cx<T>* y = (cx<T>*)m.y;
   if (q == (int)H.lv.size() - 1) {
     if (H.dense) {
-      HM_CHECK(launch_dense_matvec<T>((const cx<T>*)H.inv, (int)m.N, b, x, p->s));
+      HM_CHECK(launch_dense_matvec<T>((const cx<T>*)H.inv, (int)m.N, b, x, p->s, z));
       return x;
     }
-    gmres_cgs<T>(p, op, k, H.gm, H.maxit, p->cfg.tol_cslp, K_MGC, b, x);
+    gmres_cgs<T>(c, a, op, k, H.gm, H.maxit, p->cfg.tol_cslp, K_MGC, b, x);
     return x;
   }
   const T om = (T)m.omega;
-  HM_CHECK(launch_jacobi0<T>(op, k, b, x, om, p->s));
+  HM_CHECK(launch_jacobi0<T>(op, k, b, x, om, p->s, z));
   for (int s = 1; s < p->cfg.mg_nu_pre; ++s) {
-    HM_CHECK(launch_stencil<T>(op, ST_JACOBI, x, k, b, y, om, p->s));
+    HM_CHECK(launch_stencil<T>(op, ST_JACOBI, x, k, b, y, om, p->s, z));
     std::swap(x, y);
   }
   cx<T>* r = (cx<T>*)m.r;
-  HM_CHECK(launch_stencil<T>(op, ST_RESID, x, k, b, r, T(0), p->s));
+  HM_CHECK(launch_stencil<T>(op, ST_RESID, x, k, b, r, T(0), p->s, z));
   MGLevel& mc = H.lv[q + 1];
-  HM_CHECK(launch_restrict_fw<T>(r, m.nx, m.ny, (cx<T>*)mc.b, p->cfg.bc, p->s));
-  const cx<T>* e = mg_cycle<T>(p, D, q + 1, (const cx<T>*)mc.b);
-  HM_CHECK(launch_prolong_bilinear_add<T>(e, m.nx, m.ny, x, p->cfg.bc, p->s));
+  HM_CHECK(launch_restrict_fw<T>(r, m.nx, m.ny, (cx<T>*)mc.b, p->cfg.bc, p->s, z));
+  const cx<T>* e = mg_cycle<T>(c, a, D, q + 1, (const cx<T>*)mc.b);
+  HM_CHECK(launch_prolong_bilinear_add<T>(e, m.nx, m.ny, x, p->cfg.bc, p->s, z));
   for (int s = 0; s < p->cfg.mg_nu_post; ++s) {
-    HM_CHECK(launch_stencil<T>(op, ST_JACOBI, x, k, b, y, om, p->s));
+    HM_CHECK(launch_stencil<T>(op, ST_JACOBI, x, k, b, y, om, p->s, z));
     std::swap(x, y);
   }
   return x;
@@ -476,19 +629,25 @@ static const cx<T>* mg_cycle(hm_problem* p, DefLevel& D, int q, const cx<T>* b) 
 
 // One V-cycle for the CSLP of level D on b.  When b is the level's r~ buffer
 // and the coarsest solve is dense, the cycle runs as a HIP graph captured on
-// first use (no host decisions inside, no memset nodes); otherwise eagerly.
+// first use for this set of members (no host decisions inside, no memset
+// nodes); otherwise eagerly.
 template <typename T>
-static const cx<T>* vcycle(hm_problem* p, DefLevel& D, const cx<T>* b) {
+static const cx<T>* vcycle(Ctx& c, const Act& a, DefLevel& D, const cx<T>* b) {
+  hm_problem* p = c.p;
   MGHier& H = D.mg;
-  if (!H.dense || (const void*)b != D.rt || !p->cap_stream) return mg_cycle<T>(p, D, 0, b);
-  if (!H.graph) {
+  if (!H.dense || (const void*)b != D.rt || !p->cap_stream) return mg_cycle<T>(c, a, D, 0, b);
+  const unsigned key = mask_of(a);
+  hipGraphExec_t ge = nullptr;
+  for (const auto& g : H.graphs)
+    if (g.first == key) ge = g.second;
+  if (!ge) {
     hipStream_t saved = p->s;
     hipGraph_t g = nullptr;
     HM_CHECK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     p->s = p->cap_stream;
     const cx<T>* out = nullptr;
     try {
-      out = mg_cycle<T>(p, D, 0, b);
+      out = mg_cycle<T>(c, a, D, 0, b);
     } catch (...) {
       p->s = saved;
       (void)hipStreamEndCapture(p->cap_stream, &g);
@@ -497,12 +656,13 @@ static const cx<T>* vcycle(hm_problem* p, DefLevel& D, const cx<T>* b) {
     }
     p->s = saved;
     HM_CHECK(hipStreamEndCapture(p->cap_stream, &g));
-    const hipError_t e = hipGraphInstantiate(&H.graph, g, nullptr, nullptr, 0);
+    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HM_CHECK(e);
+    H.graphs.push_back({key, ge});
     H.graph_out = out;
   }
-  HM_CHECK(hipGraphLaunch(H.graph, p->s));
+  HM_CHECK(hipGraphLaunch(ge, p->s));
   return (const cx<T>*)H.graph_out;
 }
 
@@ -510,84 +670,86 @@ static const cx<T>* vcycle(hm_problem* p, DefLevel& D, const cx<T>* b) {
 
 namespace hm {
 
-template <typename T> static void precond(hm_problem* p, int l, const cx<T>* v, cx<T>* x);
+template <typename T>
+static void precond(Ctx& c, const Act& a, int l, const cx<T>* v, cx<T>* x);
 
 // CSLP^-1 approximation of level l: one V-cycle (levels 1-2) or GMRES.  Returns
 // the buffer holding the result (`out` for GMRES, a multigrid buffer otherwise).
 template <typename T>
-static const cx<T>* cslp_apply(hm_problem* p, int l, const cx<T>* r, cx<T>* out) {
+static const cx<T>* cslp_apply(Ctx& c, const Act& a, int l, const cx<T>* r, cx<T>* out) {
+  hm_problem* p = c.p;
   DefLevel& D = p->lev[l];
-  if (D.has_mg) return vcycle<T>(p, D, r);
-  gmres_cgs<T>(p, opsel<T>(D, true), levk<T>(D), D.cslp, D.cslp_maxit, p->cfg.tol_cslp, K_CSLP, r,
-               out);
+  if (D.has_mg) return vcycle<T>(c, a, D, r);
+  gmres_cgs<T>(c, a, opsel<T>(D, true), levk<T>(D), D.cslp, D.cslp_maxit, p->cfg.tol_cslp, K_CSLP,
+               r, out);
   return out;
 }
 
-// FGMRES with modified Gram-Schmidt (Algorithm 1) on the operator of level c,
-// zero initial guess.  Preconditioner: Prec_c (c < L) or the Krylov CSLP (c == L).
+// FGMRES with modified Gram-Schmidt (Algorithm 1) on the operator of level lv,
+// zero initial guess.  Preconditioner: Prec_lv (lv < L) or the Krylov CSLP
+// (lv == L).
 template <typename T>
-static int fgmres_level(hm_problem* p, int c, const cx<T>* b, cx<T>* x, double tol, int maxit,
-                        int kind) {
-  DefLevel& D = p->lev[c];
+static void fgmres_level(Ctx& c, const Act& a0, int lv, const cx<T>* b, cx<T>* x, double tol,
+                         int maxit, int kind) {
+  hm_problem* p = c.p;
+  DefLevel& D = p->lev[lv];
   KrylovWS& ws = D.fg;
   const size_t N = D.N;
   cx<T>* V = (cx<T>*)ws.V;
   cx<T>* X = (cx<T>*)ws.X;
   cx<T>* w = (cx<T>*)ws.w;
-  HM_CHECK(launch_norm<T>(b, N, rbuf(p, N), ws.h, p->s));
-  d2h(p, ws.h, 1);
-  const double beta = p->host[0].re;
-  if (beta == 0.0) {
-    HM_CHECK(launch_zero<T>(x, N, p->s));
-    if (kind >= 0) p->rec[kind].push_back(0);
-    return 0;
+  member_norms<T>(c, a0, b, N, ws.h);
+  std::vector<MemberKrylov> st = start_members<T>(c, a0, kind, maxit, tol, ws.cap, x, N);
+  if (st.empty()) return;
+  std::vector<int> run, every;
+  for (size_t t = 0; t < st.size(); ++t) {
+    every.push_back((int)t);
+    if (st[t].maxit > 0) run.push_back((int)t);
   }
-  if (kind >= 0) {
-    const int forced = forced_count(p, kind);
-    if (forced >= 0) {
-      maxit = forced;
-      tol = -1;
-    }
-  }
-  if (maxit > ws.cap) throw ArgError("FGMRES step count exceeds the workspace");
-  HM_CHECK(launch_scale_dev<T>(b, V, ws.h, 1, N, p->s));
-  LSQ lsq;
-  lsq.init(maxit, beta);
-  int steps = 0;
-  for (int j = 0; j < maxit; ++j) {
+  HM_CHECK(launch_scale_dev<T>(b, V, ws.h, 1, N, p->s, members(c, members_of(st, every))));
+  const double es = (double)sizeof(cx<T>);
+  for (int j = 0; !run.empty(); ++j) {
+    const Act a = members_of(st, run);
+    const Batch z = members(c, a);
+    const double nm = (double)a.size();
     cx<T>* Vj = V + (size_t)j * N;
     cx<T>* Xj = X + (size_t)j * N;
-    if (c == p->L) {
-      cslp_apply<T>(p, c, Vj, Xj);
+    if (lv == p->L) {
+      cslp_apply<T>(c, a, lv, Vj, Xj);
     } else {
-      precond<T>(p, c, Vj, Xj);
+      precond<T>(c, a, lv, Vj, Xj);
     }
-    const double es = (double)sizeof(cx<T>);
-    timed(p, D.A64.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE, 2.5 * es * N, [&] {
-      return launch_stencil<T>(opsel<T>(D, false), ST_APPLY, Xj, levk<T>(D), nullptr, w, T(0), p->s);
+    timed(p, D.A64.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE, nm * 2.5 * es * N, [&] {
+      return launch_stencil<T>(opsel<T>(D, false), ST_APPLY, Xj, levk<T>(D), nullptr, w, T(0),
+                               p->s, z);
     });
     for (int i = 0; i <= j; ++i)
-      timed(p, HM_TK_MGS, (i > 0 ? 4.0 : 2.0) * es * N, [&] {
+      timed(p, HM_TK_MGS, nm * (i > 0 ? 4.0 : 2.0) * es * N, [&] {
         return launch_mgs_step<T>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr, ws.h + i - 1,
-                                  V + (size_t)i * N, N, rbuf(p, N), ws.h + i, p->s);
+                                  V + (size_t)i * N, N, rbuf(p, N), ws.h + i, p->s, p->host + i, z);
       });
-    timed(p, HM_TK_MGS, 3.0 * es * N, [&] {
-      return launch_mgs_step<T>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s);
+    timed(p, HM_TK_MGS, nm * 3.0 * es * N, [&] {
+      return launch_mgs_step<T>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s,
+                                p->host + j + 1, z);
     });
-    d2h(p, ws.h, j + 2);
-    const double est = lsq.add(j, p->host);
-    steps = j + 1;
-    const bool broke = p->host[j + 1].re <= 1e-14 * beta;
-    if (!broke) HM_CHECK(launch_scale_dev<T>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s));
-    if (broke) break;
-    if (tol >= 0 && est <= tol * beta) break;
+    wait_stream(c);
+    std::vector<int> next, scale;
+    for (int t : run) {
+      MemberKrylov& m = st[t];
+      const c128* hc = c.mem[m.i]->host;
+      const double est = m.lsq.add(j, hc);
+      m.steps = j + 1;
+      const bool broke = hc[j + 1].re <= 1e-14 * m.beta;
+      if (!broke) scale.push_back(t);
+      if (broke || (m.tol >= 0 && est <= m.tol * m.beta) || j + 1 >= m.maxit) continue;
+      next.push_back(t);
+    }
+    if (!scale.empty())
+      HM_CHECK(launch_scale_dev<T>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s,
+                                   members(c, members_of(st, scale))));
+    run.swap(next);
   }
-  std::vector<c128> y;
-  lsq.solve(steps, y);
-  h2d_coef(p, y);
-  HM_CHECK(launch_combine<T>(X, N, steps, p->coef, 1.0, x, 0, N, p->s));
-  if (kind >= 0) p->rec[kind].push_back(steps);
-  return steps;
+  finish_members<T>(c, st, kind, X, N, x, 0);
 }
 
 // Levels 2..tol_levels above the coarsest iterate to tol_level2; every other
@@ -596,55 +758,65 @@ static bool tol_level(const hm_config& c, int L, int l) {
   return l >= 2 && l < L && l <= c.tol_levels;
 }
 
-// Coarse problem E_c x = b of level c (Algorithm 1, restriction to
+// Coarse problem E_c x = b of level cl (Algorithm 1, restriction to
 // interpolation).  Only level-2 solves are recorded / replayed (kind 0).
 template <typename T>
-static void coarse_solve(hm_problem* p, int c, const cx<T>* b, cx<T>* x) {
-  if (tol_level(p->cfg, p->L, c))
-    fgmres_level<T>(p, c, b, x, p->cfg.tol_level2, p->cfg.level2_maxit, c == 2 ? K_LEVEL2 : -1);
+static void coarse_solve(Ctx& c, const Act& a, int cl, const cx<T>* b, cx<T>* x) {
+  const hm_problem* p = c.p;
+  if (tol_level(p->cfg, p->L, cl))
+    fgmres_level<T>(c, a, cl, b, x, p->cfg.tol_level2, p->cfg.level2_maxit, cl == 2 ? K_LEVEL2 : -1);
   else
-    fgmres_level<T>(p, c, b, x, -1.0, p->cfg.coarse_steps, -1);
+    fgmres_level<T>(c, a, cl, b, x, -1.0, p->cfg.coarse_steps, -1);
 }
 
 template <typename T, typename Tn>
-static void coarse_branch(hm_problem* p, int l, const cx<T>* v) {
+static void coarse_branch(Ctx& c, const Act& a, int l, const cx<T>* v) {
+  hm_problem* p = c.p;
+  const Batch z = members(c, a);
   DefLevel& D = p->lev[l];
   DefLevel& C = p->lev[l + 1];
-  HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, (cx<Tn>*)C.rhs, p->cfg.bc, p->s));
-  coarse_solve<Tn>(p, l + 1, (const cx<Tn>*)C.rhs, (cx<Tn>*)C.sol);
-  HM_CHECK(launch_prolong_z<Tn, T>((const cx<Tn>*)C.sol, D.nx, D.ny, (cx<T>*)D.t, p->cfg.bc, p->s));
+  HM_CHECK(launch_restrict_z<T, Tn>(v, D.nx, D.ny, (cx<Tn>*)C.rhs, p->cfg.bc, p->s, z));
+  coarse_solve<Tn>(c, a, l + 1, (const cx<Tn>*)C.rhs, (cx<Tn>*)C.sol);
+  HM_CHECK(launch_prolong_z<Tn, T>((const cx<Tn>*)C.sol, D.nx, D.ny, (cx<T>*)D.t, p->cfg.bc, p->s,
+                                   z));
 }
 
 // Prec_l(v) = M_l^-1 (v - A_l t) + t,  t = Z E^-1 Z^T v   (A-DEF1, Sec. 3.1)
 template <typename T>
-static void precond(hm_problem* p, int l, const cx<T>* v, cx<T>* x) {
+static void precond(Ctx& c, const Act& a, int l, const cx<T>* v, cx<T>* x) {
+  hm_problem* p = c.p;
   DefLevel& D = p->lev[l];
   if (p->lev[l + 1].dbl)
-    coarse_branch<T, double>(p, l, v);
+    coarse_branch<T, double>(c, a, l, v);
   else
-    coarse_branch<T, float>(p, l, v);
+    coarse_branch<T, float>(c, a, l, v);
   cx<T>* t = (cx<T>*)D.t;
   cx<T>* rt = (cx<T>*)D.rt;
-  apply_level<T>(p, D, false, ST_RESID, t, v, rt);          // r~ = v - A t
-  const cx<T>* r = cslp_apply<T>(p, l, rt, (cx<T>*)D.xo);    // r ~ M^-1 r~
-  HM_CHECK(launch_add<T>(r, t, x, D.N, p->s));                // x = r + t
+  apply_level<T>(c, a, D, false, ST_RESID, t, v, rt);              // r~ = v - A t
+  const cx<T>* r = cslp_apply<T>(c, a, l, rt, (cx<T>*)D.xo);       // r ~ M^-1 r~
+  HM_CHECK(launch_add<T>(r, t, x, D.N, p->s, members(c, a)));       // x = r + t
 }
 
 // Finest-level preconditioner on complex128 vectors (casts in mixed mode).
-static void precond_top(hm_problem* p, const c128* v, c128* x) {
+static void precond_top(Ctx& c, const Act& a, const c128* v, c128* x) {
+  hm_problem* p = c.p;
   const size_t N = p->lev[1].N;
   if (p->mixed) {
-    HM_CHECK(launch_convert<double, float>(v, (c64*)p->pin_v, N, p->s));
-    precond<float>(p, 1, (const c64*)p->pin_v, (c64*)p->pin_x);
-    HM_CHECK(launch_convert<float, double>((const c64*)p->pin_x, x, N, p->s));
+    const Batch z = members(c, a);
+    HM_CHECK(launch_convert<double, float>(v, (c64*)p->pin_v, N, p->s, z));
+    precond<float>(c, a, 1, (const c64*)p->pin_v, (c64*)p->pin_x);
+    HM_CHECK(launch_convert<float, double>((const c64*)p->pin_x, x, N, p->s, z));
   } else {
-    precond<double>(p, 1, v, x);
+    precond<double>(c, a, 1, v, x);
   }
 }
 
-// Outer FGMRES (Algorithm 1 at level 1, FP64, restarted).
-static hm_status outer_solve(hm_problem* p, const c128* b, c128* u, hm_solve_info* info) {
+// Outer FGMRES (Algorithm 1 at level 1, FP64, restarted) for every member; b
+// and u are member 0's vectors (the others at the member stride).  info: one
+// record per member, or null.
+static hm_status outer_solve(Ctx& c, const c128* b, c128* u, hm_solve_info* info) {
   const auto t0 = std::chrono::steady_clock::now();
+  hm_problem* p = c.p;
   DefLevel& D = p->lev[1];
   KrylovWS& ws = p->outer;
   const size_t N = D.N;
@@ -652,83 +824,120 @@ static hm_status outer_solve(hm_problem* p, const c128* b, c128* u, hm_solve_inf
   c128* X = (c128*)ws.X;
   c128* w = (c128*)ws.w;
   const hm_config& cf = p->cfg;
-  const size_t rec0[K_NKIND] = {p->rec[0].size(), p->rec[1].size(), p->rec[2].size(),
-                                p->rec[3].size()};
-  HM_CHECK(launch_norm<double>(b, N, rbuf(p, N), ws.h, p->s));
-  d2h(p, ws.h, 1);
-  const double bnorm = p->host[0].re;
-  HM_CHECK(launch_zero<double>(u, N, p->s));
-  int total = 0;
-  double rel_true = 0, est_rel = 0;
-  while (true) {
-    HM_CHECK(launch_stencil<double>(D.A64, ST_RESID, u, D.k64, b, p->tmp64, 0.0, p->s));
-    HM_CHECK(launch_norm<double>(p->tmp64, N, rbuf(p, N), ws.h, p->s));
-    d2h(p, ws.h, 1);
-    const double rnorm = p->host[0].re;
-    rel_true = bnorm > 0 ? rnorm / bnorm : 0.0;
-    if (bnorm == 0.0 || rnorm <= cf.tol_outer * bnorm || total >= cf.outer_maxit) break;
-    int m = std::min(cf.outer_restart, cf.outer_maxit - total);
-    double tol = cf.tol_outer;
-    const int forced = forced_count(p, K_OUTER);
-    if (forced >= 0) {
-      m = forced;
-      tol = -1;
+  const int nb = (int)c.mem.size();
+  struct Outer {
+    size_t rec0[K_NKIND];
+    double bnorm = 0, rel_true = 0, est_rel = 0;
+    int total = 0;
+  };
+  std::vector<Outer> o(nb);
+  Act act;
+  for (int i = 0; i < nb; ++i) {
+    act.push_back(i);
+    for (int kd = 0; kd < K_NKIND; ++kd) o[i].rec0[kd] = c.mem[i]->rec[kd].size();
+  }
+  member_norms<double>(c, act, b, N, ws.h);
+  for (int i = 0; i < nb; ++i) o[i].bnorm = c.mem[i]->host[0].re;
+  HM_CHECK(launch_zero<double>(u, N, p->s, members(c, act)));
+  while (!act.empty()) {
+    HM_CHECK(launch_stencil<double>(D.A64, ST_RESID, u, D.k64, b, p->tmp64, 0.0, p->s,
+                                    members(c, act)));
+    member_norms<double>(c, act, p->tmp64, N, ws.h);
+    std::vector<MemberKrylov> st;       // members that run another restart cycle
+    for (int i : act) {
+      hm_problem* q = c.mem[i];
+      Outer& m = o[i];
+      const double rnorm = q->host[0].re;
+      m.rel_true = m.bnorm > 0 ? rnorm / m.bnorm : 0.0;
+      if (m.bnorm == 0.0 || rnorm <= cf.tol_outer * m.bnorm || m.total >= cf.outer_maxit) continue;
+      MemberKrylov k;
+      k.i = i;
+      k.beta = rnorm;
+      k.maxit = std::min(cf.outer_restart, cf.outer_maxit - m.total);
+      k.tol = cf.tol_outer;
+      const int forced = forced_count(q, K_OUTER);
+      if (forced >= 0) {
+        k.maxit = forced;
+        k.tol = -1;
+      }
+      if (k.maxit > ws.cap) throw ArgError("outer step count exceeds the restart length");
+      k.lsq.init(k.maxit, rnorm);
+      st.push_back(std::move(k));
     }
-    if (m > ws.cap) throw ArgError("outer step count exceeds the restart length");
-    HM_CHECK(launch_scale_dev<double>(p->tmp64, V, ws.h, 1, N, p->s));
-    LSQ lsq;
-    lsq.init(m, rnorm);
-    int steps = 0;
-    for (int j = 0; j < m; ++j) {
+    std::vector<int> run, every;
+    for (size_t t = 0; t < st.size(); ++t) {
+      every.push_back((int)t);
+      if (st[t].maxit > 0) run.push_back((int)t);
+    }
+    act = members_of(st, every);
+    if (act.empty()) break;
+    HM_CHECK(launch_scale_dev<double>(p->tmp64, V, ws.h, 1, N, p->s, members(c, act)));
+    for (int j = 0; !run.empty(); ++j) {
+      const Act a = members_of(st, run);
+      const Batch z = members(c, a);
+      const double nm = (double)a.size();
       c128* Vj = V + (size_t)j * N;
       c128* Xj = X + (size_t)j * N;
-      precond_top(p, Vj, Xj);
-      timed(p, HM_TK_FIVE_POINT, 40.0 * N, [&] {
-        return launch_stencil<double>(D.A64, ST_APPLY, Xj, D.k64, nullptr, w, 0.0, p->s);
+      precond_top(c, a, Vj, Xj);
+      timed(p, HM_TK_FIVE_POINT, nm * 40.0 * N, [&] {
+        return launch_stencil<double>(D.A64, ST_APPLY, Xj, D.k64, nullptr, w, 0.0, p->s, z);
       });
       for (int i = 0; i <= j; ++i)
-        timed(p, HM_TK_MGS, (i > 0 ? 64.0 : 32.0) * N, [&] {
+        timed(p, HM_TK_MGS, nm * (i > 0 ? 64.0 : 32.0) * N, [&] {
           return launch_mgs_step<double>(w, i > 0 ? V + (size_t)(i - 1) * N : nullptr,
                                          ws.h + i - 1, V + (size_t)i * N, N, rbuf(p, N), ws.h + i,
-                                         p->s);
+                                         p->s, p->host + i, z);
         });
-      timed(p, HM_TK_MGS, 48.0 * N, [&] {
-        return launch_mgs_step<double>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s);
+      timed(p, HM_TK_MGS, nm * 48.0 * N, [&] {
+        return launch_mgs_step<double>(w, Vj, ws.h + j, nullptr, N, rbuf(p, N), ws.h + j + 1, p->s,
+                                       p->host + j + 1, z);
       });
-      d2h(p, ws.h, j + 2);
-      const double est = lsq.add(j, p->host);
-      est_rel = bnorm > 0 ? est / bnorm : 0.0;
-      steps = j + 1;
-      const bool broke = p->host[j + 1].re <= 1e-14 * rnorm;
-      if (!broke) HM_CHECK(launch_scale_dev<double>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s));
-      if (broke) break;
-      if (tol >= 0 && est <= tol * bnorm) break;
+      wait_stream(c);
+      std::vector<int> next, scale;
+      for (int t : run) {
+        MemberKrylov& m = st[t];
+        Outer& om = o[m.i];
+        const c128* hc = c.mem[m.i]->host;
+        const double est = m.lsq.add(j, hc);
+        om.est_rel = om.bnorm > 0 ? est / om.bnorm : 0.0;
+        m.steps = j + 1;
+        const bool broke = hc[j + 1].re <= 1e-14 * m.beta;
+        if (!broke) scale.push_back(t);
+        if (broke || (m.tol >= 0 && est <= m.tol * om.bnorm) || j + 1 >= m.maxit) continue;
+        next.push_back(t);
+      }
+      if (!scale.empty())
+        HM_CHECK(launch_scale_dev<double>(w, V + (size_t)(j + 1) * N, ws.h + j + 1, 1, N, p->s,
+                                          members(c, members_of(st, scale))));
+      run.swap(next);
     }
-    std::vector<c128> y;
-    lsq.solve(steps, y);
-    h2d_coef(p, y);
-    HM_CHECK(launch_combine<double>(X, N, steps, p->coef, 1.0, u, 1, N, p->s));
-    total += steps;
-    p->rec[K_OUTER].push_back(steps);
+    for (const auto& m : st) o[m.i].total += m.steps;
+    finish_members<double>(c, st, K_OUTER, X, N, u, 1);
   }
-  HM_CHECK(hipStreamSynchronize(p->s));
-  if (!p->pending.empty()) harvest(p);
-  p->last_estimate = est_rel;
-  if (info) {
+  wait_stream(c);
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool ok = true;
+  for (int i = 0; i < nb; ++i) {
+    hm_problem* q = c.mem[i];
+    q->last_estimate = o[i].est_rel;
+    ok = ok && o[i].rel_true <= cf.tol_outer;
+    if (!info) continue;
     auto sum_since = [&](int kind) {
       long s = 0;
-      for (size_t i = rec0[kind]; i < p->rec[kind].size(); ++i) s += p->rec[kind][i];
+      for (size_t r = o[i].rec0[kind]; r < q->rec[kind].size(); ++r) s += q->rec[kind][r];
       return (int)s;
     };
-    info->outer_iters = total;
-    info->level2_iters_total = sum_since(K_LEVEL2);
-    info->cslp_iters_total = sum_since(K_CSLP);
-    info->mg_coarse_iters_total = sum_since(K_MGC);
-    info->rel_res_estimate = est_rel;
-    info->rel_res_true = rel_true;
-    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    hm_solve_info& in = info[i];
+    in.outer_iters = o[i].total;
+    in.level2_iters_total = sum_since(K_LEVEL2);
+    in.cslp_iters_total = sum_since(K_CSLP);
+    in.mg_coarse_iters_total = sum_since(K_MGC);
+    in.rel_res_estimate = o[i].est_rel;
+    in.rel_res_true = o[i].rel_true;
+    in.seconds = secs;
   }
-  return rel_true <= cf.tol_outer ? HM_OK : HM_NOT_CONVERGED;
+  return ok ? HM_OK : HM_NOT_CONVERGED;
 }
 
 // ---- set-up ------------------------------------------------------------------------
@@ -887,6 +1096,10 @@ static void plan(hm_problem* p, Carver& cv) {
   p->scal = cv.take<c128>(16);
   p->coef_cap = mmax + 2;
   p->coef = cv.take<c128>(p->coef_cap);
+  if (p->batch_io) {
+    p->ub = cv.take<c128>(D1.N);
+    p->uu = cv.take<c128>(D1.N);
+  }
 }
 
 }  // namespace hm
@@ -1044,6 +1257,8 @@ static void op_transfer(hm_problem* p, int l, int which, const c128* in, c128* o
 
 template <typename T>
 static void op_level(hm_problem* p, int l, int sub, int which, const c128* in, c128* out) {
+  Ctx c(p);
+  const Act one{0};
   DefLevel& D = p->lev[l];
   size_t nin = D.N, nout = D.N;
   if (which >= HM_OP_MG_M) {
@@ -1057,8 +1272,8 @@ static void op_level(hm_problem* p, int l, int sub, int which, const c128* in, c
   const cx<T>* v = to_level<T>(p, in, nin, p->pin_v);
   cx<T>* o = out_level<T>(out, p->pin_x);
   switch (which) {
-    case HM_OP_A: apply_level<T>(p, D, false, ST_APPLY, v, nullptr, o); break;
-    case HM_OP_M: apply_level<T>(p, D, true, ST_APPLY, v, nullptr, o); break;
+    case HM_OP_A: apply_level<T>(c, one, D, false, ST_APPLY, v, nullptr, o); break;
+    case HM_OP_M: apply_level<T>(c, one, D, true, ST_APPLY, v, nullptr, o); break;
     case HM_OP_VCYCLE: {
       if (!D.has_mg) throw ArgError("level has no multigrid hierarchy");
       const cx<T>* src = v;
@@ -1066,18 +1281,18 @@ static void op_level(hm_problem* p, int l, int sub, int which, const c128* in, c
         HM_CHECK(hipMemcpyAsync(D.rt, v, sizeof(cx<T>) * D.N, hipMemcpyDeviceToDevice, p->s));
         src = (const cx<T>*)D.rt;
       }
-      const cx<T>* r = vcycle<T>(p, D, src);
+      const cx<T>* r = vcycle<T>(c, one, D, src);
       HM_CHECK(hipMemcpyAsync(o, r, sizeof(cx<T>) * D.N, hipMemcpyDeviceToDevice, p->s));
       break;
     }
     case HM_OP_CSLP: {
-      const cx<T>* r = cslp_apply<T>(p, l, v, o);
+      const cx<T>* r = cslp_apply<T>(c, one, l, v, o);
       if (r != o) HM_CHECK(hipMemcpyAsync(o, r, sizeof(cx<T>) * D.N, hipMemcpyDeviceToDevice, p->s));
       break;
     }
     case HM_OP_PRECOND:
       if (l >= p->L) throw ArgError("no preconditioner on the coarsest level");
-      precond<T>(p, l, v, o);
+      precond<T>(c, one, l, v, o);
       break;
     case HM_OP_MG_M: {
       const MGLevel& m = D.mg.lv[sub];
@@ -1124,7 +1339,82 @@ static hm_status guard(F&& f) {
   }
 }
 
+// Planned sizes of one problem: workspace bytes, and the pinned staging the
+// problem needs (entries of host / host_coef, and of the Hessenberg mirror).
+struct Sizes {
+  size_t bytes = 0;
+  int host_cap = 0;
+  size_t host_H_cap = 0;
+  int coef_cap = 0;
+};
+
+static Sizes plan_sizes(const hm_config& cfg, bool batch_io) {
+  hm_problem tmp;
+  tmp.cfg = cfg;
+  tmp.batch_io = batch_io;
+  Carver cv;
+  plan(&tmp, cv);
+  Sizes z;
+  z.bytes = (cv.off + 255) & ~size_t(255);
+  z.coef_cap = tmp.coef_cap;
+  z.host_cap = std::max(tmp.coef_cap, 16);
+  z.host_H_cap = std::max<size_t>(tmp.host_H_cap, 1);
+  return z;
+}
+
+static size_t host_stride(const Sizes& z) {
+  const size_t b = sizeof(c128) * (2 * (size_t)z.host_cap + z.host_H_cap);
+  return (b + 255) & ~size_t(255);
+}
+
+// A problem on the workspace at `base`.  host_block: pinned staging laid out as
+// host | host_coef | Hessenberg mirror, given by a batch (null: allocated here).
+static hm_problem* make_problem(const hm_config& cfg, char* base, hipStream_t stream,
+                                bool batch_io, char* host_block, const double* k_dev) {
+  hm_problem* p = new hm_problem();
+  try {
+    p->cfg = cfg;
+    p->s = stream;
+    p->batch_io = batch_io;
+    Carver cv;
+    cv.base = base;
+    plan(p, cv);
+    p->host_cap = std::max(p->coef_cap, 16);
+    const size_t hcap = std::max<size_t>(p->host_H_cap, 1);
+    if (host_block) {
+      p->own_host = false;
+      p->host = (c128*)host_block;
+      p->host_coef = p->host + p->host_cap;
+      p->host_H = p->host_coef + p->host_cap;
+    } else {
+      HM_CHECK(hipHostMalloc((void**)&p->host, sizeof(c128) * p->host_cap, hipHostMallocDefault));
+      HM_CHECK(hipHostMalloc((void**)&p->host_coef, sizeof(c128) * p->host_cap,
+                             hipHostMallocDefault));
+      HM_CHECK(hipHostMalloc((void**)&p->host_H, sizeof(c128) * hcap, hipHostMallocDefault));
+    }
+    HM_CHECK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    HM_CHECK(hipEventCreateWithFlags(&p->col_ev[0], hipEventDisableTiming));
+    HM_CHECK(hipEventCreateWithFlags(&p->col_ev[1], hipEventDisableTiming));
+    initialize(p, k_dev);
+  } catch (...) {
+    hm_destroy_problem(p);
+    throw;
+  }
+  return p;
+}
+
 }  // namespace hm
+
+// A batch: members with one configuration, member i's workspace i * dz bytes
+// after member 0's, the coefficient rows after the last member.
+struct hm_batch {
+  std::vector<hm_problem*> mem;
+  long long dz = 0, hz = 0;
+  char* host_block = nullptr;   // pinned staging of all members, hz apart
+  c128* coef = nullptr;         // device, nb rows of coef_ld
+  c128* host_coef = nullptr;    // pinned, the same rows
+  size_t coef_ld = 0;
+};
 
 // ================================ C ABI ======================================
 
@@ -1176,27 +1466,7 @@ hm_status hm_create_problem(const hm_config* cfg, const double* k_dev, void* wor
       g_last_error = "workspace too small: need " + std::to_string(need) + " bytes";
       return HM_ERR_NOMEM;
     }
-    hm_problem* p = new hm_problem();
-    try {
-      p->cfg = *cfg;
-      p->s = (hipStream_t)stream;
-      Carver cv;
-      cv.base = (char*)workspace;
-      plan(p, cv);
-      p->host_cap = std::max(p->coef_cap, 16);
-      HM_CHECK(hipHostMalloc((void**)&p->host, sizeof(c128) * p->host_cap, hipHostMallocDefault));
-      HM_CHECK(hipHostMalloc((void**)&p->host_coef, sizeof(c128) * p->host_cap, hipHostMallocDefault));
-      HM_CHECK(hipHostMalloc((void**)&p->host_H, sizeof(c128) * std::max<size_t>(p->host_H_cap, 1),
-                             hipHostMallocDefault));
-      HM_CHECK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-      HM_CHECK(hipEventCreateWithFlags(&p->col_ev[0], hipEventDisableTiming));
-      HM_CHECK(hipEventCreateWithFlags(&p->col_ev[1], hipEventDisableTiming));
-      initialize(p, k_dev);
-    } catch (...) {
-      hm_destroy_problem(p);
-      throw;
-    }
-    *out = p;
+    *out = make_problem(*cfg, (char*)workspace, (hipStream_t)stream, false, nullptr, k_dev);
     return HM_OK;
   });
 }
@@ -1206,7 +1476,8 @@ hm_status hm_precond_apply(hm_problem* p, const void* v_dev, void* x_dev, void* 
     if (!p || !v_dev || !x_dev) throw ArgError("null argument");
     if (v_dev == x_dev) throw ArgError("v and x must not alias");
     p->s = (hipStream_t)stream;
-    precond_top(p, (const c128*)v_dev, (c128*)x_dev);
+    Ctx c(p);
+    precond_top(c, Act{0}, (const c128*)v_dev, (c128*)x_dev);
     HM_CHECK(hipStreamSynchronize(p->s));
     return HM_OK;
   });
@@ -1218,7 +1489,8 @@ hm_status hm_fgmres_solve(hm_problem* p, const void* b_dev, void* u_dev, hm_solv
     if (!p || !b_dev || !u_dev) throw ArgError("null argument");
     if (b_dev == u_dev) throw ArgError("b and u must not alias");
     p->s = (hipStream_t)stream;
-    return outer_solve(p, (const c128*)b_dev, (c128*)u_dev, info);
+    Ctx c(p);
+    return outer_solve(c, (const c128*)b_dev, (c128*)u_dev, info);
   });
 }
 
@@ -1292,14 +1564,126 @@ hm_status hm_destroy_problem(hm_problem* p) {
     (void)hipEventDestroy(e.second);
   }
   for (auto& D : p->lev)
-    if (D.mg.graph) (void)hipGraphExecDestroy(D.mg.graph);
+    for (auto& g : D.mg.graphs) (void)hipGraphExecDestroy(g.second);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (auto& e : p->col_ev)
     if (e) (void)hipEventDestroy(e);
-  if (p->host_H) (void)hipHostFree(p->host_H);
-  if (p->host) (void)hipHostFree(p->host);
-  if (p->host_coef) (void)hipHostFree(p->host_coef);
+  if (p->own_host) {
+    if (p->host_H) (void)hipHostFree(p->host_H);
+    if (p->host) (void)hipHostFree(p->host);
+    if (p->host_coef) (void)hipHostFree(p->host_coef);
+  }
   delete p;
+  return HM_OK;
+}
+
+size_t hm_batch_workspace_bytes(const hm_config* cfg, int nb) {
+  std::string why;
+  if (!validate(cfg, &why)) {
+    g_last_error = why;
+    return 0;
+  }
+  if (nb < 1 || nb > kMaxBatch) {
+    g_last_error = "batch size must be in [1, " + std::to_string(kMaxBatch) + "]";
+    return 0;
+  }
+  try {
+    const Sizes z = plan_sizes(*cfg, true);
+    const size_t rows = ((size_t)nb * z.coef_cap * sizeof(c128) + 255) & ~size_t(255);
+    return (size_t)nb * z.bytes + rows;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return 0;
+  }
+}
+
+hm_status hm_create_batch(const hm_config* cfg, int nb, const double* const* k_dev,
+                          void* workspace, size_t workspace_bytes, void* stream, hm_batch** out) {
+  if (out) *out = nullptr;
+  return guard([&]() -> hm_status {
+    std::string why;
+    if (!out) throw ArgError("out is null");
+    if (!validate(cfg, &why)) throw ArgError(why);
+    if (nb < 1 || nb > kMaxBatch)
+      throw ArgError("batch size must be in [1, " + std::to_string(kMaxBatch) + "]");
+    if (!k_dev || !workspace) throw ArgError("null pointer");
+    for (int i = 0; i < nb; ++i)
+      if (!k_dev[i]) throw ArgError("null wavenumber pointer");
+    if (((uintptr_t)workspace) & 255) throw ArgError("workspace must be 256-byte aligned");
+    const size_t need = hm_batch_workspace_bytes(cfg, nb);
+    if (workspace_bytes < need) {
+      g_last_error = "workspace too small: need " + std::to_string(need) + " bytes";
+      return HM_ERR_NOMEM;
+    }
+    const Sizes z = plan_sizes(*cfg, true);
+    hm_batch* bt = new hm_batch();
+    try {
+      bt->dz = (long long)z.bytes;
+      bt->hz = (long long)host_stride(z);
+      bt->coef_ld = (size_t)z.coef_cap;
+      bt->coef = (c128*)((char*)workspace + (size_t)nb * z.bytes);
+      HM_CHECK(hipHostMalloc((void**)&bt->host_block, (size_t)nb * bt->hz, hipHostMallocDefault));
+      HM_CHECK(hipHostMalloc((void**)&bt->host_coef, sizeof(c128) * nb * bt->coef_ld,
+                             hipHostMallocDefault));
+      for (int i = 0; i < nb; ++i)
+        bt->mem.push_back(make_problem(*cfg, (char*)workspace + (size_t)i * z.bytes,
+                                       (hipStream_t)stream, true,
+                                       bt->host_block + (size_t)i * bt->hz, k_dev[i]));
+      // one layout: every pointer of member i is member 0's plus i * dz
+      for (int i = 1; i < nb; ++i)
+        if ((char*)bt->mem[i]->uu - (char*)bt->mem[0]->uu != (long long)i * bt->dz ||
+            (char*)bt->mem[i]->host_H - (char*)bt->mem[0]->host_H != (long long)i * bt->hz)
+          throw std::logic_error("batch members differ in layout");
+    } catch (...) {
+      hm_destroy_batch(bt);
+      throw;
+    }
+    *out = bt;
+    return HM_OK;
+  });
+}
+
+hm_status hm_batch_solve(hm_batch* bt, const void* const* b_dev, void* const* u_dev,
+                         hm_solve_info* info, void* stream) {
+  return guard([&]() -> hm_status {
+    if (!bt || !b_dev || !u_dev) throw ArgError("null argument");
+    const int nb = (int)bt->mem.size();
+    for (int i = 0; i < nb; ++i) {
+      if (!b_dev[i] || !u_dev[i]) throw ArgError("null vector pointer");
+      if (b_dev[i] == u_dev[i]) throw ArgError("b and u must not alias");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (hm_problem* q : bt->mem) q->s = s;
+    hm_problem* p = bt->mem[0];
+    const size_t bytes = sizeof(c128) * p->lev[1].N;
+    for (int i = 0; i < nb; ++i)
+      HM_CHECK(hipMemcpyAsync(bt->mem[i]->ub, b_dev[i], bytes, hipMemcpyDeviceToDevice, s));
+    Ctx c(p);
+    c.mem = bt->mem;
+    c.dz = bt->dz;
+    c.hz = bt->hz;
+    c.coef = bt->coef;
+    c.host_coef = bt->host_coef;
+    c.coef_ld = bt->coef_ld;
+    const hm_status st = outer_solve(c, p->ub, p->uu, info);
+    for (int i = 0; i < nb; ++i)
+      HM_CHECK(hipMemcpyAsync(u_dev[i], bt->mem[i]->uu, bytes, hipMemcpyDeviceToDevice, s));
+    HM_CHECK(hipStreamSynchronize(s));
+    return st;
+  });
+}
+
+hm_problem* hm_batch_member(hm_batch* bt, int i) {
+  if (!bt || i < 0 || i >= (int)bt->mem.size()) return nullptr;
+  return bt->mem[i];
+}
+
+hm_status hm_destroy_batch(hm_batch* bt) {
+  if (!bt) return HM_ERR_ARG;
+  for (hm_problem* q : bt->mem) hm_destroy_problem(q);
+  if (bt->host_block) (void)hipHostFree(bt->host_block);
+  if (bt->host_coef) (void)hipHostFree(bt->host_coef);
+  delete bt;
   return HM_OK;
 }
 

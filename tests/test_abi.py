@@ -98,3 +98,34 @@ def test_matvec_entry_points_reject_bad_sizes_on_the_host():
     assert lib.hm_matfree_apply(5, 5, 0.1, nul, nul, nul, nul) == hm.HM_ERR_ARG
     assert lib.hm_csr_spmv(-1, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
     assert lib.hm_csr_spmv(4, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
+
+
+def test_batch_workspace_and_argument_checks_on_the_host():
+    """A batch of nb members needs nb single-problem layouts (plus two solution
+    copies each and the coefficient rows); sizes and pointers are checked before
+    any device call."""
+    import paper_2412_04980_amd as hm
+    c = hm.default_config(129, 129, 1 / 128)
+    one = hm.workspace_bytes(c)
+    b1 = hm.batch_workspace_bytes(c, 1)
+    b4 = hm.batch_workspace_bytes(c, 4)
+    assert b1 >= one + 2 * 16 * 129 * 129
+    assert b4 >= 4 * (one + 2 * 16 * 129 * 129)
+    assert b4 % 256 == 0
+    for nb in (0, -1, hm.MAX_BATCH + 1):
+        with pytest.raises(hm.HelmDeflError):
+            hm.batch_workspace_bytes(c, nb)
+    bad = hm.default_config(130, 129, 1 / 128)
+    with pytest.raises(hm.HelmDeflError):
+        hm.batch_workspace_bytes(bad, 2)
+    lib = hm._lib
+    out = ctypes.c_void_p()
+    ks = (ctypes.c_void_p * 2)(None, None)
+    assert lib.hm_create_batch(ctypes.byref(c), 0, ks, ctypes.c_void_p(256), b4, None,
+                               ctypes.byref(out)) == hm.HM_ERR_ARG
+    assert lib.hm_create_batch(ctypes.byref(c), 2, ks, ctypes.c_void_p(256), b4, None,
+                               ctypes.byref(out)) == hm.HM_ERR_ARG
+    assert "wavenumber" in lib.hm_last_error().decode()
+    assert lib.hm_batch_solve(None, None, None, None, None) == hm.HM_ERR_ARG
+    assert lib.hm_batch_member(None, 0) is None
+    assert lib.hm_destroy_batch(None) == hm.HM_ERR_ARG
