@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=60)
     ap.add_argument("--rate", type=float, default=50.0, help="offered requests/s")
     ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--no-batching", action="store_true",
+                    help="serving: one request per stream, no lockstep batches")
+    ap.add_argument("--max-members", type=int, default=16,
+                    help="serving: right-hand sides per lockstep batch (at most 16)")
     ap.add_argument("--matvec", action="store_true",
                     help="matrix-free versus CSR matvec of the finest operator on grids "
                          "17^2 .. 16385^2 (100 consecutive products per form and size)")
@@ -185,9 +189,16 @@ def serving_bench(args):
     for j in jobs:
         if j.nx not in seen:
             seen.add(j.nx)
-            ex(type(j)(j.rid, 0.0, j.nx, j.ny, j.h, j.k, j.rhs[:1]))
+            one = type(j)(j.rid, 0.0, j.nx, j.ny, j.h, j.k, j.rhs[:1])
+            ex(one) if args.no_batching else ex.run_group([one])
     torch.cuda.synchronize()
-    sched = Scheduler(ex, ex.bytes_needed, budget, max_active=args.max_active, realtime=True)
+    if args.no_batching:
+        sched = Scheduler(ex, ex.bytes_needed, budget, max_active=args.max_active, realtime=True)
+    else:
+        # same-size requests waiting together run as one lockstep batch
+        sched = Scheduler(ex.run_group, ex.group_bytes, budget, max_active=args.max_active,
+                          realtime=True, group_key=ex.group_key,
+                          max_members=min(args.max_members, 16), members=ex.members)
     t0 = time.perf_counter()
     res = sched.run(jobs)
     wall = time.perf_counter() - t0
@@ -206,6 +217,9 @@ def serving_bench(args):
            "value": summ["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
            "higher_is_better": True, "offered_requests_per_s": args.rate,
            "max_active": args.max_active, "budget_bytes": budget, "data": "synthetic",
+           "batching": {"lockstep": not args.no_batching, "groups": len(sched.groups),
+                        "mean_requests_per_group": len(jobs) / max(1, len(sched.groups)),
+                        "max_members": 1 if args.no_batching else min(args.max_members, 16)},
            "config": {"workload": "serving stream (Poisson, random media, 257^2..2049^2)"},
            **summ, "by_grid": by_class,
            "max_concurrent": max(e[4] for e in sched.events)}

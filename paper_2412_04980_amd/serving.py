@@ -10,6 +10,14 @@ and its kernels overlap on the device with those of the other running requests.
 When a request finishes, its memory returns to the budget and the next waiting
 request is admitted, without waiting for the others (no batch barrier).
 
+With grouping on (`group_key`), a request admitted at the head of the queue
+takes along the waiting requests of the same grid class (same key) that fit in
+the member limit and the memory budget, and the group runs as one lockstep
+batch of the library (hm_create_batch / hm_batch_solve): every right-hand side
+of every request in the group is a batch member with its request's medium, and
+each kernel launch sweeps the same level of all members still iterating.  Each
+member's result is bitwise that of its solve alone.
+
 The scheduler is independent of the GPU: `Scheduler` takes an `execute(job)`
 callable and a `bytes_needed(job)` estimate, so the admission logic runs with a
 simulated executor on the CPU as well.  `GpuExecutor` is the MI355X executor that
@@ -54,9 +62,15 @@ class JobResult:
 
 
 class Scheduler:
-    """Admits jobs FIFO under a slot limit and a memory budget; runs them concurrently."""
+    """Admits jobs FIFO under a slot limit and a memory budget; runs them concurrently.
 
-    def __init__(self, execute, bytes_needed, budget_bytes, max_active=4, realtime=True):
+    Without grouping, execute(job) and bytes_needed(job) take one job.  With
+    group_key set, they take a list of jobs (a group of one key, at most
+    max_members members counted by members(job)) and execute returns one
+    (infos, solutions) pair per job of the group."""
+
+    def __init__(self, execute, bytes_needed, budget_bytes, max_active=4, realtime=True,
+                 group_key=None, max_members=1, members=None):
         if max_active < 1:
             raise ValueError("max_active must be >= 1")
         self.execute = execute
@@ -64,16 +78,40 @@ class Scheduler:
         self.budget = int(budget_bytes)
         self.max_active = max_active
         self.realtime = realtime
+        self.group_key = group_key
+        self.max_members = max(1, int(max_members))
+        self.members = members or (lambda job: 1)
         self.events = []               # (time, kind, rid, in_use_bytes, active)
+        self.groups = []               # rids of each admitted group, in admission order
+
+    def _need(self, group):
+        return self.bytes_needed(group if self.group_key is not None else group[0])
+
+    def _group(self, waiting, in_use):
+        """The head job and, with grouping, the waiting jobs of its key that fit."""
+        head = waiting[0]
+        group = [head]
+        if self.group_key is None:
+            return group
+        key = self.group_key(head)
+        count = self.members(head)
+        for job in list(waiting)[1:]:
+            if self.group_key(job) != key or count + self.members(job) > self.max_members:
+                continue
+            if in_use + self._need(group + [job]) > self.budget:
+                break
+            group.append(job)
+            count += self.members(job)
+        return group
 
     def run(self, jobs):
         """Runs all jobs; returns their results in arrival order.  With
         realtime=False every job is available at time 0 (arrival times ignored)."""
         jobs = sorted(jobs, key=lambda j: (j.arrival, j.rid))
         for j in jobs:
-            if self.bytes_needed(j) > self.budget:
+            if self._need([j]) > self.budget:
                 raise ValueError("request %d needs %d bytes, more than the whole budget %d"
-                                 % (j.rid, self.bytes_needed(j), self.budget))
+                                 % (j.rid, self._need([j]), self.budget))
         cond = threading.Condition()          # re-entrant lock inside
         pending = collections.deque(jobs)     # not yet arrived
         waiting = collections.deque()         # arrived, not admitted (FIFO)
@@ -87,17 +125,22 @@ class Scheduler:
         def arrival(job):
             return job.arrival if self.realtime else 0.0
 
-        def finished(job, admitted, need, fut):
+        def finished(group, admitted, need, fut):
             with cond:
                 state["in_use"] -= need
                 state["active"] -= 1
                 try:
-                    infos, sols = fut.result()
-                    results[job.rid] = JobResult(job.rid, arrival(job), admitted, clock(), infos,
-                                                 sols)
+                    out = fut.result()
+                    if self.group_key is None:
+                        out = [out]
+                    done = clock()
+                    for job, (infos, sols) in zip(group, out):
+                        results[job.rid] = JobResult(job.rid, arrival(job), admitted, done,
+                                                     infos, sols)
                 except BaseException as e:    # re-raised by run()
                     state["error"] = e
-                self.events.append((clock(), "finish", job.rid, state["in_use"], state["active"]))
+                self.events.append((clock(), "finish", group[0].rid, state["in_use"],
+                                    state["active"]))
                 cond.notify_all()
 
         pool = ThreadPoolExecutor(max_workers=self.max_active)
@@ -111,20 +154,23 @@ class Scheduler:
                         waiting.append(pending.popleft())
                     # admit in arrival order while a slot and the memory are free
                     while waiting and state["active"] < self.max_active:
-                        job = waiting[0]
-                        need = self.bytes_needed(job)
+                        group = self._group(waiting, state["in_use"])
+                        need = self._need(group)
                         if state["in_use"] + need > self.budget:
                             break
-                        waiting.popleft()
+                        for job in group:
+                            waiting.remove(job)
                         state["in_use"] += need
                         state["active"] += 1
                         admitted = clock()
-                        self.events.append((admitted, "admit", job.rid, state["in_use"],
+                        self.groups.append([job.rid for job in group])
+                        self.events.append((admitted, "admit", group[0].rid, state["in_use"],
                                             state["active"]))
-                        fut = pool.submit(self.execute, job)
+                        fut = pool.submit(self.execute,
+                                          group if self.group_key is not None else group[0])
                         fut.add_done_callback(
-                            lambda f, job=job, admitted=admitted, need=need:
-                            finished(job, admitted, need, f))
+                            lambda f, group=group, admitted=admitted, need=need:
+                            finished(group, admitted, need, f))
                     if not (pending or waiting or state["active"]):
                         break
                     timeout = 0.5
@@ -159,7 +205,10 @@ def summarize(results, wall_seconds):
 class GpuExecutor:
     """Runs one request on the GPU: uploads its medium, builds its hierarchy in a
     fresh workspace, solves every right-hand side, frees everything.  Each worker
-    thread owns one stream (default priority)."""
+    thread owns one stream (default priority).  run_group / group_bytes /
+    group_key / members are the grouped counterparts for a Scheduler with
+    grouping: the right-hand sides of the group's requests become the members
+    of lockstep batches of at most MAX_BATCH members."""
 
     def __init__(self, precision=None, keep_solutions=False, device="cuda:0", overrides=None):
         import torch
@@ -180,6 +229,44 @@ class GpuExecutor:
     def bytes_needed(self, job):
         n = job.nx * job.ny
         return self.hm.workspace_bytes(self.config(job)) + 256 + 8 * n + 2 * 16 * n + (1 << 20)
+
+    def group_key(self, job):
+        return (job.nx, job.ny, job.h)
+
+    def members(self, job):
+        return len(job.rhs)
+
+    def group_bytes(self, jobs):
+        n = jobs[0].nx * jobs[0].ny
+        nm = sum(len(j.rhs) for j in jobs)
+        ws = self.hm.batch_workspace_bytes(self.config(jobs[0]), min(nm, self.hm.MAX_BATCH))
+        return ws + 256 + 8 * n * len(jobs) + 2 * 16 * n * nm + (1 << 20)
+
+    def run_group(self, jobs):
+        """Solves every right-hand side of the jobs (one grid class) in lockstep
+        batches; returns one (infos, solutions) pair per job."""
+        torch, hm = self.torch, self.hm
+        s = self._stream()
+        members = [(q, r) for q, job in enumerate(jobs) for r in range(len(job.rhs))]
+        infos = [[None] * len(job.rhs) for job in jobs]
+        sols = [[None] * len(job.rhs) for job in jobs]
+        with torch.cuda.stream(s):
+            ks = [torch.from_numpy(job.k).to(self.device) for job in jobs]
+            cfg = self.config(jobs[0])
+            for c0 in range(0, len(members), hm.MAX_BATCH):
+                chunk = members[c0:c0 + hm.MAX_BATCH]
+                bt = hm.create_batch(cfg, [ks[q] for q, _ in chunk], stream=s)
+                try:
+                    bs = [torch.from_numpy(jobs[q].rhs[r]).to(self.device) for q, r in chunk]
+                    us, out = hm.batch_solve(bt, bs, stream=s)
+                    for (q, r), u, d in zip(chunk, us, out):
+                        infos[q][r] = d
+                        if self.keep:
+                            sols[q][r] = u.cpu().numpy()
+                finally:
+                    s.synchronize()
+                    bt.close()
+        return [(infos[q], sols[q] if self.keep else None) for q in range(len(jobs))]
 
     def _stream(self):
         s = getattr(self._local, "stream", None)

@@ -46,3 +46,25 @@ def test_results_identical_alone_and_in_the_mix(precision):
         for s, rhs in enumerate(j.rhs):
             assert np.linalg.norm(rhs - A @ r.solutions[s]) <= 1e-6 * np.linalg.norm(rhs)
             assert r.infos[s]["outer_iters"] == alone_infos[s]["outer_iters"]
+
+
+@pytest.mark.parametrize("precision", [hm.HM_FP64, hm.HM_MIXED_FP32])
+def test_grouped_requests_run_as_lockstep_batches(precision):
+    """With grouping, same-size requests waiting together run as one lockstep
+    batch (every right-hand side a member); each result is bitwise the result
+    of the request solved alone."""
+    jobs = small_jobs(seed=12, n_jobs=8)
+    ex = GpuExecutor(precision=precision, keep_solutions=True)
+    budget = 4 * max(ex.group_bytes([j]) for j in jobs) + sum(ex.group_bytes([j]) for j in jobs)
+    sched = Scheduler(ex.run_group, ex.group_bytes, budget, max_active=2, realtime=False,
+                      group_key=ex.group_key, max_members=hm.MAX_BATCH, members=ex.members)
+    grouped = sched.run(jobs)
+    assert any(len(g) > 1 for g in sched.groups)           # batches of several requests
+    by_rid = {j.rid: j for j in jobs}
+    for g in sched.groups:
+        assert len({(by_rid[r].nx, by_rid[r].ny) for r in g}) == 1
+    for j, r in zip(jobs, grouped):
+        alone_infos, alone = ex(j)
+        for s, (ua, um) in enumerate(zip(alone, r.solutions)):
+            assert np.array_equal(ua, um), (j.rid, s)
+            assert r.infos[s]["outer_iters"] == alone_infos[s]["outer_iters"]

@@ -82,3 +82,39 @@ def test_executor_error_propagates():
     s = Scheduler(bad, lambda j: 1, budget_bytes=10, max_active=2, realtime=False)
     with pytest.raises(RuntimeError):
         s.run([job(0, 0.0, 1), job(1, 0.0, 1)])
+
+
+class FakeGroupExecutor:
+    def __init__(self):
+        self.groups = []
+
+    def __call__(self, group):
+        self.groups.append([j.rid for j in group])
+        time.sleep(0.01)
+        return [([{"rel_res_true": 1e-7}] * len(j.rhs), None) for j in group]
+
+
+def gjob(rid, key, nrhs=1, size=10):
+    return Job(rid, 0.0, key, key, 1.0, None, [None] * nrhs, {"size": size})
+
+
+def test_grouping_takes_same_key_jobs_within_member_and_memory_limits():
+    ex = FakeGroupExecutor()
+    jobs = [gjob(0, 65, 2), gjob(1, 129), gjob(2, 65, 3), gjob(3, 65, 2), gjob(4, 129, 1),
+            gjob(5, 65, 1)]
+    s = Scheduler(ex, lambda g: sum(j.meta["size"] for j in g), budget_bytes=1000, max_active=1,
+                  realtime=False, group_key=lambda j: j.nx, max_members=6,
+                  members=lambda j: len(j.rhs))
+    res = s.run(jobs)
+    assert [r.rid for r in res] == list(range(6))
+    # head 0 (2) takes 2 (3) and 5 (1): 6 members, 3 (2) does not fit; then the
+    # 129 class, then the rest
+    assert s.groups == [[0, 2, 5], [1, 4], [3]]
+    assert ex.groups == s.groups
+    assert all(len(r.infos) == len(j.rhs) for r, j in zip(res, jobs))
+    # the memory budget also bounds a group
+    s2 = Scheduler(FakeGroupExecutor(), lambda g: sum(j.meta["size"] for j in g), budget_bytes=25,
+                   max_active=1, realtime=False, group_key=lambda j: j.nx, max_members=16,
+                   members=lambda j: len(j.rhs))
+    s2.run([gjob(i, 65) for i in range(5)])
+    assert s2.groups == [[0, 1], [2, 3], [4]]
