@@ -19,6 +19,7 @@ Other measurements, each one JSON line of its own:
     --matvec       matrix-free vs CSR product of the finest operator, 17^2..16385^2
     --complexity   five-level MADP on the wedge stand-in at kh = 0.1745, 145x241..4609x7681
     --variants     MADP-v3, W-cycle, fixed steps and deeper hierarchies on the bench workload
+    --shots        every right-hand side of --config I, sequential vs one lockstep batch
 """
 import argparse
 import json
@@ -79,6 +80,10 @@ def parse():
     ap.add_argument("--variants", action="store_true",
                     help="the method variants (MADP-v3, W-cycle, fixed steps, tolerance on "
                          "level 3, 4 levels) on the benchmark workload, FP64")
+    ap.add_argument("--shots", action="store_true",
+                    help="all right-hand sides of the workload (config 3: 8 surface shots), "
+                         "solved one after another and as one lockstep batch")
+    ap.add_argument("--shots-precision", choices=("fp64", "mixed"), default="mixed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size, to calibrate hardware byte counters)")
@@ -407,6 +412,63 @@ def variants_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def shots_bench(args):
+    """Every right-hand side of one medium: sequential solves on one problem against
+    one lockstep batch of all of them (members share the medium).  The timed
+    region of each leg holds every solve of its shots; one untimed pass first."""
+    import numpy as np
+    import torch
+
+    import paper_2412_04980_amd as hm
+    import workloads
+
+    dev = torch.device("cuda:0")
+    problem = workloads.config(args.config)
+    nrhs = len(problem.sources)
+    if nrhs > hm.MAX_BATCH:
+        raise SystemExit("at most %d right-hand sides per batch" % hm.MAX_BATCH)
+    prec = hm.HM_MIXED_FP32 if args.shots_precision == "mixed" else hm.HM_FP64
+    cfg = hm.default_config(problem.nx, problem.ny, problem.h, precision=prec)
+    k = torch.from_numpy(problem.k).to(dev)
+    bs = [torch.from_numpy(problem.rhs(s)).to(dev) for s in range(nrhs)]
+    log("shots: %s, %d right-hand sides, %s" % (problem.name, nrhs, args.shots_precision))
+    prob = hm.create_problem(cfg, k)
+    seq = [torch.empty_like(b) for b in bs]
+    hm.fgmres_solve(prob, bs[0], out=seq[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_infos = [hm.fgmres_solve(prob, b, out=u)[1] for b, u in zip(bs, seq)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    prob.close()
+    log("sequential: %.3f s" % t_seq)
+    bt = hm.create_batch(cfg, [k] * nrhs)
+    outs = [torch.empty_like(b) for b in bs]
+    hm.batch_solve(bt, bs, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, bat_infos = hm.batch_solve(bt, bs, outs=outs)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    bt.close()
+    log("lockstep batch: %.3f s" % t_bat)
+    same = all(torch.equal(a, b) for a, b in zip(seq, outs))
+    res = {"metric": "shots: solves/s, sequential solves vs one lockstep batch",
+           "value": nrhs / t_bat, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32 precond / f64 outer" if prec == hm.HM_MIXED_FP32 else "f64",
+           "data": "synthetic",
+           "config": {"workload": problem.name, "nx": problem.nx, "ny": problem.ny,
+                      "right_hand_sides": nrhs},
+           "sequential": {"seconds": t_seq, "solves_per_s": nrhs / t_seq},
+           "lockstep_batch": {"seconds": t_bat, "solves_per_s": nrhs / t_bat},
+           "speedup": t_seq / t_bat,
+           "bitwise_equal_to_sequential": same,
+           "outer_iters": [i["outer_iters"] for i in bat_infos],
+           "max_rel_res_true": max(i["rel_res_true"] for i in bat_infos),
+           "sequential_outer_iters": [i["outer_iters"] for i in seq_infos]}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -431,6 +493,9 @@ def main():
         return
     if args.variants:
         variants_bench(args)
+        return
+    if args.shots:
+        shots_bench(args)
         return
     dev = torch.device("cuda:0")
     if args.copy_calibration:
