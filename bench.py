@@ -582,6 +582,20 @@ def main():
                         "outer_iters": infm[-1]["outer_iters"],
                         "rel_res_true": infm[-1]["rel_res_true"],
                         "rel_err_vs_fp64_solution": err, "dtype": "f32 precond / f64 outer"}
+        # every preconditioner level in FP32, the coarsest problem included
+        cfga = hm.default_config(problem.nx, problem.ny, problem.h,
+                                 precision=hm.HM_MIXED_FP32_ALL)
+        proba = hm.create_problem(cfga, k)
+        ua, tota, lata, infa, _ = timed_solves(hm, torch, proba, b, args.steps, args.warmup, False)
+        proba.close()
+        erra = float(torch.linalg.vector_norm(ua - u64) / torch.linalg.vector_norm(u64))
+        la = np.array(lata) * 1e3
+        res["mixed_all_levels"] = {
+            "value": args.steps / tota, "unit": "solves/s",
+            "p50_ms": float(np.percentile(la, 50)), "p99_ms": float(np.percentile(la, 99)),
+            "outer_iters": infa[-1]["outer_iters"], "rel_res_true": infa[-1]["rel_res_true"],
+            "rel_err_vs_fp64_solution": erra,
+            "dtype": "f32 preconditioner incl. coarsest problem / f64 outer"}
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(problem, info, counts_l3)
     print(json.dumps(res), flush=True)

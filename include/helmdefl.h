@@ -63,11 +63,20 @@ typedef enum {
  * on the boundary; the solution then does too. */
 typedef enum { HM_BC_SOMMERFELD = 0, HM_BC_DIRICHLET = 1 } hm_bc;
 
+/* Precision of the preconditioner (the outer FGMRES is FP64 in every mode).  The
+ * paper computes in FP64 throughout; the mixed modes are this library's.
+ * HM_MIXED_FP32 keeps the coarsest problem (the solve on the deepest deflation
+ * level, Sec. 4.1) in FP64; HM_MIXED_FP32_ALL runs it in FP32 as well.
+ * Reductions accumulate in FP64 throughout, and the dense coarsest multigrid
+ * inverse is applied in FP64 in every mode. */
 typedef enum {
-  HM_FP64 = 0,        /* every step in complex128                                     */
-  HM_MIXED_FP32 = 1   /* preconditioner levels 1-2 in complex64 with FP32 arithmetic;
-                         outer FGMRES (Arnoldi/MGS, Givens, true residual) and the
-                         coarsest-level solve in complex128                           */
+  HM_FP64 = 0,          /* every step in complex128                                   */
+  HM_MIXED_FP32 = 1,    /* preconditioner levels 1-2 in complex64 with FP32 arithmetic;
+                           outer FGMRES (Arnoldi/MGS, Givens, true residual) and the
+                           coarsest-level solve (levels >= 3) in complex128           */
+  HM_MIXED_FP32_ALL = 2 /* every preconditioner level, the coarsest-level solve
+                           included, in complex64 with FP32 arithmetic; outer FGMRES
+                           in complex128                                               */
 } hm_precision;
 
 typedef struct {

@@ -31,7 +31,7 @@ LIB_PATH = os.path.join(_HERE, "libhelmdefl.so")
 
 HM_OK, HM_NOT_CONVERGED = 0, 1
 HM_ERR_ARG, HM_ERR_NOMEM, HM_ERR_HIP, HM_ERR_STATE = -1, -2, -3, -4
-HM_FP64, HM_MIXED_FP32 = 0, 1
+HM_FP64, HM_MIXED_FP32, HM_MIXED_FP32_ALL = 0, 1, 2
 HM_BC_SOMMERFELD, HM_BC_DIRICHLET = 0, 1
 
 HM_OP_A, HM_OP_M, HM_OP_ZT, HM_OP_Z, HM_OP_VCYCLE, HM_OP_CSLP, HM_OP_PRECOND = range(7)

@@ -753,8 +753,10 @@ __global__ void __launch_bounds__(NT) k_combine(const cx<T>* __restrict__ V, siz
   out[i] = mk((T)re, (T)im);
 }
 
+// y = A x with A in complex128 in every precision (the coarsest multigrid
+// solve stays FP64); x is widened exactly, y rounded to the level's type.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_dense_matvec(const cx<T>* __restrict__ A, int n,
+__global__ void __launch_bounds__(NT) k_dense_matvec(const c128* __restrict__ A, int n,
                                                      const cx<T>* __restrict__ x, cx<T>* __restrict__ y,
                                                      Batch z) {
   const int i = blockIdx.x * NT + threadIdx.x;
@@ -762,10 +764,10 @@ __global__ void __launch_bounds__(NT) k_dense_matvec(const cx<T>* __restrict__ A
   HM_MEMBER(A); HM_MEMBER(x); HM_MEMBER(y);
   double re = 0, im = 0;
   for (int j = 0; j < n; ++j) {
-    const cx<T> a = A[(size_t)i * n + j];
+    const c128 a = A[(size_t)i * n + j];
     const cx<T> v = x[j];
-    re += (double)a.re * (double)v.re - (double)a.im * (double)v.im;
-    im += (double)a.re * (double)v.im + (double)a.im * (double)v.re;
+    re += a.re * (double)v.re - a.im * (double)v.im;
+    im += a.re * (double)v.im + a.im * (double)v.re;
   }
   y[i] = mk((T)re, (T)im);
 }
@@ -1264,7 +1266,7 @@ hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, s
 }
 
 template <typename T>
-hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s,
+hipError_t launch_dense_matvec(const c128* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s,
                                const Batch& z) {
   k_dense_matvec<T><<<zgrid(blocks1d((size_t)n), z), NT, 0, s>>>(A, n, x, y, z);
   return hipGetLastError();
@@ -1423,7 +1425,7 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
   template hipError_t launch_scale_dev<T>(const cx<T>*, cx<T>*, const c128*, int, size_t,          \
                                           hipStream_t, const Batch&);                               \
   template hipError_t launch_zero<T>(cx<T>*, size_t, hipStream_t, const Batch&);                   \
-  template hipError_t launch_dense_matvec<T>(const cx<T>*, int, const cx<T>*, cx<T>*, hipStream_t, \
+  template hipError_t launch_dense_matvec<T>(const c128*, int, const cx<T>*, cx<T>*, hipStream_t,  \
                                              const Batch&);                                         \
   template hipError_t launch_combine<T>(const cx<T>*, size_t, int, const c128*, size_t, double,    \
                                         cx<T>*, int, size_t, hipStream_t, const Batch&);            \

@@ -123,9 +123,10 @@ hipError_t launch_combine(const cx<T>* V, size_t ldv, int m, const c128* coef, s
                           double sign, cx<T>* out, int accumulate, size_t n, hipStream_t s,
                           const Batch& z = Batch());
 
-// y = A x with A a dense n x n row-major matrix (coarsest multigrid solve)
+// y = A x with A a dense n x n row-major complex128 matrix (coarsest multigrid
+// solve, FP64 in every precision; x widened, y rounded to T)
 template <typename T>
-hipError_t launch_dense_matvec(const cx<T>* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s,
+hipError_t launch_dense_matvec(const c128* A, int n, const cx<T>* x, cx<T>* y, hipStream_t s,
                                const Batch& z = Batch());
 // out = unit vectors: out[j*n + i] = (i == j)
 hipError_t launch_identity(c128* out, int n, hipStream_t s);

@@ -602,7 +602,7 @@ static const cx<T>* mg_cycle(Ctx& c, const Act& a, DefLevel& D, int q, const cx<
   cx<T>* y = (cx<T>*)m.y;
   if (q == (int)H.lv.size() - 1) {
     if (H.dense) {
-      HM_CHECK(launch_dense_matvec<T>((const cx<T>*)H.inv, (int)m.N, b, x, p->s, z));
+      HM_CHECK(launch_dense_matvec<T>((const c128*)H.inv, (int)m.N, b, x, p->s, z));
       return x;
     }
     gmres_cgs<T>(c, a, op, k, H.gm, H.maxit, p->cfg.tol_cslp, K_MGC, b, x);
@@ -953,7 +953,8 @@ static bool validate(const hm_config* c, std::string* why) {
   if (!(c->h > 0) || !std::isfinite(c->h)) return bad("h must be positive");
   if (c->bc != HM_BC_SOMMERFELD && c->bc != HM_BC_DIRICHLET) return bad("unknown boundary condition");
   if (!std::isfinite(c->beta1) || !std::isfinite(c->beta2)) return bad("beta not finite");
-  if (c->precision != HM_FP64 && c->precision != HM_MIXED_FP32) return bad("precision");
+  if (c->precision != HM_FP64 && c->precision != HM_MIXED_FP32 && c->precision != HM_MIXED_FP32_ALL)
+    return bad("precision");
   if (c->outer_restart < 1 || c->outer_maxit < 1 || c->level2_maxit < 1) return bad("step caps");
   if (c->mg_nu_pre < 1 || c->mg_nu_post < 0) return bad("smoothing steps");
   if (!(c->tol_outer > 0) || !(c->tol_level2 > 0) || !(c->tol_cslp > 0) || !(c->maxit_coef > 0))
@@ -973,7 +974,7 @@ static bool can_coarsen(int nx, int ny) {
 static void plan(hm_problem* p, Carver& cv) {
   const hm_config& c = p->cfg;
   p->L = c.levels;
-  p->mixed = c.precision == HM_MIXED_FP32;
+  p->mixed = c.precision != HM_FP64;
   p->lev.assign(p->L + 2, DefLevel());
   const cd sig_m(c.beta1, c.beta2);
   int mmax = c.outer_restart + 2;
@@ -984,7 +985,9 @@ static void plan(hm_problem* p, Carver& cv) {
     D.l = l; D.nx = nx; D.ny = ny; D.N = (size_t)nx * ny;
     D.hl = c.h * std::ldexp(1.0, l - 1);
     D.sl = std::ldexp(1.0, 2 * (l - 1));
-    D.dbl = (l >= 3) || !p->mixed;
+    // mixed: levels 1-2 in FP32, the coarsest-level solve (levels >= 3) in FP64;
+    // HM_MIXED_FP32_ALL: every preconditioner level in FP32
+    D.dbl = !p->mixed || (l >= 3 && c.precision == HM_MIXED_FP32);
     const size_t es = esz(D.dbl);
     D.k64 = cv.take<double>(D.N);
     if (!D.dbl) D.k32 = cv.take<float>(D.N);
@@ -1046,7 +1049,7 @@ static void plan(hm_problem* p, Carver& cv) {
       MGLevel& last = H.lv.back();
       H.dense = last.N <= (size_t)kDenseMax;
       if (H.dense) {
-        H.inv = cv.take<char>(last.N * last.N * es);
+        H.inv = cv.take<c128>(last.N * last.N);      // FP64 in every precision
         H.tmpA = cv.take<c128>(last.N * last.N);
         H.tmpB = cv.take<c128>(last.N * last.N);
       } else {
@@ -1195,17 +1198,10 @@ static void initialize(hm_problem* p, const double* k_dev) {
           A[(size_t)i * n + j] = cd(v.re, v.im);
         }
       invert_dense(A, n);
-      if (D.dbl) {
-        std::vector<c128> up((size_t)n * n);
-        for (size_t i = 0; i < up.size(); ++i) up[i] = mk(A[i].real(), A[i].imag());
-        HM_CHECK(hipMemcpyAsync(H.inv, up.data(), sizeof(c128) * up.size(), hipMemcpyHostToDevice, p->s));
-        HM_CHECK(hipStreamSynchronize(p->s));
-      } else {
-        std::vector<c64> up((size_t)n * n);
-        for (size_t i = 0; i < up.size(); ++i) up[i] = mk((float)A[i].real(), (float)A[i].imag());
-        HM_CHECK(hipMemcpyAsync(H.inv, up.data(), sizeof(c64) * up.size(), hipMemcpyHostToDevice, p->s));
-        HM_CHECK(hipStreamSynchronize(p->s));
-      }
+      std::vector<c128> up((size_t)n * n);
+      for (size_t i = 0; i < up.size(); ++i) up[i] = mk(A[i].real(), A[i].imag());
+      HM_CHECK(hipMemcpyAsync(H.inv, up.data(), sizeof(c128) * up.size(), hipMemcpyHostToDevice, p->s));
+      HM_CHECK(hipStreamSynchronize(p->s));
     }
   }
   HM_CHECK(hipStreamSynchronize(p->s));

@@ -66,6 +66,11 @@ def test_workspace_grows_with_grid_and_mixed_is_smaller():
     f64 = hm.workspace_bytes(hm.default_config(601, 1001, 1.0))
     mix = hm.workspace_bytes(hm.default_config(601, 1001, 1.0, precision=hm.HM_MIXED_FP32))
     assert mix < f64
+    # every preconditioner level in FP32: the level-3 Krylov basis halves as well
+    allf = hm.workspace_bytes(hm.default_config(601, 1001, 1.0, precision=hm.HM_MIXED_FP32_ALL))
+    assert allf < mix
+    with pytest.raises(hm.HelmDeflError):
+        hm.workspace_bytes(hm.default_config(601, 1001, 1.0, precision=3))
 
 
 def test_variant_fields_size_the_coarse_workspaces():

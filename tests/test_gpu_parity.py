@@ -228,6 +228,28 @@ def test_solve_mixed_config0():
     assert err <= 1e-5
 
 
+def test_solve_all_fp32_levels_config0_and_wedge():
+    """Every preconditioner level in FP32 (the coarsest problem included): the FP64
+    outer FGMRES still meets 1e-6 against the oracle's matrix, the solution is
+    within 1e-5 of the oracle's, and the outer count stays within one step."""
+    p = workloads.config(0)
+    o, u, info, u_ref, info_ref, err = _solve_pair("config0", p.nx, p.ny, p.h, p.k, p.sources[0],
+                                                   hm.HM_MIXED_FP32_ALL)
+    b = p.rhs()
+    assert info["status"] == hm.HM_OK
+    assert np.linalg.norm(b - o.levels[1].A @ u) <= 1e-6 * np.linalg.norm(b)
+    assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+    assert err <= 1e-5
+    nx, ny, h = 121, 201, 5.0                   # wedge medium at a fifth of the resolution
+    k = 2 * np.pi * 8.0 / workloads.wedge_velocity(nx, ny, h)
+    o, u, info, u_ref, info_ref, err = _solve_pair("wedge", nx, ny, h, k, (60, 1),
+                                                   hm.HM_MIXED_FP32_ALL)
+    b = workloads.point_source(nx, ny, h, 60, 1)
+    assert np.linalg.norm(b - o.levels[1].A @ u) <= 1e-6 * np.linalg.norm(b)
+    assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+    assert err <= 1e-5
+
+
 def test_solve_heterogeneous_gmres_coarsest_multigrid():
     # 93 x 93: the multigrid hierarchies end on 24 x 24 = 576 > 512 nodes, so the
     # coarsest multigrid solve is GMRES (nonlinear) on both sides

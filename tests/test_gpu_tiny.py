@@ -2,7 +2,7 @@
 nearly every node is on or next to the boundary: every level operator, the
 deflation transfers and the multigrid components against the oracle's
 matrices, for Sommerfeld and Dirichlet boundaries, FP64 (1e-13 / 1e-14) and
-the mixed build's FP32 levels (2e-6).  These shapes reach the ghost and
+the FP32 levels of the two mixed modes (2e-6).  These shapes reach the ghost and
 zero-padding rules of the wide stencils from every side at once and the
 ragged ends of every tiled launch.
 """
@@ -44,7 +44,8 @@ def test_tiny_grid_components(nx, ny, levels, bc):
     k = np.random.default_rng(nx * 31 + ny).uniform(2.0, 6.0, nx * ny)
     o = MADP(nx, ny, h, k, levels=levels, bc=op.DIRICHLET if bc else op.SOMMERFELD)
     probs = [hm.create_problem(hm.default_config(nx, ny, h, levels=levels, bc=bc, precision=prec),
-                               gpu(k)) for prec in (hm.HM_FP64, hm.HM_MIXED_FP32)]
+                               gpu(k))
+             for prec in (hm.HM_FP64, hm.HM_MIXED_FP32, hm.HM_MIXED_FP32_ALL)]
     try:
         for l in range(1, levels + 1):
             lev = o.levels[l]
@@ -53,6 +54,7 @@ def test_tiny_grid_components(nx, ny, levels, bc):
                 assert relerr(host(hm.apply_operator(probs[0], l, which, gpu(x))), M @ x) <= 1e-13
                 tol = 2e-6 if l <= 2 else 1e-13
                 assert relerr(host(hm.apply_operator(probs[1], l, which, gpu(x))), M @ x) <= tol
+                assert relerr(host(hm.apply_operator(probs[2], l, which, gpu(x))), M @ x) <= 2e-6
             if l < levels:
                 Z = lev.Z
                 xf, xc = rand_c(Z.shape[0], 11 * l), rand_c(Z.shape[1], 13 * l)
