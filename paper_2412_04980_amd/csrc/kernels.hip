@@ -812,8 +812,8 @@ inline size_t chunk_len(size_t n, int nchunks) { return (n + nchunks - 1) / nchu
 
 constexpr int G = 4;   // dot products per block in the multi-dot
 
-// Streaming load of a basis element that is not re-read within the same pass
-// (non-temporal hint).
+// Streaming load of a basis element with the non-temporal hint (the caches
+// need not keep it).
 template <typename T>
 __device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
   typedef T v2 __attribute__((ext_vector_type(2)));
@@ -824,12 +824,15 @@ __device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
 // Partial dots of w with V_{i0}..V_{i0+G-1} over one chunk of the vector
 // (block = (chunk, group)); partials[i * nchunks + chunk].  Few accumulators
 // per thread keep occupancy high; the re-reads of w by the groups of a chunk
-// are served by the caches.
-template <typename T>
+// are served by the caches.  STREAM: the basis is loaded with the
+// non-temporal hint (bases much larger than the 256 MB Infinity Cache);
+// otherwise with plain loads, so that the update pass that follows and the
+// next step find it in the cache.
+template <typename T, bool STREAM>
 __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, size_t ldv, int m,
                                                  const cx<T>* __restrict__ w, size_t n, size_t clen,
                                                  c128* __restrict__ partials, int nchunks,
-                                                 int reverse, Batch z) {
+                                                 Batch z) {
   __shared__ double sh[NT / 64][2 * G];
   HM_MEMBER(V); HM_MEMBER(w); HM_MEMBER(partials);
   // XCD-aware block order: workgroups are dispatched round-robin over the 8
@@ -838,8 +841,7 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
   // and from that L2 for the other groups.  nchunks is a multiple of 8.
   const int ngroups = (m + G - 1) / G;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
-  const int c = (local / ngroups) * 8 + xcd;
-  const int chunk = reverse ? nchunks - 1 - c : c;
+  const int chunk = (local / ngroups) * 8 + xcd;
   const int i0 = (local % ngroups) * G;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
@@ -852,7 +854,8 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (i0 + g < m) {
-        const cx<T> v = load_stream(V + (size_t)(i0 + g) * ldv + i);
+        const size_t q = (size_t)(i0 + g) * ldv + i;
+        const cx<T> v = STREAM ? load_stream(V + q) : V[q];
         re[g] += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
         im[g] += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
       }
@@ -940,11 +943,10 @@ template <typename T>
 __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, const cx<T>* __restrict__ V,
                                                         size_t ldv, int m, const c128* __restrict__ h,
                                                         size_t n, size_t clen,
-                                                        c128* __restrict__ partials, int reverse,
-                                                        Batch z) {
+                                                        c128* __restrict__ partials, Batch z) {
   __shared__ double sh[2 * NT / 64];
   HM_MEMBER(w); HM_MEMBER(V); HM_MEMBER(h); HM_MEMBER(partials);
-  const int chunk = reverse ? (int)gridDim.x - 1 - (int)blockIdx.x : (int)blockIdx.x;
+  const int chunk = (int)blockIdx.x;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   double acc = 0;
@@ -1311,12 +1313,17 @@ static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
 
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
-                                   RedBuf rb, int reverse, hipStream_t s, const Batch& z) {
+                                   RedBuf rb, hipStream_t s, const Batch& z) {
   if (m <= 0) return hipSuccess;
   const int nch = multidot_chunks(n, m, rb);
   const size_t clen = multidot_chunk_len(n, m);
-  k_multidot<T><<<zgrid(((m + G - 1) / G) * nch, z), NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials,
-                                                                 nch, reverse, z);
+  // plain loads while the basis and w stay within kCacheBasisBytes: measured
+  // on the coarsest-level solves of 1025^2 .. 4097^2 problems
+  const dim3 g = zgrid(((m + G - 1) / G) * nch, z);
+  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > kCacheBasisBytes)
+    k_multidot<T, true><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, z);
+  else
+    k_multidot<T, false><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, z);
   return hipGetLastError();
 }
 
@@ -1331,7 +1338,7 @@ hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStrea
 template <typename T>
 hipError_t launch_multidot(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n, RedBuf rb,
                            c128* out, hipStream_t s) {
-  const hipError_t e = launch_multidot_partial<T>(V, ldv, m, w, n, rb, 0, s);
+  const hipError_t e = launch_multidot_partial<T>(V, ldv, m, w, n, rb, s);
   if (e != hipSuccess) return e;
   return launch_multidot_final<T>(m, n, rb, out, s);
 }
@@ -1364,12 +1371,11 @@ static int update_chunks(size_t n, const RedBuf& rb) {
 
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
-                                     size_t n, RedBuf rb, int reverse, hipStream_t s,
+                                     size_t n, RedBuf rb, hipStream_t s,
                                      const Batch& z) {
   const int nch = update_chunks(n, rb);
   const size_t clen = update_chunk_len(n);
-  k_cgs_update_norm<T><<<zgrid(nch, z), NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, reverse,
-                                                    z);
+  k_cgs_update_norm<T><<<zgrid(nch, z), NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, z);
   return hipGetLastError();
 }
 
@@ -1382,7 +1388,7 @@ hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t 
 template <typename T>
 hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                   size_t n, RedBuf rb, c128* out, hipStream_t s) {
-  const hipError_t e = launch_cgs_update_partial<T>(w, V, ldv, m, h, n, rb, 0, s);
+  const hipError_t e = launch_cgs_update_partial<T>(w, V, ldv, m, h, n, rb, s);
   if (e != hipSuccess) return e;
   return launch_update_norm_final(n, rb, out, s);
 }
@@ -1432,11 +1438,11 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
   template hipError_t launch_multidot<T>(const cx<T>*, size_t, int, const cx<T>*, size_t, RedBuf,  \
                                          c128*, hipStream_t);                                       \
   template hipError_t launch_multidot_partial<T>(const cx<T>*, size_t, int, const cx<T>*, size_t,  \
-                                                 RedBuf, int, hipStream_t, const Batch&);           \
+                                                 RedBuf, hipStream_t, const Batch&);                \
   template hipError_t launch_multidot_final<T>(int, size_t, RedBuf, c128*, hipStream_t, c128*,     \
                                                const Batch&);                                       \
   template hipError_t launch_cgs_update_partial<T>(cx<T>*, const cx<T>*, size_t, int, const c128*, \
-                                                   size_t, RedBuf, int, hipStream_t, const Batch&); \
+                                                   size_t, RedBuf, hipStream_t, const Batch&);      \
   template hipError_t launch_stencil_scaled<T>(const OpDesc<T>&, const cx<T>*, const T*,            \
                                                const c128*, cx<T>*, cx<T>*, hipStream_t,            \
                                                const Batch&);                                       \

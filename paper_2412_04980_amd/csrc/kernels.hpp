@@ -152,11 +152,13 @@ int reduction_chunks(size_t n);
 
 // out[i] = (V_i, w) = sum conj(V_i) w, i = 0..m-1.  Split in two launches
 // (partial sums over chunks of the vector, then the sums of the partials) so
-// that the streaming kernel can be timed on its own.  `reverse` sweeps the
-// chunks from the end of the vectors (cache reuse between successive passes).
+// that the streaming kernel can be timed on its own.  Bases (plus w) larger than
+// kCacheBasisBytes are loaded with the non-temporal hint, smaller ones with plain
+// loads that leave them in the Infinity Cache for the update pass and the next step.
+constexpr double kCacheBasisBytes = 320.0 * 1048576.0;
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
-                                   RedBuf rb, int reverse, hipStream_t s, const Batch& z = Batch());
+                                   RedBuf rb, hipStream_t s, const Batch& z = Batch());
 // host_out (optional): pinned host memory that receives a copy of out
 template <typename T>
 hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s,
@@ -173,7 +175,7 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
 // Classical Gram-Schmidt update fused with the norm: w -= sum_{i<m} h[i] V_i ; out[0] = ||w||
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
-                                     size_t n, RedBuf rb, int reverse, hipStream_t s,
+                                     size_t n, RedBuf rb, hipStream_t s,
                                      const Batch& z = Batch());
 // sum of the partials written by launch_cgs_update_partial over a vector of length n
 hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,

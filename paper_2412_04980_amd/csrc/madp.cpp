@@ -520,9 +520,8 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
   cx<T>* wb[2] = {w, (cx<T>*)ws.w2};
   // step j of the members st[t], t in who: v_j = src / s_j (s_0 = ||b||,
   // s_j = h_{j,j-1}) written to the basis in the same pass as w = M v_j;
-  // classical Gram-Schmidt with the two sweeps over the basis in opposite
-  // directions (the second starts on the chunks the first read last, which the
-  // caches still hold)
+  // classical Gram-Schmidt: one pass for the dots, one for the update and the
+  // new norm
   auto enqueue_step = [&](int j, const std::vector<int>& who) {
     const Batch z = members(c, members_of(st, who));
     const double nm = (double)who.size();
@@ -534,12 +533,12 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
       return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, wj, p->s, z);
     });
     timed(p, HM_TK_CGS_DOT, nm * (j + 2) * es * N, [&] {
-      return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), 0, p->s, z);
+      return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), p->s, z);
     });
     c128* hcol = p->host_H + (size_t)j * ld;      // pinned mirror of the column
     HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s, hcol, z));
     timed(p, HM_TK_CGS_UPDATE, nm * (j + 3) * es * N, [&] {
-      return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), 1, p->s, z);
+      return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), p->s, z);
     });
     HM_CHECK(launch_update_norm_final(N, rbuf(p, N), col + j + 1, p->s, hcol + j + 1, z));
     HM_CHECK(hipEventRecord(p->col_ev[j & 1], p->s));
