@@ -33,15 +33,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 TIMING_EVERY = 16
 # calibrated hardware byte counts of the dominant kernel (two rocprofv3 --pmc
-# passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size);
-# valid only while the kernel source is unchanged
+# passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
+# taken on one workload (k = 200 on 4097^2, FP64); valid only for that
+# workload and while the kernel source is unchanged
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_gmres_kernels.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2412_04980_amd", "csrc", "kernels.hip")
 
 
-def measured_traffic(kernel_class):
+TRAFFIC_WORKLOAD = "constant_k200_4097"
+
+
+def measured_traffic(kernel_class, workload):
     import hashlib
-    if not os.path.exists(TRAFFIC_RECORD):
+    if workload != TRAFFIC_WORKLOAD or not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = json.load(open(TRAFFIC_RECORD))
     digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
@@ -556,7 +560,7 @@ def main():
         d = classes[dom]
         res["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["GBps"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                           "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, problem.name),
                            "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1),
                            "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1)}
         res["roofline"]["sampled_launches"] = d["launches"]
