@@ -373,7 +373,8 @@ VARIANTS = [("MADP", {}),
             ("fixed m = 1 on every coarse level", {"tol_levels": 1}),
             ("4 levels", {"levels": 4}),
             ("4 levels, W-cycle", {"levels": 4, "coarse_steps": 2}),
-            ("4 levels, tol 0.3 on levels 2-3", {"levels": 4, "tol_levels": 3})]
+            ("4 levels, tol 0.3 on levels 2-3", {"levels": 4, "tol_levels": 3}),
+            ("modified Gram-Schmidt in the Krylov CSLP", {"cslp_orth": 1})]
 
 
 def variants_bench(args):

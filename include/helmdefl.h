@@ -101,8 +101,17 @@ typedef struct {
                             tol_level2 with at most level2_maxit steps: 2 = MADP;
                             1 = every coarse level takes coarse_steps; 3-4 = the
                             tolerance on the third/fourth levels too (Sec. 4.5)   */
-  int reserved[6];       /* must be zero                                            */
+  int cslp_orth;         /* orthogonalisation of the GMRES that approximates the
+                            CSLP inverse on levels >= 3 (and the GMRES coarsest
+                            multigrid solves): HM_ORTH_CLASSICAL (default, two
+                            passes over the basis per step) or HM_ORTH_MODIFIED
+                            (the modified Gram-Schmidt of Algorithm 1, j+1
+                            passes per step); same Krylov space and iterates in
+                            exact arithmetic                                       */
+  int reserved[5];       /* must be zero                                            */
 } hm_config;
+
+enum { HM_ORTH_CLASSICAL = 0, HM_ORTH_MODIFIED = 1 };
 
 typedef struct {
   int outer_iters;             /* outer FGMRES steps                                 */

@@ -33,6 +33,7 @@ HM_OK, HM_NOT_CONVERGED = 0, 1
 HM_ERR_ARG, HM_ERR_NOMEM, HM_ERR_HIP, HM_ERR_STATE = -1, -2, -3, -4
 HM_FP64, HM_MIXED_FP32, HM_MIXED_FP32_ALL = 0, 1, 2
 HM_BC_SOMMERFELD, HM_BC_DIRICHLET = 0, 1
+HM_ORTH_CLASSICAL, HM_ORTH_MODIFIED = 0, 1
 
 HM_OP_A, HM_OP_M, HM_OP_ZT, HM_OP_Z, HM_OP_VCYCLE, HM_OP_CSLP, HM_OP_PRECOND = range(7)
 HM_OP_MG_M, HM_OP_MG_JACOBI, HM_OP_MG_RESTRICT, HM_OP_MG_PROLONG = 7, 8, 9, 10
@@ -64,7 +65,8 @@ class HmConfig(ctypes.Structure):
                 ("outer_maxit", ctypes.c_int), ("level2_maxit", ctypes.c_int),
                 ("mg_nu_pre", ctypes.c_int), ("mg_nu_post", ctypes.c_int),
                 ("precision", ctypes.c_int), ("coarse_steps", ctypes.c_int),
-                ("tol_levels", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+                ("tol_levels", ctypes.c_int), ("cslp_orth", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
     def replace(self, **kw):
         c = HmConfig()

@@ -518,10 +518,12 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
   const double es = (double)sizeof(cx<T>);
   const int tk_op = op.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE;
   cx<T>* wb[2] = {w, (cx<T>*)ws.w2};
+  const bool mgs = p->cfg.cslp_orth == HM_ORTH_MODIFIED;
   // step j of the members st[t], t in who: v_j = src / s_j (s_0 = ||b||,
   // s_j = h_{j,j-1}) written to the basis in the same pass as w = M v_j;
   // classical Gram-Schmidt: one pass for the dots, one for the update and the
-  // new norm
+  // new norm; modified Gram-Schmidt: one fused step per basis vector (subtract
+  // the previous projection, take the next dot), then the norm
   auto enqueue_step = [&](int j, const std::vector<int>& who) {
     const Batch z = members(c, members_of(st, who));
     const double nm = (double)who.size();
@@ -532,10 +534,23 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
     timed(p, tk_op, nm * 3.5 * es * N, [&] {
       return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, wj, p->s, z);
     });
+    c128* hcol = p->host_H + (size_t)j * ld;      // pinned mirror of the column
+    if (mgs) {
+      for (int i = 0; i <= j; ++i)
+        timed(p, HM_TK_MGS, nm * (i > 0 ? 4.0 : 2.0) * es * N, [&] {
+          return launch_mgs_step<T>(wj, i > 0 ? V + (size_t)(i - 1) * N : nullptr, col + i - 1,
+                                    V + (size_t)i * N, N, rbuf(p, N), col + i, p->s, hcol + i, z);
+        });
+      timed(p, HM_TK_MGS, nm * 3.0 * es * N, [&] {
+        return launch_mgs_step<T>(wj, V + (size_t)j * N, col + j, nullptr, N, rbuf(p, N),
+                                  col + j + 1, p->s, hcol + j + 1, z);
+      });
+      HM_CHECK(hipEventRecord(p->col_ev[j & 1], p->s));
+      return;
+    }
     timed(p, HM_TK_CGS_DOT, nm * (j + 2) * es * N, [&] {
       return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), p->s, z);
     });
-    c128* hcol = p->host_H + (size_t)j * ld;      // pinned mirror of the column
     HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s, hcol, z));
     timed(p, HM_TK_CGS_UPDATE, nm * (j + 3) * es * N, [&] {
       return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), p->s, z);
@@ -960,6 +975,8 @@ static bool validate(const hm_config* c, std::string* why) {
     return bad("tolerances");
   if (c->coarse_steps < 1 || c->coarse_steps > 16) return bad("coarse_steps must be in [1, 16]");
   if (c->tol_levels < 1 || c->tol_levels > 6) return bad("tol_levels must be in [1, 6]");
+  if (c->cslp_orth != HM_ORTH_CLASSICAL && c->cslp_orth != HM_ORTH_MODIFIED)
+    return bad("cslp_orth must be HM_ORTH_CLASSICAL or HM_ORTH_MODIFIED");
   for (int r : c->reserved)
     if (r != 0) return bad("reserved fields must be zero");
   return true;

@@ -38,6 +38,7 @@ def test_default_config_is_madp():
     assert (c.tol_outer, c.tol_level2, c.tol_cslp, c.maxit_coef) == (1e-6, 0.3, 0.1, 6.0)
     assert (c.outer_restart, c.outer_maxit, c.level2_maxit) == (30, 300, 100)
     assert (c.mg_nu_pre, c.mg_nu_post, c.precision) == (1, 1, hm.HM_FP64)
+    assert c.cslp_orth == hm.HM_ORTH_CLASSICAL
 
 
 def test_workspace_bytes_validation():
@@ -46,7 +47,7 @@ def test_workspace_bytes_validation():
     for bad in (dict(nx=130), dict(levels=1), dict(levels=7), dict(h=-1.0),
                 dict(precision=5), dict(outer_restart=0), dict(tol_outer=0.0), dict(bc=2),
                 dict(coarse_steps=0), dict(coarse_steps=17), dict(tol_levels=0),
-                dict(tol_levels=7)):
+                dict(tol_levels=7), dict(cslp_orth=2), dict(cslp_orth=-1)):
         c = hm.default_config(129, 129, 1 / 128)
         for key, val in bad.items():
             setattr(c, key, val)

@@ -140,6 +140,41 @@ def test_coarsest_cslp_gmres(small):
     assert relerr(got, ref) <= 1e-11
 
 
+def test_modified_gram_schmidt_option(small):
+    """HM_ORTH_MODIFIED runs the Krylov CSLP with the oracle's modified
+    Gram-Schmidt: the same counts and 1e-12 on the coarsest solve, replayed
+    preconditioner applications at 1e-11, and a solve that meets the gates."""
+    nx, ny, h, k, o, p64, p32 = small
+    pm = make(nx, ny, h, k, cslp_orth=hm.HM_ORTH_MODIFIED)
+    try:
+        lev = o.levels[3]
+        x = rand_c(lev.N, 71)
+        o.log = CountLog("record")
+        ref = o.cslp(3, x)
+        hm.reset_counts(pm)
+        got = host(hm.apply_operator(pm, 3, hm.HM_OP_CSLP, gpu(x)))
+        assert hm.get_counts(pm, hm.KIND_CSLP) == o.log.data["cslp_l3"]
+        assert relerr(got, ref) <= 1e-12
+        v = rand_c(nx * ny, 83)
+        o.log = CountLog("record")
+        ref = o.apply(v)
+        _replay_all(pm, o.log)
+        try:
+            got = host(hm.precond_apply(pm, gpu(v)))
+        finally:
+            _replay_off(pm)
+        assert relerr(got, ref) <= 1e-11
+        b = workloads.point_source(nx, ny, h, 16, 20)
+        u_ref, info_ref = o.solve(b)
+        u, info = hm.fgmres_solve(pm, gpu(b))
+        u = host(u)
+        assert info["rel_res_true"] <= 1e-6
+        assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+        assert np.linalg.norm(u - u_ref) <= 1e-5 * np.linalg.norm(u_ref)
+    finally:
+        pm.close()
+
+
 def _replay_all(prob, log):
     for kind, key in ((hm.KIND_LEVEL2, "level2"), (hm.KIND_CSLP, "cslp_l3"),
                       (hm.KIND_MG_COARSE, "mg_coarse"), (hm.KIND_OUTER, "outer")):
