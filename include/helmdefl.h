@@ -138,8 +138,11 @@ size_t hm_workspace_bytes(const hm_config* cfg);
  *   k_dev: device, nx*ny doubles, the nodal wavenumber k = 2 pi f / c >= 0
  *          (Sec. 2, eq. wavenum); read during the call only.
  *   workspace: device, >= hm_workspace_bytes(cfg) bytes, 256-byte aligned.
- * Errors: HM_ERR_ARG for invalid cfg or pointers or a non-finite/negative k
- * (checked on the device), HM_ERR_NOMEM for a short workspace.
+ * Errors: HM_ERR_ARG for invalid cfg or pointers, for a non-finite or negative
+ * k (checked on the device), or for k = 0 at every node with Sommerfeld
+ * boundaries (the operator is then the Neumann Laplacian, which is singular;
+ * with Dirichlet boundaries k = 0 is the Poisson problem and is accepted);
+ * HM_ERR_NOMEM for a short workspace.
  * Synchronises `stream`. */
 hm_status hm_create_problem(const hm_config* cfg, const double* k_dev, void* workspace,
                             size_t workspace_bytes, void* stream, hm_problem** out);

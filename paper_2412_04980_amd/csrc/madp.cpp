@@ -1182,6 +1182,10 @@ static void initialize(hm_problem* p, const double* k_dev) {
     HM_CHECK(launch_max_real(D.k64, N, rbuf(p, N), p->scal, p->s));
     d2h(p, p->scal, 1);
     D.kmax = p->host[0].re;
+    // k = 0 everywhere with Sommerfeld ghosts leaves the Neumann Laplacian,
+    // whose constants span its null space: no solution to approximate
+    if (l == 1 && D.kmax == 0.0 && p->cfg.bc == HM_BC_SOMMERFELD)
+      throw ArgError("wavenumber field is zero everywhere: the Sommerfeld problem is singular");
     if (!D.has_mg) continue;
     MGHier& H = D.mg;
     for (size_t q = 0; q < H.lv.size(); ++q) {

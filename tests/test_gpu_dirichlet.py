@@ -167,6 +167,27 @@ def test_precond_apply_replay(small):
     assert relerr(got, ref) <= 1e-11
 
 
+@pytest.mark.parametrize("precision", [hm.HM_FP64, hm.HM_MIXED_FP32_ALL])
+def test_poisson_k_zero_matches_oracle(precision):
+    """The degenerate case k = 0: the Poisson problem with Dirichlet boundaries,
+    where the CSLP is the operator itself.  Solve against the oracle."""
+    n, h = 65, 1.0 / 64
+    k = np.zeros(n * n)
+    b = workloads.point_source(n, n, h, 20, 41)
+    o = MADP(n, n, h, k, levels=3, bc=D)
+    u_ref, info_ref = o.solve(b)
+    p = make(n, n, h, k, precision=precision)
+    try:
+        u, info = hm.fgmres_solve(p, gpu(b))
+    finally:
+        p.close()
+    u = host(u)
+    assert info["status"] == hm.HM_OK
+    assert np.linalg.norm(b - o.levels[1].A @ u) <= 1e-6 * np.linalg.norm(b)
+    assert np.linalg.norm(u - u_ref) <= 1e-5 * np.linalg.norm(u_ref)
+    assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+
+
 @pytest.mark.parametrize("precision", [hm.HM_FP64, hm.HM_MIXED_FP32])
 def test_solve_matches_oracle(precision):
     """Constant wavenumber, point source at the centre (the Dirichlet model

@@ -338,6 +338,20 @@ def test_rejects_bad_wavenumber():
         make(nx, ny, 1 / 16, k)
 
 
+def test_rejects_zero_wavenumber_with_sommerfeld():
+    """k = 0 everywhere with Sommerfeld ghosts is the Neumann Laplacian, whose
+    constants span its null space: creation fails with an argument error (with
+    Dirichlet boundaries the same field is the Poisson problem and is solved,
+    see the Dirichlet tests)."""
+    nx = ny = 17
+    with pytest.raises(hm.HelmDeflError) as e:
+        make(nx, ny, 1 / 16, np.zeros(nx * ny))
+    assert e.value.status == hm.HM_ERR_ARG and "singular" in str(e.value)
+    k = np.zeros(nx * ny)
+    k[40] = 1e-3                      # one nonzero node is enough
+    make(nx, ny, 1 / 16, k).close()
+
+
 def test_rejects_short_workspace():
     nx = ny = 17
     cfg = hm.default_config(nx, ny, 1 / 16)

@@ -118,8 +118,10 @@ def test_masked_transfers_keep_vectors_boundary_free():
     assert np.allclose((Z.T @ vf)[inner], (Zs.T @ vf)[inner])
 
 
-@pytest.mark.parametrize("kval,n", [(6.0, 33), (12.0, 41)])
+@pytest.mark.parametrize("kval,n", [(0.0, 33), (6.0, 33), (12.0, 41)])
 def test_madp_dirichlet_solve_is_the_textbook_solution(kval, n):
+    """kval = 0 is the degenerate case of the method: the Poisson problem, with
+    the CSLP equal to the operator itself."""
     h = 1.0 / (n - 1)
     rng = np.random.default_rng(3)
     k = kval * rng.uniform(0.9, 1.1, n * n)
