@@ -338,6 +338,41 @@ def test_rejects_bad_wavenumber():
         make(nx, ny, 1 / 16, k)
 
 
+@pytest.mark.parametrize("restart,maxit", [(3, 300), (30, 3), (4, 6)])
+def test_restarts_and_step_cap_match_the_oracle(restart, maxit):
+    """Outer restarts and the outer step cap: restart 3 converges through
+    several restart cycles; a cap of 3 (or 6 steps in restarts of 4) stops
+    short of the tolerance with HM_NOT_CONVERGED and the solution written.  The
+    solution agrees with the oracle's run of the same settings (1e-5); a capped
+    run takes exactly the oracle's steps and ends at its residual, a converged
+    one within one outer step of it.  The reported true residual is that of
+    the returned solution."""
+    p = workloads.config(0)
+    b = p.rhs()
+    o = MADP(p.nx, p.ny, p.h, p.k, levels=3)
+    u_ref, info_ref = o.solve(b, restart=restart, maxit=maxit)
+    prob = make(p.nx, p.ny, p.h, p.k, outer_restart=restart, outer_maxit=maxit)
+    try:
+        u, info = hm.fgmres_solve(prob, gpu(b))
+    finally:
+        prob.close()
+    u = host(u)
+    A = o.levels[1].A
+    rel = np.linalg.norm(b - A @ u) / np.linalg.norm(b)
+    rel_ref = np.linalg.norm(b - A @ u_ref) / np.linalg.norm(b)
+    converged = rel_ref <= 1e-6
+    assert info["status"] == (hm.HM_OK if converged else hm.HM_NOT_CONVERGED)
+    assert abs(info["rel_res_true"] - rel) <= 1e-9 * max(rel, 1e-12)
+    assert np.linalg.norm(u - u_ref) <= 1e-5 * np.linalg.norm(u_ref)
+    if converged:
+        assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
+        assert rel <= 1e-6
+    else:
+        # the same iterate after the same number of steps
+        assert info["outer_iters"] == info_ref["outer_iters"] == maxit
+        assert abs(rel - rel_ref) <= 1e-6 * rel_ref and rel > 1e-6
+
+
 def test_rejects_zero_wavenumber_with_sommerfeld():
     """k = 0 everywhere with Sommerfeld ghosts is the Neumann Laplacian, whose
     constants span its null space: creation fails with an argument error (with
