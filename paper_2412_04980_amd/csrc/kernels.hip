@@ -824,15 +824,16 @@ __device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
 // Partial dots of w with V_{i0}..V_{i0+G-1} over one chunk of the vector
 // (block = (chunk, group)); partials[i * nchunks + chunk].  Few accumulators
 // per thread keep occupancy high; the re-reads of w by the groups of a chunk
-// are served by the caches.  STREAM: the basis is loaded with the
-// non-temporal hint (bases much larger than the 256 MB Infinity Cache);
-// otherwise with plain loads, so that the update pass that follows and the
-// next step find it in the cache.
+// are served by the caches.  STREAM (bases larger than the Infinity Cache):
+// the vectors older than the `recent` most recent ones are loaded with the
+// non-temporal hint, the recent ones with plain loads; otherwise every vector
+// with plain loads, so that the update pass and the next step find them in
+// the cache.
 template <typename T, bool STREAM>
 __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, size_t ldv, int m,
                                                  const cx<T>* __restrict__ w, size_t n, size_t clen,
                                                  c128* __restrict__ partials, int nchunks,
-                                                 Batch z) {
+                                                 int recent, Batch z) {
   __shared__ double sh[NT / 64][2 * G];
   HM_MEMBER(V); HM_MEMBER(w); HM_MEMBER(partials);
   // XCD-aware block order: workgroups are dispatched round-robin over the 8
@@ -855,7 +856,7 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
     for (int g = 0; g < G; ++g) {
       if (i0 + g < m) {
         const size_t q = (size_t)(i0 + g) * ldv + i;
-        const cx<T> v = STREAM ? load_stream(V + q) : V[q];
+        const cx<T> v = (STREAM && i0 + g < m - recent) ? load_stream(V + q) : V[q];
         re[g] += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
         im[g] += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
       }
@@ -939,11 +940,12 @@ __global__ void __launch_bounds__(NT) k_mgs_step(cx<T>* __restrict__ w, const cx
 
 // w -= sum_j h_j V_j with the partial ||w||^2 of one chunk; every thread
 // updates two elements (i, i + NT) per pass for more loads in flight.
-template <typename T>
+template <typename T, bool STREAM>
 __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, const cx<T>* __restrict__ V,
                                                         size_t ldv, int m, const c128* __restrict__ h,
                                                         size_t n, size_t clen,
-                                                        c128* __restrict__ partials, Batch z) {
+                                                        c128* __restrict__ partials, int recent,
+                                                        Batch z) {
   __shared__ double sh[2 * NT / 64];
   HM_MEMBER(w); HM_MEMBER(V); HM_MEMBER(h); HM_MEMBER(partials);
   const int chunk = (int)blockIdx.x;
@@ -959,11 +961,12 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
 #pragma unroll 8
     for (int j = 0; j < m; ++j) {
       const c128 c = h[j];
-      const cx<T> v0 = V[(size_t)j * ldv + i];
+      const bool old = STREAM && j < m - recent;   // see k_multidot
+      const cx<T> v0 = old ? load_stream(V + (size_t)j * ldv + i) : V[(size_t)j * ldv + i];
       re0 += c.re * (double)v0.re - c.im * (double)v0.im;
       im0 += c.re * (double)v0.im + c.im * (double)v0.re;
       if (two) {
-        const cx<T> v1 = V[(size_t)j * ldv + i2];
+        const cx<T> v1 = old ? load_stream(V + (size_t)j * ldv + i2) : V[(size_t)j * ldv + i2];
         re1 += c.re * (double)v1.re - c.im * (double)v1.im;
         im1 += c.re * (double)v1.im + c.im * (double)v1.re;
       }
@@ -1317,13 +1320,14 @@ hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T
   if (m <= 0) return hipSuccess;
   const int nch = multidot_chunks(n, m, rb);
   const size_t clen = multidot_chunk_len(n, m);
-  // plain loads while the basis and w stay within kCacheBasisBytes: measured
-  // on the coarsest-level solves of 1025^2 .. 4097^2 problems
+  // load policy (kCacheBasisBytes, kCacheRecentBytes): measured on the
+  // coarsest-level solves of 1025^2 .. 4097^2 and 4597 x 1453 problems
   const dim3 g = zgrid(((m + G - 1) / G) * nch, z);
+  const int recent = (int)(kCacheRecentBytes / ((double)n * sizeof(cx<T>)));
   if ((double)(m + 1) * (double)n * sizeof(cx<T>) > kCacheBasisBytes)
-    k_multidot<T, true><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, z);
+    k_multidot<T, true><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, recent, z);
   else
-    k_multidot<T, false><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, z);
+    k_multidot<T, false><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, recent, z);
   return hipGetLastError();
 }
 
@@ -1375,7 +1379,12 @@ hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m
                                      const Batch& z) {
   const int nch = update_chunks(n, rb);
   const size_t clen = update_chunk_len(n);
-  k_cgs_update_norm<T><<<zgrid(nch, z), NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, z);
+  const int recent = (int)(kCacheRecentBytes / ((double)n * sizeof(cx<T>)));
+  const dim3 g = zgrid(nch, z);
+  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > kCacheBasisBytes)
+    k_cgs_update_norm<T, true><<<g, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, recent, z);
+  else
+    k_cgs_update_norm<T, false><<<g, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, recent, z);
   return hipGetLastError();
 }
 

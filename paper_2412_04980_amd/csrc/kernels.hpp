@@ -152,10 +152,13 @@ int reduction_chunks(size_t n);
 
 // out[i] = (V_i, w) = sum conj(V_i) w, i = 0..m-1.  Split in two launches
 // (partial sums over chunks of the vector, then the sums of the partials) so
-// that the streaming kernel can be timed on its own.  Bases (plus w) larger than
-// kCacheBasisBytes are loaded with the non-temporal hint, smaller ones with plain
-// loads that leave them in the Infinity Cache for the update pass and the next step.
-constexpr double kCacheBasisBytes = 320.0 * 1048576.0;
+// that the streaming kernel can be timed on its own.  A basis (plus w) up to
+// kCacheBasisBytes is read with plain loads in both Gram-Schmidt passes, which
+// leave it in the 256 MB Infinity Cache for the other pass and the next step.  A
+// larger one keeps only its most recent vectors, kCacheRecentBytes of them,
+// cache-resident that way; the older ones are read with the non-temporal hint.
+constexpr double kCacheBasisBytes = 256.0 * 1048576.0;
+constexpr double kCacheRecentBytes = 200.0 * 1048576.0;
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
                                    RedBuf rb, hipStream_t s, const Batch& z = Batch());
