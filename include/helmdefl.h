@@ -8,8 +8,9 @@
  * uniform grid of nx*ny nodes INCLUDING the boundary nodes, spacing h, 5-point
  * second-order finite differences, first-order Sommerfeld radiation condition on
  * all four sides imposed through the ghost point u_ghost = u_mirror + 2 i h k u_b
- * (eq. ghost_sommerfeld), or a homogeneous Dirichlet condition (hm_bc).  The outer solver is FGMRES from a zero initial guess
- * stopping at ||b - A u||_2 / ||b||_2 <= tol_outer (Sec. 4); the preconditioner
+ * (eq. ghost_sommerfeld), or a homogeneous Dirichlet condition (hm_bc).  The
+ * outer solver is FGMRES from a zero initial guess stopping at
+ * ||b - A u||_2 / ||b||_2 <= tol_outer (Sec. 4); the preconditioner
  * is MADP (Sec. 4.4): Algorithm 1 applied recursively over `levels` levels with
  * the CSLP  M = -Lap - (beta1 + i beta2) k^2  (eq. CSLP def) approximated by one
  * multigrid V-cycle on levels 1-2 and by GMRES on coarser levels, the
