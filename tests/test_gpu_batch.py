@@ -10,7 +10,8 @@ for bit, those of the same problem solved on its own with hm_fgmres_solve
     (GMRES inside the V-cycle, eager instead of a captured graph);
   * members that stop after different numbers of outer steps, a zero
     right-hand side, the largest batch (16 members) and a batch of one;
-  * a second solve on the same batch (graphs reused per member set).
+  * a second solve on the same batch (graphs reused per member set);
+  * per-member replayed step counts and kernel timing inside a batch.
 """
 import numpy as np
 import pytest
@@ -134,3 +135,46 @@ def test_batch_argument_errors():
     bad = gpu(np.full(n * n, -1.0))
     with pytest.raises(hm.HelmDeflError):
         hm.create_batch(cfg, [gpu(ks[0]), bad])
+
+
+def test_batch_with_replayed_counts_and_timing():
+    """Per-member replayed step counts (a member's fixed-count parity mode) and
+    kernel timing on member 0 work inside a batch: every member equals its
+    replayed solve alone bit for bit, and the timed classes record launches
+    whose bytes count every member of the launch."""
+    n = 65
+    h, ks = media(n, (1.0, 1.3), seed=13)
+    cfg = hm.default_config(n, n, h)
+    bs = sources(n, h, 2, seed=14)
+    # record each member's counts alone, then replay them in the batch
+    recorded = []
+    for k, b in zip(ks, bs):
+        p = hm.create_problem(cfg, gpu(k))
+        try:
+            hm.fgmres_solve(p, gpu(b))
+            recorded.append([hm.get_counts(p, kind) for kind in range(4)])
+        finally:
+            p.close()
+    bt = hm.create_batch(cfg, [gpu(k) for k in ks])
+    try:
+        for m, counts in zip(bt.members, recorded):
+            for kind in range(4):
+                hm.set_replay(m, kind, counts[kind])
+        hm.set_timing(bt.members[0], (1 << 5) - 1, 1)
+        us, infos = hm.batch_solve(bt, [gpu(b) for b in bs])
+        timing = hm.get_timing(bt.members[0])
+    finally:
+        bt.close()
+    for i, (k, b) in enumerate(zip(ks, bs)):
+        p = hm.create_problem(cfg, gpu(k))
+        try:
+            for kind in range(4):
+                hm.set_replay(p, kind, recorded[i][kind])
+            u, info = hm.fgmres_solve(p, gpu(b))
+        finally:
+            p.close()
+        assert torch.equal(us[i], u)
+        assert infos[i]["outer_iters"] == info["outer_iters"]
+    ms, by, launches = timing["cgs_dot"]
+    assert launches > 0 and ms > 0 and by > 0
+    assert sum(t[2] for t in timing.values()) > launches
