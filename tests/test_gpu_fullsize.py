@@ -4,7 +4,8 @@
     levels 1 and 3 and the level-1 deflation restriction compared with the
     oracle's assembled matrices on every row; one FP64 and one mixed solve
     checked through the property that holds at any size, the true relative
-    residual computed by the oracle's own matrix (<= 1e-6);
+    residual computed by the oracle's own matrix (<= 1e-6); a two-member lockstep
+    batch bitwise against the solves alone (member offsets beyond 32 bits);
   * wedge stand-in, 601 x 1001, f = 40 Hz: full oracle solve against the GPU
     FP64 solve (outer steps +-1, solution error <= 1e-5) and the mixed solve
     (residual <= 1e-6, error vs the FP64 oracle <= 1e-5);
@@ -110,6 +111,41 @@ def test_config1_solve_true_residual(cfg1, precision):
     assert true_residual(p, host(u)) <= 1e-6
     # the paper's MADP runs take 10-19 outer steps; a trend check
     assert 5 <= info["outer_iters"] <= 30
+
+
+def test_config1_two_member_batch_bitwise(cfg1):
+    """The benchmarked workload as a lockstep batch of two right-hand sides
+    (members 36.7 GB apart in one workspace, so the member offsets of every
+    kernel exceed 32 bits): each member's solution is bitwise that of its
+    solve alone."""
+    p = cfg1
+    n = p.nx * p.ny
+    b0 = p.rhs()
+    b1 = workloads.point_source(p.nx, p.ny, p.h, 1000, 3000)
+    cfg = hm.default_config(p.nx, p.ny, p.h)
+    kd = gpu(p.k)
+    alone = []
+    prob = hm.create_problem(cfg, kd)
+    try:
+        for b in (b0, b1):
+            u, info = hm.fgmres_solve(prob, gpu(b))
+            alone.append((u.cpu(), info["outer_iters"]))
+            del u
+    finally:
+        prob.close()
+        torch.cuda.empty_cache()
+    assert hm.batch_workspace_bytes(cfg, 2) > 2 * 2**32
+    bt = hm.create_batch(cfg, [kd, kd])
+    try:
+        us, infos = hm.batch_solve(bt, [gpu(b0), gpu(b1)])
+        for i in range(2):
+            assert torch.equal(us[i].cpu(), alone[i][0]), "member %d differs" % i
+            assert infos[i]["outer_iters"] == alone[i][1]
+            assert infos[i]["rel_res_true"] <= 1e-6
+        assert us[0].numel() == n
+    finally:
+        bt.close()
+        torch.cuda.empty_cache()
 
 
 def test_config2_wedge_solves_vs_oracle():
