@@ -671,7 +671,14 @@ static void fgmres_level(Ctx& c, const Act& a0, int lv, const cx<T>* b, cx<T>* x
     cx<T>* Vj = V + (size_t)j * N;
     cx<T>* Xj = X + (size_t)j * N;
     if (lv == p->L) {
-      cslp_apply<T>(c, a, lv, Vj, Xj);
+      // with two levels the coarsest one owns a multigrid hierarchy, whose
+      // V-cycle leaves its result in a multigrid buffer: move it into Z_j
+      const cx<T>* r = cslp_apply<T>(c, a, lv, Vj, Xj);
+      if (r != Xj)
+        for (int i : a)
+          HM_CHECK(hipMemcpyAsync((char*)Xj + (long long)i * c.dz,
+                                  (const char*)r + (long long)i * c.dz, sizeof(cx<T>) * N,
+                                  hipMemcpyDeviceToDevice, p->s));
     } else {
       precond<T>(c, a, lv, Vj, Xj);
     }

@@ -8,6 +8,7 @@ for bit, those of the same problem solved on its own with hm_fgmres_solve
   * Dirichlet boundaries with the W-cycle, and the tolerance on three levels;
   * a grid whose multigrid coarsest level is too large for the dense solve
     (GMRES inside the V-cycle, eager instead of a captured graph);
+  * two levels, where the coarsest level's CSLP is a V-cycle;
   * members that stop after different numbers of outer steps, a zero
     right-hand side, the largest batch (16 members) and a batch of one;
   * a second solve on the same batch (graphs reused per member set);
@@ -83,6 +84,7 @@ CASES = {
     "dirichlet_w": (129, (1.0, 1.5), dict(levels=3, bc=hm.HM_BC_DIRICHLET, coarse_steps=2)),
     "tol3_l4": (129, (1.2, 1.0), dict(levels=4, tol_levels=3)),
     "krylov_mg_coarsest": (149, (1.0, 1.3), dict(levels=3)),
+    "two_levels": (65, (1.0, 1.3, 1.1), dict(levels=2)),
 }
 
 
