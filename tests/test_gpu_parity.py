@@ -223,6 +223,30 @@ def test_precond_mixed_close_to_fp64(small):
     assert relerr(got, ref) <= 1e-4
 
 
+def test_two_level_precond_apply():
+    """Two levels: level 2 is the coarsest, its coarse problem takes one FGMRES
+    step and its CSLP is a V-cycle, so no inner solve stops on a tolerance and
+    one application is a fixed map on both sides.  Three applications in a row
+    (the coarsest FGMRES and the V-cycle reuse their buffers) each match the
+    oracle: 1e-11 in FP64 as the replayed three-level preconditioner, 1e-4 in
+    the mixed modes (with two levels both run every level in FP32)."""
+    nx, ny, h = 33, 41, 1.0 / 32
+    k = medium(nx, ny, 11.0, 4)
+    o = MADP(nx, ny, h, k, levels=2)
+    precs = (hm.HM_FP64, hm.HM_MIXED_FP32, hm.HM_MIXED_FP32_ALL)
+    probs = [make(nx, ny, h, k, levels=2, precision=prec) for prec in precs]
+    try:
+        for rep in range(3):
+            v = rand_c(nx * ny, 90 + rep)
+            ref = o.apply(v)
+            for prec, p in zip(precs, probs):
+                got = host(hm.precond_apply(p, gpu(v)))
+                assert relerr(got, ref) <= (1e-11 if prec == hm.HM_FP64 else 1e-4), (rep, prec)
+    finally:
+        for p in probs:
+            p.close()
+
+
 def _solve_pair(prob_name, nx, ny, h, k, src, precision=hm.HM_FP64):
     o = MADP(nx, ny, h, k, levels=3)
     b = workloads.point_source(nx, ny, h, *src)
