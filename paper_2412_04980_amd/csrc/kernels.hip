@@ -821,14 +821,59 @@ __device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
   return mk(t.x, t.y);
 }
 
+// One chunk of the partial dots of w with NG consecutive basis vectors (NG and
+// the load kind fixed at compile time, so that the NG + 1 loads of a row are
+// all in flight together); re/im accumulate over the rows in order.
+template <typename T, int NG, bool NTL>
+__device__ __forceinline__ void dot_rows(const cx<T>* __restrict__ V, size_t ldv,
+                                         const cx<T>* __restrict__ w, size_t lo, size_t hi,
+                                         double* re, double* im) {
+  size_t i = lo + threadIdx.x;
+  for (; i + NT < hi; i += 2 * NT) {
+    const cx<T> wa = w[i], wb = w[i + NT];
+    cx<T> va[NG], vb[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      va[g] = NTL ? load_stream(V + (size_t)g * ldv + i) : V[(size_t)g * ldv + i];
+      vb[g] = NTL ? load_stream(V + (size_t)g * ldv + i + NT) : V[(size_t)g * ldv + i + NT];
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      re[g] += (double)va[g].re * (double)wa.re + (double)va[g].im * (double)wa.im;
+      im[g] += (double)va[g].re * (double)wa.im - (double)va[g].im * (double)wa.re;
+      re[g] += (double)vb[g].re * (double)wb.re + (double)vb[g].im * (double)wb.im;
+      im[g] += (double)vb[g].re * (double)wb.im - (double)vb[g].im * (double)wb.re;
+    }
+  }
+  if (i < hi) {
+    const cx<T> wv = w[i];
+    cx<T> v[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) v[g] = NTL ? load_stream(V + (size_t)g * ldv + i) : V[(size_t)g * ldv + i];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      re[g] += (double)v[g].re * (double)wv.re + (double)v[g].im * (double)wv.im;
+      im[g] += (double)v[g].re * (double)wv.im - (double)v[g].im * (double)wv.re;
+    }
+  }
+}
+
+template <typename T, int NG>
+__device__ __forceinline__ void dot_rows_kind(const cx<T>* __restrict__ V, size_t ldv,
+                                              const cx<T>* __restrict__ w, size_t lo, size_t hi,
+                                              bool ntl, double* re, double* im) {
+  if (ntl) dot_rows<T, NG, true>(V, ldv, w, lo, hi, re, im);
+  else dot_rows<T, NG, false>(V, ldv, w, lo, hi, re, im);
+}
+
 // Partial dots of w with V_{i0}..V_{i0+G-1} over one chunk of the vector
 // (block = (chunk, group)); partials[i * nchunks + chunk].  Few accumulators
 // per thread keep occupancy high; the re-reads of w by the groups of a chunk
 // are served by the caches.  STREAM (bases larger than the Infinity Cache):
-// the vectors older than the `recent` most recent ones are loaded with the
-// non-temporal hint, the recent ones with plain loads; otherwise every vector
-// with plain loads, so that the update pass and the next step find them in
-// the cache.
+// groups whose vectors are all older than the `recent` most recent ones are
+// loaded with the non-temporal hint, the others with plain loads; otherwise
+// every vector with plain loads, so that the update pass and the next step
+// find them in the cache.
 template <typename T, bool STREAM>
 __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, size_t ldv, int m,
                                                  const cx<T>* __restrict__ w, size_t n, size_t clen,
@@ -850,18 +895,14 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
   double re[G], im[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) { re[g] = 0; im[g] = 0; }
-  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
-    const cx<T> wv = w[i];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (i0 + g < m) {
-        const size_t q = (size_t)(i0 + g) * ldv + i;
-        const cx<T> v = (STREAM && i0 + g < m - recent) ? load_stream(V + q) : V[q];
-        re[g] += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
-        im[g] += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
-      }
-    }
-  }
+  const int gm = m - i0 < G ? m - i0 : G;           // vectors of this group
+  const bool ntl = STREAM && i0 + gm <= m - recent;
+  const cx<T>* Vg = V + (size_t)i0 * ldv;
+  static_assert(G == 4, "the group tails below cover G = 4");
+  if (gm == 4) dot_rows_kind<T, 4>(Vg, ldv, w, lo, hi, ntl, re, im);
+  else if (gm == 3) dot_rows_kind<T, 3>(Vg, ldv, w, lo, hi, ntl, re, im);
+  else if (gm == 2) dot_rows_kind<T, 2>(Vg, ldv, w, lo, hi, ntl, re, im);
+  else dot_rows_kind<T, 1>(Vg, ldv, w, lo, hi, ntl, re, im);
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     re[g] = wave_sum(re[g]);
