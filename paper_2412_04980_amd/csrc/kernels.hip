@@ -949,7 +949,23 @@ __global__ void __launch_bounds__(NT) k_final(const c128* __restrict__ partials,
   }
 }
 
-template <typename T>
+// Partial of next^H w (NEXT) or of ||w||^2 for one row.
+template <typename T, bool NEXT>
+__device__ __forceinline__ void mgs_acc(double& re, double& im, const cx<T>& wv, const cx<T>& v) {
+  if (NEXT) {
+    re += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
+    im += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
+  } else {
+    re += (double)wv.re * (double)wv.re + (double)wv.im * (double)wv.im;
+  }
+}
+
+// One modified Gram-Schmidt step fused with the next dot: w -= hprev * prev
+// (PREV), then the chunk's partial of next^H w (NEXT) or of ||w||^2.  Which of
+// prev and next are present is fixed at compile time, and each thread takes
+// two rows per pass, so that the loads of both rows are in flight together;
+// the partial sums its rows in order.
+template <typename T, bool PREV, bool NEXT>
 __global__ void __launch_bounds__(NT) k_mgs_step(cx<T>* __restrict__ w, const cx<T>* __restrict__ prev,
                                                  const c128* __restrict__ hprev,
                                                  const cx<T>* __restrict__ next, size_t n, size_t clen,
@@ -960,20 +976,29 @@ __global__ void __launch_bounds__(NT) k_mgs_step(cx<T>* __restrict__ w, const cx
   const size_t hi = lo + clen < n ? lo + clen : n;
   double re = 0, im = 0;
   cx<T> h = mk(T(0), T(0));
-  if (prev) h = cvt<T>(hprev[0]);
-  for (size_t i = lo + threadIdx.x; i < hi; i += NT) {
-    cx<T> wv = w[i];
-    if (prev) {
-      wv = wv - h * prev[i];
-      w[i] = wv;
+  if (PREV) h = cvt<T>(hprev[0]);
+  const cx<T> zero = mk(T(0), T(0));
+  size_t i = lo + threadIdx.x;
+  for (; i + NT < hi; i += 2 * NT) {
+    cx<T> wa = w[i], wb = w[i + NT];
+    const cx<T> pa = PREV ? prev[i] : zero, pb = PREV ? prev[i + NT] : zero;
+    const cx<T> na = NEXT ? next[i] : zero, nb = NEXT ? next[i + NT] : zero;
+    if (PREV) {
+      wa = wa - h * pa;
+      wb = wb - h * pb;
+      w[i] = wa;
+      w[i + NT] = wb;
     }
-    if (next) {
-      const cx<T> v = next[i];
-      re += (double)v.re * (double)wv.re + (double)v.im * (double)wv.im;
-      im += (double)v.re * (double)wv.im - (double)v.im * (double)wv.re;
-    } else {
-      re += (double)wv.re * (double)wv.re + (double)wv.im * (double)wv.im;
+    mgs_acc<T, NEXT>(re, im, wa, na);
+    mgs_acc<T, NEXT>(re, im, wb, nb);
+  }
+  if (i < hi) {
+    cx<T> wa = w[i];
+    if (PREV) {
+      wa = wa - h * prev[i];
+      w[i] = wa;
     }
+    mgs_acc<T, NEXT>(re, im, wa, NEXT ? next[i] : zero);
   }
   const c128 s = block_sum(re, im, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -1393,7 +1418,15 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
                            size_t n, RedBuf rb, c128* out, hipStream_t s, c128* host_out,
                            const Batch& z) {
   const size_t clen = chunk_len(n, rb.nchunks);
-  k_mgs_step<T><<<zgrid(rb.nchunks, z), NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials, z);
+  const dim3 g = zgrid(rb.nchunks, z);
+  if (prev && next)
+    k_mgs_step<T, true, true><<<g, NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials, z);
+  else if (prev)
+    k_mgs_step<T, true, false><<<g, NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials, z);
+  else if (next)
+    k_mgs_step<T, false, true><<<g, NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials, z);
+  else
+    k_mgs_step<T, false, false><<<g, NT, 0, s>>>(w, prev, hprev, next, n, clen, rb.partials, z);
   k_final<<<zgrid(1, z), NT, 0, s>>>(rb.partials, rb.nchunks, out, next ? 0 : 1, host_out, z);
   return hipGetLastError();
 }
