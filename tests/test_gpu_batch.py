@@ -9,6 +9,8 @@ for bit, those of the same problem solved on its own with hm_fgmres_solve
   * a grid whose multigrid coarsest level is too large for the dense solve
     (GMRES inside the V-cycle, eager instead of a captured graph);
   * two levels, where the coarsest level's CSLP is a V-cycle;
+  * every preconditioner level in FP32 with the modified Gram-Schmidt Krylov
+    CSLP;
   * members that stop after different numbers of outer steps, a zero
     right-hand side, the largest batch (16 members) and a batch of one;
   * a second solve on the same batch (graphs reused per member set);
@@ -85,6 +87,8 @@ CASES = {
     "tol3_l4": (129, (1.2, 1.0), dict(levels=4, tol_levels=3)),
     "krylov_mg_coarsest": (149, (1.0, 1.3), dict(levels=3)),
     "two_levels": (65, (1.0, 1.3, 1.1), dict(levels=2)),
+    "all_fp32_mgs": (129, (1.0, 1.4), dict(levels=3, precision=hm.HM_MIXED_FP32_ALL,
+                                            cslp_orth=hm.HM_ORTH_MODIFIED)),
 }
 
 
