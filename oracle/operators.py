@@ -208,6 +208,12 @@ def wide_stencil(nx, ny, h, level, k, sigma, bc=SOMMERFELD):
         sum_{a,b} ( h^-2 L[b,a] - sigma K[b,a] k^2_{I+(a,b)} ) u_{I+(a,b)}
     with the ghost/zero rule for points outside the grid; boundary rows are
     s_l * five_point at spacing h_l.  bc = "dirichlet": reading R24.
+
+    Parity: interior rows are pinned (rows of the assembled Galerkin triple
+    product, plane-wave consistency).  The values of the boundary band (rows
+    whose taps leave the grid) are parity unpinned: the paper prints none.  Its
+    consistency across the four sides and the two axes is pinned by the grid
+    symmetries (reflections and transposition of medium and vector).
     """
     if bc == DIRICHLET:
         return _wide_dirichlet(nx, ny, h, level, k, sigma)

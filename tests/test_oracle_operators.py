@@ -148,3 +148,40 @@ def test_five_point_rows_match_the_assembled_matrix(bc):
     A = op.five_point(nx, ny, H, k, 1.0 + 0.5j, bc=bc)
     got = op.five_point_rows(nx, ny, H, k, 1.0 + 0.5j, np.arange(nx * ny), x, bc=bc)
     assert np.allclose(got, A @ x, rtol=0, atol=1e-12 * np.abs(A @ x).max())
+
+
+def _flip_x(v, nx, ny):
+    return np.asarray(v).reshape(ny, nx)[:, ::-1].ravel()
+
+
+def _flip_y(v, nx, ny):
+    return np.asarray(v).reshape(ny, nx)[::-1, :].ravel()
+
+
+def _swap_xy(v, nx, ny):
+    return np.asarray(v).reshape(ny, nx).T.ravel()
+
+
+@pytest.mark.parametrize("bc", [op.SOMMERFELD, op.DIRICHLET])
+@pytest.mark.parametrize("level", [1, 2, 3, 4, 5, 6])
+def test_level_operators_commute_with_grid_symmetries(level, bc):
+    """The boundary band of the coarse operators (readings R7, R8, R24) has no
+    printed values, but the discretisation must treat the four sides and the two
+    axes alike: the operator built from a reflected (or transposed) medium,
+    applied to the reflected (transposed) vector, gives the reflected
+    (transposed) result.  A ghost rule slipped on one side, a mirror index off by
+    one, or x and y exchanged in a tap breaks this on the rows next to that side.
+    Oblong grid, random medium and vector; the two sides differ only in the
+    order of each row's sum."""
+    nx, ny, h, sigma = 15, 19, 1.0 / 32, 1.0 + 0.5j
+    rng = np.random.default_rng(40 + level)
+    k = rng.uniform(2.0, 6.0, nx * ny)
+    u = rng.standard_normal(nx * ny) + 1j * rng.standard_normal(nx * ny)
+    Au = op.level_operator(nx, ny, h, level, k, sigma, bc=bc) @ u
+    scale = np.max(np.abs(Au))
+    for flip in (_flip_x, _flip_y):
+        got = op.level_operator(nx, ny, h, level, flip(k, nx, ny), sigma, bc=bc) @ flip(u, nx, ny)
+        assert np.max(np.abs(got - flip(Au, nx, ny))) <= 1e-12 * scale, flip.__name__
+    # transposition maps an nx x ny grid to an ny x nx one
+    got = op.level_operator(ny, nx, h, level, _swap_xy(k, nx, ny), sigma, bc=bc) @ _swap_xy(u, nx, ny)
+    assert np.max(np.abs(got - _swap_xy(Au, nx, ny))) <= 1e-12 * scale
