@@ -201,6 +201,7 @@ def create_problem(cfg, k, stream=None, workspace=None):
     nbytes = workspace_bytes(cfg)
     if workspace is None:
         workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=k.device)
+    _same_device(workspace, k.device, "workspace")
     base = workspace.data_ptr()
     off = (-base) % 256
     handle = ctypes.c_void_p()
@@ -210,22 +211,30 @@ def create_problem(cfg, k, stream=None, workspace=None):
     return Problem(handle, cfg, workspace, k.device)
 
 
-def _c128(x, n, name):
+def _same_device(x, device, name):
+    """The library's kernels take every buffer of a call on one device: the
+    problem's (or the call's first buffer's) device."""
+    if device is not None and x.device != device:
+        raise ValueError("%s is on %s, the call's other buffers on %s" % (name, x.device, device))
+
+
+def _c128(x, n, name, device=None):
     if not (x.is_cuda and x.dtype == torch.complex128 and x.numel() == n and x.is_contiguous()):
         raise ValueError("%s must be a contiguous complex128 GPU tensor with %d entries" % (name, n))
+    _same_device(x, device, name)
     return x
 
 
 def precond_apply(prob, v, out=None, stream=None):
-    _c128(v, prob.N, "v")
-    x = torch.empty_like(v) if out is None else _c128(out, prob.N, "out")
+    _c128(v, prob.N, "v", prob.device)
+    x = torch.empty_like(v) if out is None else _c128(out, prob.N, "out", prob.device)
     _check(_lib.hm_precond_apply(prob.handle, _ptr(v), _ptr(x), _stream(stream)))
     return x
 
 
 def fgmres_solve(prob, b, out=None, stream=None):
-    _c128(b, prob.N, "b")
-    u = torch.empty_like(b) if out is None else _c128(out, prob.N, "out")
+    _c128(b, prob.N, "b", prob.device)
+    u = torch.empty_like(b) if out is None else _c128(out, prob.N, "out", prob.device)
     info = HmSolveInfo()
     st = _check(_lib.hm_fgmres_solve(prob.handle, _ptr(b), _ptr(u), ctypes.byref(info),
                                      _stream(stream)))
@@ -259,7 +268,7 @@ def apply_operator(prob, level, which, x, sub=0, stream=None):
                 nout = c[0] * c[1]
             else:
                 nin = c[0] * c[1]
-    _c128(x, nin, "x")
+    _c128(x, nin, "x", prob.device)
     out = torch.empty(nout, dtype=torch.complex128, device=x.device)
     _check(_lib.hm_apply_operator(prob.handle, level, sub, which, _ptr(x), _ptr(out),
                                   _stream(stream)))
@@ -301,15 +310,17 @@ def get_timing(prob):
     return out
 
 
-def _f64(x, n, name):
+def _f64(x, n, name, device=None):
     if not (x.is_cuda and x.dtype == torch.float64 and x.numel() == n and x.is_contiguous()):
         raise ValueError("%s must be a contiguous float64 GPU tensor with %d entries" % (name, n))
+    _same_device(x, device, name)
     return x
 
 
-def _i32(x, n, name):
+def _i32(x, n, name, device=None):
     if not (x.is_cuda and x.dtype == torch.int32 and x.numel() == n and x.is_contiguous()):
         raise ValueError("%s must be a contiguous int32 GPU tensor with %d entries" % (name, n))
+    _same_device(x, device, name)
     return x
 
 
@@ -317,8 +328,8 @@ def matfree_apply(nx, ny, h, k, u, out=None, stream=None):
     """v = A u with the 5-point Sommerfeld Helmholtz stencil, no stored matrix."""
     n = nx * ny
     _f64(k, n, "k")
-    _c128(u, n, "u")
-    v = torch.empty_like(u) if out is None else _c128(out, n, "out")
+    _c128(u, n, "u", k.device)
+    v = torch.empty_like(u) if out is None else _c128(out, n, "out", k.device)
     _check(_lib.hm_matfree_apply(int(nx), int(ny), float(h), _ptr(k), _ptr(u), _ptr(v),
                                  _stream(stream)))
     return v
@@ -341,11 +352,11 @@ def csr_spmv(row_ptr, col_idx, vals, x, out=None, stream=None):
     nrows = row_ptr.numel() - 1
     _i32(row_ptr, nrows + 1, "row_ptr")
     nnz = col_idx.numel()
-    _i32(col_idx, nnz, "col_idx")
-    _c128(vals, nnz, "vals")
-    _c128(x, x.numel(), "x")
+    _i32(col_idx, nnz, "col_idx", row_ptr.device)
+    _c128(vals, nnz, "vals", row_ptr.device)
+    _c128(x, x.numel(), "x", row_ptr.device)
     y = torch.empty(nrows, dtype=torch.complex128, device=x.device) if out is None \
-        else _c128(out, nrows, "out")
+        else _c128(out, nrows, "out", row_ptr.device)
     _check(_lib.hm_csr_spmv(int(nrows), _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(x),
                             _ptr(y), _stream(stream)))
     return y
@@ -393,11 +404,15 @@ class BatchProblem:
 def create_batch(cfg, ks, stream=None, workspace=None):
     """ks: one nodal wavenumber per member (float64 GPU tensors, nx*ny each)."""
     nb = len(ks)
+    if nb == 0:
+        raise ValueError("a batch needs at least one member")
     n = cfg.nx * cfg.ny
-    ks = [_f64(k.contiguous(), n, "k[%d]" % i) for i, k in enumerate(ks)]
+    dev = ks[0].device
+    ks = [_f64(k.contiguous(), n, "k[%d]" % i, dev) for i, k in enumerate(ks)]
     nbytes = batch_workspace_bytes(cfg, nb)
     if workspace is None:
-        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=ks[0].device)
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    _same_device(workspace, dev, "workspace")
     base = workspace.data_ptr()
     off = (-base) % 256
     arr = (ctypes.c_void_p * nb)(*[k.data_ptr() for k in ks])
@@ -413,9 +428,9 @@ def batch_solve(bt, bs, outs=None, stream=None):
     infos), infos[i] as for fgmres_solve with the batch status under "status"."""
     if len(bs) != bt.nb or (outs is not None and len(outs) != bt.nb):
         raise ValueError("need one right-hand side (and output) per member")
-    bs = [_c128(b, bt.N, "b[%d]" % i) for i, b in enumerate(bs)]
+    bs = [_c128(b, bt.N, "b[%d]" % i, bt.device) for i, b in enumerate(bs)]
     us = [torch.empty_like(b) for b in bs] if outs is None else \
-        [_c128(u, bt.N, "out[%d]" % i) for i, u in enumerate(outs)]
+        [_c128(u, bt.N, "out[%d]" % i, bt.device) for i, u in enumerate(outs)]
     barr = (ctypes.c_void_p * bt.nb)(*[b.data_ptr() for b in bs])
     uarr = (ctypes.c_void_p * bt.nb)(*[u.data_ptr() for u in us])
     infos = (HmSolveInfo * bt.nb)()

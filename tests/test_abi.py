@@ -135,3 +135,66 @@ def test_batch_workspace_and_argument_checks_on_the_host():
     assert lib.hm_batch_solve(None, None, None, None, None) == hm.HM_ERR_ARG
     assert lib.hm_batch_member(None, 0) is None
     assert lib.hm_destroy_batch(None) == hm.HM_ERR_ARG
+
+
+class _FakeGpuTensor:
+    """Stands in for a GPU tensor in the binding's host-side argument checks (no
+    GPU here): only the attributes those checks read, with real torch devices."""
+
+    def __init__(self, n, dtype, device):
+        self.is_cuda, self.dtype, self.device, self._n = True, dtype, device, n
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return True
+
+
+def test_binding_checks_dtype_size_host_and_device():
+    import torch
+    hm = pytest.importorskip("paper_2412_04980_amd")
+    d0, d1 = torch.device("cuda", 0), torch.device("cuda", 1)
+    x = _FakeGpuTensor(10, torch.complex128, d0)
+    assert hm._c128(x, 10, "x", d0) is x
+    assert hm._c128(x, 10, "x", torch.device("cuda:0")) is x
+    assert hm._c128(x, 10, "x") is x
+    with pytest.raises(ValueError, match="is on cuda:1"):
+        hm._c128(_FakeGpuTensor(10, torch.complex128, d1), 10, "x", d0)
+    with pytest.raises(ValueError, match="is on cuda:1"):
+        hm._f64(_FakeGpuTensor(10, torch.float64, d1), 10, "k", d0)
+    with pytest.raises(ValueError, match="is on cuda:1"):
+        hm._i32(_FakeGpuTensor(11, torch.int32, d1), 11, "row_ptr", d0)
+    with pytest.raises(ValueError):
+        hm._c128(torch.zeros(10, dtype=torch.complex128), 10, "x")     # host memory
+    with pytest.raises(ValueError):
+        hm._c128(_FakeGpuTensor(10, torch.complex64, d0), 10, "x", d0)
+    with pytest.raises(ValueError):
+        hm._c128(_FakeGpuTensor(9, torch.complex128, d0), 10, "x", d0)
+
+
+def test_wrappers_reject_buffers_on_another_device_before_any_call():
+    """The solve and apply wrappers check every buffer against the problem's
+    device first; the fake problems' handles are never passed to the library."""
+    import torch
+    hm = pytest.importorskip("paper_2412_04980_amd")
+    d0, d1 = torch.device("cuda", 0), torch.device("cuda", 1)
+
+    class Prob:
+        N, device, handle = 10, d0, None
+
+    class Batch:
+        N, nb, device, handle = 10, 2, d0, None
+
+    far = _FakeGpuTensor(10, torch.complex128, d1)
+    near = _FakeGpuTensor(10, torch.complex128, d0)
+    with pytest.raises(ValueError, match="is on cuda:1"):
+        hm.fgmres_solve(Prob, far)
+    with pytest.raises(ValueError, match="is on cuda:1"):
+        hm.fgmres_solve(Prob, near, out=far)
+    with pytest.raises(ValueError, match="is on cuda:1"):
+        hm.precond_apply(Prob, far)
+    with pytest.raises(ValueError, match="is on cuda:1"):
+        hm.batch_solve(Batch, [near, far])
+    with pytest.raises(ValueError, match="at least one member"):
+        hm.create_batch(hm.default_config(9, 9, 1 / 8), [])
