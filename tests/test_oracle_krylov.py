@@ -83,3 +83,35 @@ def test_zero_rhs():
     A, b = _system()
     x, steps, est = fgmres(lambda v: A @ v, 0 * b, None, tol=1e-6, maxit=5)
     assert steps == 0 and not x.any()
+
+
+def _krylov_minimiser(A, b, M, j):
+    """argmin ||b - A x|| over x in M K_j(A M, b), from an orthonormal basis of
+    the explicit Krylov matrix [b, (AM) b, ..., (AM)^{j-1} b] (M = I: GMRES)."""
+    cols = [b]
+    for _ in range(j - 1):
+        cols.append(A @ (M @ cols[-1]))
+    Q, _ = np.linalg.qr(np.stack(cols, axis=1))
+    y = np.linalg.lstsq(A @ (M @ Q), b, rcond=None)[0]
+    return M @ (Q @ y)
+
+
+@pytest.mark.parametrize("j", [1, 2, 4, 7])
+@pytest.mark.parametrize("preconditioned", [False, True])
+def test_iterate_minimises_the_residual_over_the_krylov_space(j, preconditioned):
+    """The defining property of (F)GMRES with a fixed preconditioner: after
+    exactly j steps from zero, x_j minimises ||b - A x|| over M K_j(AM, b).
+    Checked at every j, not only at convergence, so a wrong rotation sign, a
+    transposed Hessenberg or a misplaced update fails at the step it enters."""
+    A, b = _system(n=30, seed=3)
+    rng = np.random.default_rng(4)
+    M = np.eye(30) + 0.1 * (rng.standard_normal((30, 30)) + 1j * rng.standard_normal((30, 30)))
+    if not preconditioned:
+        M = np.eye(30)
+    x, steps, est = fgmres(lambda v: A @ v, b, (lambda v: M @ v) if preconditioned else None,
+                           tol=None, maxit=j)
+    assert steps == j
+    xr = _krylov_minimiser(A, b, M, j)
+    assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
+    # the estimate is that minimal residual
+    assert abs(est - np.linalg.norm(b - A @ xr) / np.linalg.norm(b)) <= 1e-12
