@@ -6,6 +6,7 @@ multigrid iteration for the CSLP: its fixed point is the exact solution and it
 is a linear map when the coarsest solve is direct.
 """
 import numpy as np
+import pytest
 import scipy.sparse.linalg as spla
 
 from oracle import operators as op
@@ -72,3 +73,42 @@ def test_rules():
     assert smoothing_weight(10.0, 0.2) == 0.5
     assert krylov_maxit(1089) == 34
     assert krylov_maxit(1050625) == 192
+
+
+def _cycle_closed_form(V):
+    """B_0 of the textbook V-cycle recursion, from dense matrices: with an exact
+    coarsest solve B_L = M_L^-1, smoother S_q = I - omega_q D_q^-1 M_q, and
+    E_q = S_q^nu_post (I - P_q B_{q+1} R_q M_q) S_q^nu_pre,  B_q = (I - E_q) M_q^-1."""
+    L = len(V.levels) - 1
+    B = np.linalg.inv(V.levels[L].M.toarray())
+    for q in range(L - 1, -1, -1):
+        lev = V.levels[q]
+        M = lev.M.toarray()
+        I = np.eye(M.shape[0])
+        S = I - lev.omega * (M / lev.diag[:, None])
+        R, P = V.R[q].toarray(), V.P[q].toarray()
+        E = np.linalg.matrix_power(S, V.nu_post) @ (I - P @ B @ R @ M) \
+            @ np.linalg.matrix_power(S, V.nu_pre)
+        B = (I - E) @ np.linalg.inv(M)
+    return B
+
+
+@pytest.mark.parametrize("nx, ny, nu_pre, nu_post", [(9, 5, 1, 1), (9, 9, 1, 1), (9, 9, 2, 1),
+                                                     (13, 9, 1, 2)])
+def test_vcycle_is_the_textbook_recursion(nx, ny, nu_pre, nu_post):
+    """The cycle's composition (pre-smoothing from zero, restriction of the
+    residual, recursive correction, prolongation, post-smoothing) against the
+    closed-form error operator of the V-cycle, column by column: two-level
+    (9 x 5) and three-level (9 x 9, 13 x 9) hierarchies with a direct coarsest
+    solve, V(1,1), V(2,1) and V(1,2)."""
+    h = 1.0 / 8
+    rng = np.random.default_rng(nx * ny + nu_pre)
+    k = 6.0 * rng.uniform(0.8, 1.2, nx * ny)
+    sigma = 1.0 + 0.5j
+    M = op.five_point(nx, ny, h, k, sigma)
+    V = VCycle(nx, ny, h, k, M, sigma, 1.0, nu_pre=nu_pre, nu_post=nu_post)
+    assert V.dense and len(V.levels) == (2 if ny == 5 else 3)
+    N = nx * ny
+    got = np.stack([V(np.eye(N, dtype=np.complex128)[:, i]) for i in range(N)], axis=1)
+    ref = _cycle_closed_form(V)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
