@@ -126,3 +126,21 @@ def test_config0_iteration_count_in_paper_range():
     # the paper's MADP runs take 10-19 outer steps (its tables of Sec. 4.4 and 4.5);
     # a trend check, not an exact pin
     assert 5 <= info["outer_iters"] <= 20
+
+
+def test_adef1_closed_form_with_an_arbitrary_linear_M():
+    """Sec. 3.1: P_ADEF1 v = M^-1 (v - A Q v) + Q v with Q = Z E^-1 Z^T, for any
+    v and any linear approximation M^-1 of the CSLP inverse (here a random dense
+    matrix in place of the V-cycle), with the exact Galerkin coarse solve."""
+    n, h, k = _problem(n=17)
+    N = n * n
+    rng = np.random.default_rng(5)
+    Minv = np.eye(N) + 0.05 * (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    m = _two_level_exact(n, h, k, cslp_override={1: lambda r: Minv @ r})
+    A = m.levels[1].A
+    Z = m.levels[1].Z
+    Einv = np.linalg.inv(m.levels[2].A.toarray())
+    v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    Qv = Z @ (Einv @ (Z.T @ v))
+    ref = Minv @ (v - A @ Qv) + Qv
+    assert np.linalg.norm(m.apply(v) - ref) <= 1e-12 * np.linalg.norm(ref)
