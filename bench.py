@@ -20,6 +20,8 @@ Other measurements, each one JSON line of its own:
     --complexity   five-level MADP on the wedge stand-in at kh = 0.1745, 145x241..4609x7681
     --variants     MADP-v3, W-cycle, fixed steps and deeper hierarchies on the bench workload
     --shots        every right-hand side of --config I, sequential vs one lockstep batch
+    --kernels      the component kernels of --config I one by one, with measured
+                   copy / read-stream bandwidth ceilings
 """
 import argparse
 import json
@@ -88,6 +90,12 @@ def parse():
                     help="all right-hand sides of the workload (config 3: 8 surface shots), "
                          "solved one after another and as one lockstep batch")
     ap.add_argument("--shots-precision", choices=("fp64", "mixed"), default="mixed")
+    ap.add_argument("--kernels", action="store_true",
+                    help="component kernels of the workload (every level operator, the "
+                         "deflation and multigrid transfers, the V-cycles) timed one by one "
+                         "through the C ABI, with a plain copy and a read-only stream as "
+                         "measured bandwidth ceilings")
+    ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size, to calibrate hardware byte counters)")
@@ -232,6 +240,123 @@ def serving_bench(args):
            "config": {"workload": "serving stream (Poisson, random media, 257^2..2049^2)"},
            **summ, "by_grid": by_class,
            "max_concurrent": max(e[4] for e in sched.events)}
+    print(json.dumps(out), flush=True)
+
+
+def bandwidth_ceilings(torch, mib=1024, reps=20):
+    """Measured ceilings on this GPU: a device-to-device copy (read + write) and
+    a read-only stream (a sum over the array), both over `mib` MiB, in GB/s."""
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, nbytes in (("copy_GBps", lambda: y.copy_(x), 2 * 8 * n),
+                             ("read_GBps", lambda: x.sum(), 8 * n)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[name] = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    out["array_MiB"] = mib
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
+# Algorithmic bytes per grid point of the component kernels (each array read or
+# written once; es = bytes of a complex value, kb of a wavenumber), on the grid
+# named in the table (the fine grid of a transfer).
+def _component_bytes(es, kb):
+    return {"apply": 2 * es + kb, "deflation_restrict": es + es / 4,
+            "deflation_prolong": es / 4 + es, "jacobi_first": 2 * es + kb,
+            "full_weighting": es + es / 4, "prolong_bilinear_add+zero": es + es / 4 + 2 * es}
+
+
+def kernels_bench(args):
+    """Each component kernel of the workload's preconditioner applied R times in
+    a row through the C ABI (hm_apply_operator) and timed with HIP events on the
+    stream; bytes are algorithmic, rates are against the 8 TB/s peak and against
+    the measured copy / read ceilings."""
+    import ctypes
+
+    import torch
+
+    import paper_2412_04980_amd as hm
+    import workloads
+    dev = torch.device("cuda:0")
+    problem = workloads.config(args.config)
+    k = torch.from_numpy(problem.k).to(dev)
+    ceil = bandwidth_ceilings(torch)
+    log("ceilings: copy %.0f GB/s, read %.0f GB/s" % (ceil["copy_GBps"], ceil["read_GBps"]))
+    rows = []
+    for prec_name, prec in (("fp64", hm.HM_FP64), ("fp32", hm.HM_MIXED_FP32_ALL)):
+        cfg = hm.default_config(problem.nx, problem.ny, problem.h, precision=prec)
+        prob = hm.create_problem(cfg, k)
+        es, kb = (16, 8) if prec == hm.HM_FP64 else (8, 4)
+        per = _component_bytes(es, kb)
+        ops = []
+        for level in (1, 2, 3):
+            ops.append((level, 0, hm.HM_OP_A, "apply", "A/E"))
+            ops.append((level, 0, hm.HM_OP_M, "apply", "M (CSLP)"))
+            if level < 3:
+                ops.append((level, 0, hm.HM_OP_ZT, "deflation_restrict", "Z^T"))
+                ops.append((level, 0, hm.HM_OP_Z, "deflation_prolong", "Z"))
+                for sub in (0, 1):
+                    ops.append((level, sub, hm.HM_OP_MG_JACOBI, "jacobi_first", "MG Jacobi (x=0)"))
+                    ops.append((level, sub, hm.HM_OP_MG_RESTRICT, "full_weighting", "MG full weighting"))
+                    ops.append((level, sub, hm.HM_OP_MG_PROLONG, "prolong_bilinear_add+zero",
+                                "MG bilinear add (+ zero fill)"))
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        for level, sub, which, kind, label in ops:
+            f = hm.level_shape(prob, level, sub)
+            nf = f[0] * f[1]
+            if which in (hm.HM_OP_ZT, hm.HM_OP_MG_RESTRICT):
+                c = hm.level_shape(prob, level + 1, 0) if which == hm.HM_OP_ZT else \
+                    hm.level_shape(prob, level, sub + 1)
+                nin, nout = nf, c[0] * c[1]
+            elif which in (hm.HM_OP_Z, hm.HM_OP_MG_PROLONG):
+                c = hm.level_shape(prob, level + 1, 0) if which == hm.HM_OP_Z else \
+                    hm.level_shape(prob, level, sub + 1)
+                nin, nout = c[0] * c[1], nf
+            else:
+                nin = nout = nf
+            x = torch.randn(nin, dtype=torch.complex128, device=dev)
+            y = torch.empty(nout, dtype=torch.complex128, device=dev)
+            call = lambda: hm._lib.hm_apply_operator(prob.handle, level, sub, which,
+                                                     ctypes.c_void_p(x.data_ptr()),
+                                                     ctypes.c_void_p(y.data_ptr()), stream)
+            for _ in range(3):
+                assert call() == 0
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.kernel_reps):
+                call()
+            e1.record()
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / args.kernel_reps
+            gbs = per[kind] * nf / (us * 1e-6) / 1e9
+            row = {"precision": prec_name, "level": level, "mg_level": sub, "op": label,
+                   "grid": "%dx%d" % f, "us": us, "GBps": gbs, "frac_of_peak": gbs / HBM_PEAK_GBS,
+                   "frac_of_copy": gbs / ceil["copy_GBps"], "bytes_per_point": per[kind]}
+            if prec_name == "fp32":
+                row["note"] = "time includes the complex128 <-> complex64 casts of the test hook"
+            rows.append(row)
+            log("%s L%d/%d %-30s %-10s %8.1f us %7.0f GB/s %.2f" % (
+                prec_name, level, sub, label, row["grid"], us, gbs, gbs / HBM_PEAK_GBS))
+            del x, y
+        prob.close()
+        torch.cuda.empty_cache()
+    out = {"metric": "component kernel rates (algorithmic bytes / event time)",
+           "unit": "GB/s", "n_gpus": 1, "data": "synthetic", "reps": args.kernel_reps,
+           "peak_GBps": HBM_PEAK_GBS, "ceilings": ceil,
+           "config": {"workload": problem.name, "nx": problem.nx, "ny": problem.ny},
+           "table": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -501,6 +626,9 @@ def main():
         return
     if args.shots:
         shots_bench(args)
+        return
+    if args.kernels:
+        kernels_bench(args)
         return
     dev = torch.device("cuda:0")
     if args.copy_calibration:

@@ -221,6 +221,18 @@ enum {
 hm_status hm_set_timing(hm_problem* p, unsigned mask, int every);
 hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes, long* launches);
 
+/* Load hints of the two Gram-Schmidt passes of the Krylov CSLP (GMRES with
+ * classical Gram-Schmidt, the coarsest-level CSLP approximation of Sec. 4.2 /
+ * 4.4).  A basis of (m+1) vectors plus w of at most basis_bytes is read with
+ * plain loads, which keep it in the 256 MB Infinity Cache between the passes;
+ * a larger one reads its most recent vectors, recent_bytes of them, with plain
+ * loads and the older ones with the non-temporal hint.  Defaults 256 MiB and
+ * 200 MiB; a negative value restores a default.  The arithmetic and the
+ * results are the same for every setting: this is a tuning hook, and it lets
+ * small problems run the large-basis code path.  HM_ERR_ARG for NaN or a null
+ * problem. */
+hm_status hm_set_basis_cache(hm_problem* p, double basis_bytes, double recent_bytes);
+
 hm_status hm_destroy_problem(hm_problem* p);
 
 /* ---- Lockstep batches: several problems of one configuration per launch -----
@@ -277,14 +289,38 @@ hm_status hm_destroy_batch(hm_batch* bt);
  *   entries (centre, west, east, south, north); at a boundary the ghost's
  *   coupling is folded into the mirrored neighbour and the freed slot holds an
  *   explicit zero whose column is the row itself.
- * hm_csr_spmv: y = A x for any CSR matrix with 32-bit indices (nrows rows,
- *   columns < the length of x), one thread per row. */
+ * hm_csr_spmv: y = A x for any CSR matrix with 32-bit indices: nrows rows,
+ *   ncols columns, x holds ncols entries, y nrows; row_ptr must be
+ *   non-decreasing with row_ptr[nrows] entries in col_idx and vals.  An entry
+ *   whose column lies outside [0, ncols) is not read from x: its row's result
+ *   is NaN.  Rows are staged per block through LDS. */
 hm_status hm_matfree_apply(int nx, int ny, double h, const double* k_dev, const void* u_dev,
                            void* v_dev, void* stream);
 hm_status hm_csr_assemble(int nx, int ny, double h, const double* k_dev, int* row_ptr_dev,
                           int* col_idx_dev, void* vals_dev, void* stream);
-hm_status hm_csr_spmv(int nrows, const int* row_ptr_dev, const int* col_idx_dev,
+hm_status hm_csr_spmv(int nrows, int ncols, const int* row_ptr_dev, const int* col_idx_dev,
                       const void* vals_dev, const void* x_dev, void* y_dev, void* stream);
+
+/* ---- True residual (the stopping test of Sec. 4) ------------------------------
+ * r = b - A u and its norm for the finest-level operator of eq. (helm operator
+ * h): the 5-point Helmholtz stencil -Laplace_h - k^2 on an nx x ny node grid of
+ * spacing h with boundary condition bc (hm_bc: Sommerfeld ghosts or the
+ * decoupled Dirichlet rows), in FP64.  The relative residual of a solution is
+ * norms[0] / norms[1], the quantity FGMRES stops on (Sec. 4: 1e-6).
+ *   k_dev: nx*ny doubles; b_dev, u_dev: nx*ny complex128; all device, read only.
+ *   r_dev: nx*ny complex128 written with b - A u, or NULL (norms only); it
+ *          may be b_dev but not u_dev.
+ *   norms_dev: device, 2 doubles: ||b - A u||_2, ||b||_2 (written by the call).
+ *   workspace: device, >= hm_residual_workspace_bytes() bytes, 256-byte
+ *          aligned: the reduction's partial sums (no state is kept there).
+ * One pass over u, k and b (neighbours from cache) plus a fixed-order sum of
+ * at most 2048 partials, so the result is bitwise reproducible.  Asynchronous
+ * on `stream`; HM_ERR_ARG for bad sizes, pointers, aliasing or alignment,
+ * HM_ERR_NOMEM for a short workspace, HM_ERR_HIP for a failed launch. */
+size_t hm_residual_workspace_bytes(void);
+hm_status hm_residual(int nx, int ny, double h, int bc, const double* k_dev, const void* b_dev,
+                      const void* u_dev, void* r_dev, double* norms_dev, void* workspace,
+                      size_t workspace_bytes, void* stream);
 
 const char* hm_status_string(hm_status s);
 const char* hm_last_error(void);

@@ -49,9 +49,10 @@ TIMING_CLASSES = {HM_TK_CGS_DOT: "cgs_dot", HM_TK_CGS_UPDATE: "cgs_update_norm",
 EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_precond_apply",
             "hm_fgmres_solve", "hm_apply_operator", "hm_level_shape", "hm_set_replay",
             "hm_get_counts", "hm_reset_counts", "hm_set_timing", "hm_get_timing",
-            "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
+            "hm_set_basis_cache", "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
             "hm_batch_workspace_bytes", "hm_create_batch", "hm_batch_solve", "hm_batch_member",
-            "hm_destroy_batch", "hm_status_string", "hm_last_error"]
+            "hm_destroy_batch", "hm_residual_workspace_bytes", "hm_residual",
+            "hm_status_string", "hm_last_error"]
 
 MAX_BATCH = 16
 
@@ -113,10 +114,11 @@ def _load():
         "hm_set_timing": (I, [P, ctypes.c_uint, I]),
         "hm_get_timing": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(D),
                               ctypes.POINTER(ctypes.c_long)]),
+        "hm_set_basis_cache": (I, [P, D, D]),
         "hm_destroy_problem": (I, [P]),
         "hm_matfree_apply": (I, [I, I, D, P, P, P, P]),
         "hm_csr_assemble": (I, [I, I, D, P, P, P, P, P]),
-        "hm_csr_spmv": (I, [I, P, P, P, P, P, P]),
+        "hm_csr_spmv": (I, [I, I, P, P, P, P, P, P]),
         "hm_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(HmConfig), I]),
         "hm_create_batch": (I, [ctypes.POINTER(HmConfig), I, ctypes.POINTER(P), P,
                                 ctypes.c_size_t, P, ctypes.POINTER(P)]),
@@ -124,6 +126,8 @@ def _load():
                                ctypes.POINTER(HmSolveInfo), P]),
         "hm_batch_member": (P, [P, I]),
         "hm_destroy_batch": (I, [P]),
+        "hm_residual_workspace_bytes": (ctypes.c_size_t, []),
+        "hm_residual": (I, [I, I, D, I, P, P, P, P, P, P, ctypes.c_size_t, P]),
         "hm_status_string": (ctypes.c_char_p, [I]),
         "hm_last_error": (ctypes.c_char_p, []),
     }
@@ -151,6 +155,14 @@ def _stream(stream):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _ordered(x, stream):
+    """x was produced on torch's current stream; a call on another stream must
+    not read it before that work is done."""
+    if stream is not None and stream != torch.cuda.current_stream(x.device):
+        stream.wait_stream(torch.cuda.current_stream(x.device))
+    return x
 
 
 def default_config(nx, ny, h, **overrides):
@@ -197,7 +209,7 @@ def create_problem(cfg, k, stream=None, workspace=None):
     """k: nodal wavenumber, torch.float64 CUDA tensor with nx*ny entries."""
     if not (k.is_cuda and k.dtype == torch.float64 and k.numel() == cfg.nx * cfg.ny):
         raise ValueError("k must be a float64 GPU tensor with nx*ny entries")
-    k = k.contiguous()
+    k = _ordered(k.contiguous(), stream)
     nbytes = workspace_bytes(cfg)
     if workspace is None:
         workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=k.device)
@@ -292,6 +304,11 @@ def reset_counts(prob):
     _check(_lib.hm_reset_counts(prob.handle))
 
 
+def set_basis_cache(prob, basis_bytes=-1.0, recent_bytes=-1.0):
+    """Load hints of the Krylov CSLP's Gram-Schmidt passes (negative: default)."""
+    _check(_lib.hm_set_basis_cache(prob.handle, float(basis_bytes), float(recent_bytes)))
+
+
 def set_timing(prob, mask, every=1):
     """Enables HIP-event timing of every `every`-th launch of the kernel classes in
     `mask` (one bit per class); mask 0 turns it off."""
@@ -347,19 +364,53 @@ def csr_assemble(nx, ny, h, k, stream=None):
     return row_ptr, col_idx, vals
 
 
-def csr_spmv(row_ptr, col_idx, vals, x, out=None, stream=None):
-    """y = A x for a CSR matrix with int32 indices and complex128 values."""
+def csr_spmv(row_ptr, col_idx, vals, x, ncols=None, out=None, stream=None):
+    """y = A x for a CSR matrix with int32 indices and complex128 values; x has
+    ncols entries (default: square, ncols = the number of rows)."""
     nrows = row_ptr.numel() - 1
+    ncols = nrows if ncols is None else int(ncols)
+    if x.numel() != ncols:
+        # the kernel reads x only at column indices below ncols
+        raise ValueError("x has %d entries, the matrix %d columns" % (x.numel(), ncols))
     _i32(row_ptr, nrows + 1, "row_ptr")
     nnz = col_idx.numel()
     _i32(col_idx, nnz, "col_idx", row_ptr.device)
     _c128(vals, nnz, "vals", row_ptr.device)
-    _c128(x, x.numel(), "x", row_ptr.device)
+    _c128(x, ncols, "x", row_ptr.device)
     y = torch.empty(nrows, dtype=torch.complex128, device=x.device) if out is None \
         else _c128(out, nrows, "out", row_ptr.device)
-    _check(_lib.hm_csr_spmv(int(nrows), _ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(x),
-                            _ptr(y), _stream(stream)))
+    _check(_lib.hm_csr_spmv(int(nrows), ncols, _ptr(row_ptr), _ptr(col_idx), _ptr(vals),
+                            _ptr(x), _ptr(y), _stream(stream)))
     return y
+
+
+def _residual_args(nx, ny, k, b, u, r):
+    n = nx * ny
+    _f64(k, n, "k")
+    _c128(b, n, "b", k.device)
+    _c128(u, n, "u", k.device)
+    if r is not None:
+        _c128(r, n, "r", k.device)
+        if r.data_ptr() == u.data_ptr():
+            raise ValueError("r must not alias u")
+    return torch.empty(2, dtype=torch.float64, device=k.device)
+
+
+def residual(nx, ny, h, k, b, u, bc=HM_BC_SOMMERFELD, r=None, workspace=None, stream=None):
+    """(||b - A u||_2, ||b||_2) on the device as a float64 tensor of 2; r, if
+    given, receives b - A u (the 5-point operator of the finest level)."""
+    norms = _residual_args(nx, ny, k, b, u, r)
+    nbytes = _lib.hm_residual_workspace_bytes()
+    if workspace is None:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=k.device)
+    _same_device(workspace, k.device, "workspace")
+    base = workspace.data_ptr()
+    off = (-base) % 256
+    _check(_lib.hm_residual(int(nx), int(ny), float(h), int(bc), _ptr(k), _ptr(b), _ptr(u),
+                            None if r is None else _ptr(r), _ptr(norms),
+                            ctypes.c_void_p(base + off), ctypes.c_size_t(workspace.numel() - off),
+                            _stream(stream)))
+    return norms
 
 
 def destroy_problem(prob):
@@ -408,7 +459,7 @@ def create_batch(cfg, ks, stream=None, workspace=None):
         raise ValueError("a batch needs at least one member")
     n = cfg.nx * cfg.ny
     dev = ks[0].device
-    ks = [_f64(k.contiguous(), n, "k[%d]" % i, dev) for i, k in enumerate(ks)]
+    ks = [_ordered(_f64(k.contiguous(), n, "k[%d]" % i, dev), stream) for i, k in enumerate(ks)]
     nbytes = batch_workspace_bytes(cfg, nb)
     if workspace is None:
         workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)

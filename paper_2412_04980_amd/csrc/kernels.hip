@@ -821,6 +821,16 @@ __device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
   return mk(t.x, t.y);
 }
 
+// (re, im) += conj(v) w in FP64 with explicitly fused multiply-adds, so that
+// every instantiation (plain or non-temporal loads) rounds the same way
+template <typename T>
+__device__ __forceinline__ void dot_acc(double& re, double& im, const cx<T>& v, const cx<T>& w) {
+  re = fma((double)v.re, (double)w.re, re);
+  re = fma((double)v.im, (double)w.im, re);
+  im = fma((double)v.re, (double)w.im, im);
+  im = fma(-(double)v.im, (double)w.re, im);
+}
+
 // One chunk of the partial dots of w with NG consecutive basis vectors (NG and
 // the load kind fixed at compile time, so that the NG + 1 loads of a row are
 // all in flight together); re/im accumulate over the rows in order.
@@ -839,10 +849,8 @@ __device__ __forceinline__ void dot_rows(const cx<T>* __restrict__ V, size_t ldv
     }
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      re[g] += (double)va[g].re * (double)wa.re + (double)va[g].im * (double)wa.im;
-      im[g] += (double)va[g].re * (double)wa.im - (double)va[g].im * (double)wa.re;
-      re[g] += (double)vb[g].re * (double)wb.re + (double)vb[g].im * (double)wb.im;
-      im[g] += (double)vb[g].re * (double)wb.im - (double)vb[g].im * (double)wb.re;
+      dot_acc(re[g], im[g], va[g], wa);
+      dot_acc(re[g], im[g], vb[g], wb);
     }
   }
   if (i < hi) {
@@ -851,10 +859,7 @@ __device__ __forceinline__ void dot_rows(const cx<T>* __restrict__ V, size_t ldv
 #pragma unroll
     for (int g = 0; g < NG; ++g) v[g] = NTL ? load_stream(V + (size_t)g * ldv + i) : V[(size_t)g * ldv + i];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      re[g] += (double)v[g].re * (double)wv.re + (double)v[g].im * (double)wv.im;
-      im[g] += (double)v[g].re * (double)wv.im - (double)v[g].im * (double)wv.re;
-    }
+    for (int g = 0; g < NG; ++g) dot_acc(re[g], im[g], v[g], wv);
   }
 }
 
@@ -1004,6 +1009,16 @@ __global__ void __launch_bounds__(NT) k_mgs_step(cx<T>* __restrict__ w, const cx
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// (re, im) += c v in FP64 with explicitly fused multiply-adds (the same
+// rounding in every instantiation)
+template <typename T>
+__device__ __forceinline__ void upd_acc(double& re, double& im, const c128& c, const cx<T>& v) {
+  re = fma(c.re, (double)v.re, re);
+  re = fma(-c.im, (double)v.im, re);
+  im = fma(c.re, (double)v.im, im);
+  im = fma(c.im, (double)v.re, im);
+}
+
 // w -= sum_j h_j V_j with the partial ||w||^2 of one chunk; every thread
 // updates two elements (i, i + NT) per pass for more loads in flight.
 template <typename T, bool STREAM>
@@ -1029,21 +1044,21 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
       const c128 c = h[j];
       const bool old = STREAM && j < m - recent;   // see k_multidot
       const cx<T> v0 = old ? load_stream(V + (size_t)j * ldv + i) : V[(size_t)j * ldv + i];
-      re0 += c.re * (double)v0.re - c.im * (double)v0.im;
-      im0 += c.re * (double)v0.im + c.im * (double)v0.re;
+      upd_acc(re0, im0, c, v0);
       if (two) {
         const cx<T> v1 = old ? load_stream(V + (size_t)j * ldv + i2) : V[(size_t)j * ldv + i2];
-        re1 += c.re * (double)v1.re - c.im * (double)v1.im;
-        im1 += c.re * (double)v1.im + c.im * (double)v1.re;
+        upd_acc(re1, im1, c, v1);
       }
     }
     const cx<T> n0 = mk((T)((double)w0.re - re0), (T)((double)w0.im - im0));
     w[i] = n0;
-    acc += (double)n0.re * (double)n0.re + (double)n0.im * (double)n0.im;
+    acc = fma((double)n0.re, (double)n0.re, acc);
+    acc = fma((double)n0.im, (double)n0.im, acc);
     if (two) {
       const cx<T> n1 = mk((T)((double)w1.re - re1), (T)((double)w1.im - im1));
       w[i2] = n1;
-      acc += (double)n1.re * (double)n1.re + (double)n1.im * (double)n1.im;
+      acc = fma((double)n1.re, (double)n1.re, acc);
+      acc = fma((double)n1.im, (double)n1.im, acc);
     }
   }
   const c128 s = block_sum(acc, 0.0, sh);
@@ -1064,6 +1079,48 @@ __global__ void __launch_bounds__(NT) k_norm2(const cx<T>* __restrict__ x, size_
   }
   const c128 s = block_sum(acc, 0.0, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// True residual r = b - A u of the five-point operator d (FP64) over one chunk
+// of the nodes, with the chunk's partial sums of |r|^2 (re) and |b|^2 (im);
+// r is written when it is not null.
+__global__ void __launch_bounds__(NT) k_residual_norm(OpDesc<double> d, const c128* __restrict__ u,
+                                                      const double* __restrict__ k,
+                                                      const c128* __restrict__ b,
+                                                      c128* __restrict__ r, size_t n, size_t clen,
+                                                      c128* __restrict__ partials) {
+  __shared__ double sh[2 * NT / 64];
+  const size_t lo = (size_t)blockIdx.x * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  double rr = 0, bb = 0;
+  for (size_t p = lo + threadIdx.x; p < hi; p += NT) {
+    const int y = (int)(p / (size_t)d.nx);
+    const int x = (int)(p - (size_t)y * d.nx);
+    const c128 bv = b[p];
+    const c128 rv = bv - five_point_any(d, u, k, x, y);
+    if (r) r[p] = rv;
+    rr += rv.re * rv.re + rv.im * rv.im;
+    bb += bv.re * bv.re + bv.im * bv.im;
+  }
+  const c128 s = block_sum(rr, bb, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// norms[0] = sqrt(sum of re), norms[1] = sqrt(sum of im) over the partials,
+// summed in a fixed order
+__global__ void __launch_bounds__(NT) k_residual_final(const c128* __restrict__ partials,
+                                                       int nchunks, double* __restrict__ norms) {
+  __shared__ double sh[2 * NT / 64];
+  double re = 0, im = 0;
+  for (int c = threadIdx.x; c < nchunks; c += NT) {
+    re += partials[c].re;
+    im += partials[c].im;
+  }
+  const c128 s = block_sum(re, im, sh);
+  if (threadIdx.x == 0) {
+    norms[0] = sqrt(s.re);
+    norms[1] = sqrt(s.im);
+  }
 }
 
 __global__ void __launch_bounds__(NT) k_check_k(const double* __restrict__ k, size_t n, size_t clen,
@@ -1142,7 +1199,13 @@ __global__ void __launch_bounds__(NT) k_csr5_assemble(OpDesc<double> d, const do
 // per row reading its entries directly.
 constexpr int kCsrStage = 2048;
 
-__global__ void __launch_bounds__(NT) k_csr_spmv(int nrows, const int* __restrict__ rowptr,
+// x[c] for a column index inside [0, ncols), NaN otherwise (an index outside
+// makes its row's result NaN instead of reading outside x)
+__device__ __forceinline__ c128 csr_x(const c128* __restrict__ x, int c, int ncols) {
+  return (unsigned)c < (unsigned)ncols ? x[c] : mk(__builtin_nan(""), __builtin_nan(""));
+}
+
+__global__ void __launch_bounds__(NT) k_csr_spmv(int nrows, int ncols, const int* __restrict__ rowptr,
                                                  const int* __restrict__ colidx,
                                                  const c128* __restrict__ vals,
                                                  const c128* __restrict__ x, c128* __restrict__ y) {
@@ -1161,7 +1224,7 @@ __global__ void __launch_bounds__(NT) k_csr_spmv(int nrows, const int* __restric
 #pragma unroll 4
     for (int i = threadIdx.x; i < q1 - q0; i += NT) {
       const c128 v = vals[q0 + i];
-      const c128 xv = x[colidx[q0 + i]];
+      const c128 xv = csr_x(x, colidx[q0 + i], ncols);
       prod[i] = mk(v.re * xv.re - v.im * xv.im, v.re * xv.im + v.im * xv.re);
     }
     __syncthreads();
@@ -1172,7 +1235,7 @@ __global__ void __launch_bounds__(NT) k_csr_spmv(int nrows, const int* __restric
   } else {
     for (int q = a; q < b; ++q) {
       const c128 v = vals[q];
-      const c128 xv = x[colidx[q]];
+      const c128 xv = csr_x(x, colidx[q], ncols);
       re += v.re * xv.re - v.im * xv.im;
       im += v.re * xv.im + v.im * xv.re;
     }
@@ -1191,9 +1254,9 @@ hipError_t launch_csr5_assemble(const OpDesc<double>& d, const double* k, int* r
   return hipGetLastError();
 }
 
-hipError_t launch_csr_spmv(int nrows, const int* rowptr, const int* colidx, const c128* vals,
-                           const c128* x, c128* y, hipStream_t s) {
-  k_csr_spmv<<<blocks1d((size_t)nrows), NT, 0, s>>>(nrows, rowptr, colidx, vals, x, y);
+hipError_t launch_csr_spmv(int nrows, int ncols, const int* rowptr, const int* colidx,
+                           const c128* vals, const c128* x, c128* y, hipStream_t s) {
+  k_csr_spmv<<<blocks1d((size_t)nrows), NT, 0, s>>>(nrows, ncols, rowptr, colidx, vals, x, y);
   return hipGetLastError();
 }
 
@@ -1382,15 +1445,16 @@ static int multidot_chunks(size_t n, int m, const RedBuf& rb) {
 
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
-                                   RedBuf rb, hipStream_t s, const Batch& z) {
+                                   RedBuf rb, hipStream_t s, const Batch& z,
+                                   const CachePolicy& cp) {
   if (m <= 0) return hipSuccess;
   const int nch = multidot_chunks(n, m, rb);
   const size_t clen = multidot_chunk_len(n, m);
-  // load policy (kCacheBasisBytes, kCacheRecentBytes): measured on the
+  // load policy (default kCacheBasisBytes, kCacheRecentBytes): measured on the
   // coarsest-level solves of 1025^2 .. 4097^2 and 4597 x 1453 problems
   const dim3 g = zgrid(((m + G - 1) / G) * nch, z);
-  const int recent = (int)(kCacheRecentBytes / ((double)n * sizeof(cx<T>)));
-  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > kCacheBasisBytes)
+  const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
+  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis)
     k_multidot<T, true><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, recent, z);
   else
     k_multidot<T, false><<<g, NT, 0, s>>>(V, ldv, m, w, n, clen, rb.partials, nch, recent, z);
@@ -1450,12 +1514,12 @@ static int update_chunks(size_t n, const RedBuf& rb) {
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                      size_t n, RedBuf rb, hipStream_t s,
-                                     const Batch& z) {
+                                     const Batch& z, const CachePolicy& cp) {
   const int nch = update_chunks(n, rb);
   const size_t clen = update_chunk_len(n);
-  const int recent = (int)(kCacheRecentBytes / ((double)n * sizeof(cx<T>)));
+  const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
   const dim3 g = zgrid(nch, z);
-  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > kCacheBasisBytes)
+  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis)
     k_cgs_update_norm<T, true><<<g, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, recent, z);
   else
     k_cgs_update_norm<T, false><<<g, NT, 0, s>>>(w, V, ldv, m, h, n, clen, rb.partials, recent, z);
@@ -1492,6 +1556,17 @@ hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipS
   return hipGetLastError();
 }
 
+hipError_t launch_residual_norm(const OpDesc<double>& d, const c128* u, const double* k,
+                                const c128* b, c128* r, c128* partials, double* norms,
+                                hipStream_t s) {
+  const size_t n = (size_t)d.nx * d.ny;
+  const int nch = reduction_chunks(n);
+  const size_t clen = chunk_len(n, nch);
+  k_residual_norm<<<nch, NT, 0, s>>>(d, u, k, b, r, n, clen, partials);
+  k_residual_final<<<1, NT, 0, s>>>(partials, nch, norms);
+  return hipGetLastError();
+}
+
 hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s) {
   const size_t clen = chunk_len(n, rb.nchunks);
   k_check_k<<<rb.nchunks, NT, 0, s>>>(k, n, clen, rb.partials);
@@ -1521,11 +1596,13 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
   template hipError_t launch_multidot<T>(const cx<T>*, size_t, int, const cx<T>*, size_t, RedBuf,  \
                                          c128*, hipStream_t);                                       \
   template hipError_t launch_multidot_partial<T>(const cx<T>*, size_t, int, const cx<T>*, size_t,  \
-                                                 RedBuf, hipStream_t, const Batch&);                \
+                                                 RedBuf, hipStream_t, const Batch&,                 \
+                                                 const CachePolicy&);                               \
   template hipError_t launch_multidot_final<T>(int, size_t, RedBuf, c128*, hipStream_t, c128*,     \
                                                const Batch&);                                       \
   template hipError_t launch_cgs_update_partial<T>(cx<T>*, const cx<T>*, size_t, int, const c128*, \
-                                                   size_t, RedBuf, hipStream_t, const Batch&);      \
+                                                   size_t, RedBuf, hipStream_t, const Batch&,       \
+                                                   const CachePolicy&);                             \
   template hipError_t launch_stencil_scaled<T>(const OpDesc<T>&, const cx<T>*, const T*,            \
                                                const c128*, cx<T>*, cx<T>*, hipStream_t,            \
                                                const Batch&);                                       \

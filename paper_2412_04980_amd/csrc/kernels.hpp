@@ -138,9 +138,10 @@ hipError_t launch_identity(c128* out, int n, hipStream_t s);
 // pointing at the row itself.
 hipError_t launch_csr5_assemble(const OpDesc<double>& d, const double* k, int* rowptr, int* colidx,
                                 c128* vals, hipStream_t s);
-// y = A x for a CSR matrix (one thread per row)
-hipError_t launch_csr_spmv(int nrows, const int* rowptr, const int* colidx, const c128* vals,
-                           const c128* x, c128* y, hipStream_t s);
+// y = A x for a CSR matrix with nrows rows and ncols columns (x has ncols
+// entries; a column index outside [0, ncols) makes its row NaN)
+hipError_t launch_csr_spmv(int nrows, int ncols, const int* rowptr, const int* colidx,
+                           const c128* vals, const c128* x, c128* y, hipStream_t s);
 
 // ---- reductions (double accumulation; results on the device) --------------
 struct RedBuf {
@@ -159,9 +160,16 @@ int reduction_chunks(size_t n);
 // cache-resident that way; the older ones are read with the non-temporal hint.
 constexpr double kCacheBasisBytes = 256.0 * 1048576.0;
 constexpr double kCacheRecentBytes = 200.0 * 1048576.0;
+// The two thresholds as a run-time setting (a problem may override them; the
+// arithmetic is the same for every setting, only the load hints change).
+struct CachePolicy {
+  double basis = kCacheBasisBytes;
+  double recent = kCacheRecentBytes;
+};
 template <typename T>
 hipError_t launch_multidot_partial(const cx<T>* V, size_t ldv, int m, const cx<T>* w, size_t n,
-                                   RedBuf rb, hipStream_t s, const Batch& z = Batch());
+                                   RedBuf rb, hipStream_t s, const Batch& z = Batch(),
+                                   const CachePolicy& cp = CachePolicy());
 // host_out (optional): pinned host memory that receives a copy of out
 template <typename T>
 hipError_t launch_multidot_final(int m, size_t n, RedBuf rb, c128* out, hipStream_t s,
@@ -179,7 +187,8 @@ hipError_t launch_mgs_step(cx<T>* w, const cx<T>* prev, const c128* hprev, const
 template <typename T>
 hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                      size_t n, RedBuf rb, hipStream_t s,
-                                     const Batch& z = Batch());
+                                     const Batch& z = Batch(),
+                                     const CachePolicy& cp = CachePolicy());
 // sum of the partials written by launch_cgs_update_partial over a vector of length n
 hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,
                                     c128* host_out = nullptr, const Batch& z = Batch());
@@ -192,6 +201,12 @@ hipError_t launch_norm(const cx<T>* x, size_t n, RedBuf rb, c128* out, hipStream
                        c128* host_out = nullptr, const Batch& z = Batch());
 // out[0].re = max of a real field (reduction over chunks)
 hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipStream_t s);
+// True residual of the five-point operator d (FP64): r = b - A u (r may be
+// null), norms[0] = ||r||_2, norms[1] = ||b||_2 on the device.  partials: at
+// least reduction_chunks(nx * ny) <= kMaxChunks entries.
+hipError_t launch_residual_norm(const OpDesc<double>& d, const c128* u, const double* k,
+                                const c128* b, c128* r, c128* partials, double* norms,
+                                hipStream_t s);
 // Validation of the wavenumber field: out[0] = number of entries that are not
 // finite or negative (as a double in the real part).
 hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s);

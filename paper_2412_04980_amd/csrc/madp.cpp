@@ -16,6 +16,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdint>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -216,6 +217,8 @@ struct hm_problem {
   std::vector<int> rep[K_NKIND];
   size_t rep_pos[K_NKIND] = {0, 0, 0, 0};
   double last_estimate = 0;
+  // load hints of the Krylov CSLP's Gram-Schmidt passes (hm_set_basis_cache)
+  CachePolicy cache;
   // optional per-kernel-class timing with HIP events on the problem's stream
   unsigned timing_mask = 0;
   int timing_every = 1;                 // bracket every n-th launch of a class
@@ -491,11 +494,12 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
       return;
     }
     timed(p, HM_TK_CGS_DOT, nm * (j + 2) * es * N, [&] {
-      return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), p->s, z);
+      return launch_multidot_partial<T>(V, N, j + 1, wj, N, rbuf(p, N), p->s, z, p->cache);
     });
     HM_CHECK(launch_multidot_final<T>(j + 1, N, rbuf(p, N), col, p->s, hcol, z));
     timed(p, HM_TK_CGS_UPDATE, nm * (j + 3) * es * N, [&] {
-      return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), p->s, z);
+      return launch_cgs_update_partial<T>(wj, V, N, j + 1, col, N, rbuf(p, N), p->s, z,
+                                          p->cache);
     });
     HM_CHECK(launch_update_norm_final(N, rbuf(p, N), col + j + 1, p->s, hcol + j + 1, z));
     HM_CHECK(hipEventRecord(p->col_ev[j & 1], p->s));
@@ -1690,18 +1694,72 @@ hm_status hm_csr_assemble(int nx, int ny, double h, const double* k_dev, int* ro
   });
 }
 
-hm_status hm_csr_spmv(int nrows, const int* row_ptr_dev, const int* col_idx_dev,
+hm_status hm_csr_spmv(int nrows, int ncols, const int* row_ptr_dev, const int* col_idx_dev,
                       const void* vals_dev, const void* x_dev, void* y_dev, void* stream) {
-  if (nrows < 0 || !row_ptr_dev || !col_idx_dev || !vals_dev || !x_dev || !y_dev) {
+  if (nrows < 0 || ncols < 0 || !row_ptr_dev || !col_idx_dev || !vals_dev || !x_dev || !y_dev) {
     g_last_error = "csr_spmv: bad arguments";
     return HM_ERR_ARG;
   }
   if (nrows == 0) return HM_OK;
   return guard([&]() -> hm_status {
-    HM_CHECK(launch_csr_spmv(nrows, row_ptr_dev, col_idx_dev, (const c128*)vals_dev,
+    HM_CHECK(launch_csr_spmv(nrows, ncols, row_ptr_dev, col_idx_dev, (const c128*)vals_dev,
                              (const c128*)x_dev, (c128*)y_dev, (hipStream_t)stream));
     return HM_OK;
   });
+}
+
+size_t hm_residual_workspace_bytes(void) { return sizeof(c128) * (size_t)kMaxChunks; }
+
+// Arguments of the true-residual entry points; false (with the message set)
+// when one is invalid.
+static bool residual_args_ok(int nx, int ny, double h, int bc, const double* k_dev,
+                             const void* b_dev, const void* u_dev, const void* r_dev,
+                             const double* norms_dev) {
+  if (nx < 3 || ny < 3 || !(h > 0) || !std::isfinite(h)) {
+    g_last_error = "residual: need nx, ny >= 3 and h > 0";
+    return false;
+  }
+  if (bc != HM_BC_SOMMERFELD && bc != HM_BC_DIRICHLET) {
+    g_last_error = "residual: unknown boundary condition";
+    return false;
+  }
+  if (!k_dev || !b_dev || !u_dev || !norms_dev) {
+    g_last_error = "residual: null pointer";
+    return false;
+  }
+  if (r_dev && r_dev == u_dev) {
+    g_last_error = "residual: r must not alias u";
+    return false;
+  }
+  return true;
+}
+
+static hm_status residual_launch(int nx, int ny, double h, int bc, const double* k_dev,
+                                 const void* b_dev, const void* u_dev, void* r_dev,
+                                 double* norms_dev, c128* partials, void* stream) {
+  return guard([&]() -> hm_status {
+    OpDesc<double> d;
+    set_five_point(d, nx, ny, h, 1.0, cd(1.0, 0.0), bc);
+    HM_CHECK(launch_residual_norm(d, (const c128*)u_dev, k_dev, (const c128*)b_dev, (c128*)r_dev,
+                                  partials, norms_dev, (hipStream_t)stream));
+    return HM_OK;
+  });
+}
+
+hm_status hm_residual(int nx, int ny, double h, int bc, const double* k_dev, const void* b_dev,
+                      const void* u_dev, void* r_dev, double* norms_dev, void* workspace,
+                      size_t workspace_bytes, void* stream) {
+  if (!residual_args_ok(nx, ny, h, bc, k_dev, b_dev, u_dev, r_dev, norms_dev)) return HM_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace & 255)) {
+    g_last_error = "residual: workspace must be a 256-byte aligned device pointer";
+    return HM_ERR_ARG;
+  }
+  if (workspace_bytes < hm_residual_workspace_bytes()) {
+    g_last_error = "residual: workspace smaller than hm_residual_workspace_bytes()";
+    return HM_ERR_NOMEM;
+  }
+  return residual_launch(nx, ny, h, bc, k_dev, b_dev, u_dev, r_dev, norms_dev, (c128*)workspace,
+                         stream);
 }
 
 hm_status hm_set_timing(hm_problem* p, unsigned mask, int every) {
@@ -1719,6 +1777,14 @@ hm_status hm_set_timing(hm_problem* p, unsigned mask, int every) {
     }
     return HM_OK;
   });
+}
+
+hm_status hm_set_basis_cache(hm_problem* p, double basis_bytes, double recent_bytes) {
+  if (!p || std::isnan(basis_bytes) || std::isnan(recent_bytes)) return HM_ERR_ARG;
+  const CachePolicy def;
+  p->cache.basis = basis_bytes < 0 ? def.basis : basis_bytes;
+  p->cache.recent = recent_bytes < 0 ? def.recent : recent_bytes;
+  return HM_OK;
 }
 
 hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes, long* launches) {

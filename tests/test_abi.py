@@ -102,8 +102,29 @@ def test_matvec_entry_points_reject_bad_sizes_on_the_host():
         assert lib.hm_csr_assemble(nx, ny, h, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
     # valid sizes, missing pointers
     assert lib.hm_matfree_apply(5, 5, 0.1, nul, nul, nul, nul) == hm.HM_ERR_ARG
-    assert lib.hm_csr_spmv(-1, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
-    assert lib.hm_csr_spmv(4, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
+    assert lib.hm_csr_spmv(-1, 4, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
+    assert lib.hm_csr_spmv(4, -1, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
+    assert lib.hm_csr_spmv(4, 4, nul, nul, nul, nul, nul, nul) == hm.HM_ERR_ARG
+
+
+def test_csr_spmv_binding_rejects_x_of_the_wrong_length():
+    """x must have exactly ncols entries (nrows for a square matrix); the check
+    runs before any buffer reaches the library."""
+    import torch
+    import paper_2412_04980_amd as hm
+    rp = torch.arange(0, 13, 3, dtype=torch.int32)          # 4 rows, 3 entries each
+    ci = torch.zeros(12, dtype=torch.int32)
+    va = torch.zeros(12, dtype=torch.complex128)
+    with pytest.raises(ValueError, match="x has 3 entries"):
+        hm.csr_spmv(rp, ci, va, torch.zeros(3, dtype=torch.complex128))
+    with pytest.raises(ValueError, match="x has 4 entries"):
+        hm.csr_spmv(rp, ci, va, torch.zeros(4, dtype=torch.complex128), ncols=6)
+
+
+def test_set_basis_cache_rejects_bad_arguments_on_the_host():
+    import paper_2412_04980_amd as hm
+    nul = ctypes.c_void_p(0)
+    assert hm._lib.hm_set_basis_cache(nul, 0.0, 0.0) == hm.HM_ERR_ARG
 
 
 def test_batch_workspace_and_argument_checks_on_the_host():
@@ -198,3 +219,27 @@ def test_wrappers_reject_buffers_on_another_device_before_any_call():
         hm.batch_solve(Batch, [near, far])
     with pytest.raises(ValueError, match="at least one member"):
         hm.create_batch(hm.default_config(9, 9, 1 / 8), [])
+
+
+def test_residual_rejects_bad_arguments_on_the_host():
+    """hm_residual checks sizes, the boundary condition, pointers, aliasing and
+    the workspace before any device call."""
+    import paper_2412_04980_amd as hm
+    lib = hm._lib
+    assert lib.hm_residual_workspace_bytes() == 2048 * 16
+    nul = ctypes.c_void_p(0)
+    a, b, c = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(12288)
+    ws = ctypes.c_void_p(1 << 20)
+    n = lib.hm_residual_workspace_bytes()
+    args = lambda nx=5, ny=5, h=0.25, bc=0, k=a, bb=b, u=c, r=nul, norms=b, w=ws, wn=n: \
+        lib.hm_residual(nx, ny, h, bc, k, bb, u, r, norms, w, wn, nul)
+    assert args(nx=2) == hm.HM_ERR_ARG
+    assert args(h=0.0) == hm.HM_ERR_ARG
+    assert args(bc=2) == hm.HM_ERR_ARG
+    assert args(k=nul) == hm.HM_ERR_ARG
+    assert args(norms=nul) == hm.HM_ERR_ARG
+    assert args(r=c) == hm.HM_ERR_ARG                      # r aliases u
+    assert args(w=nul) == hm.HM_ERR_ARG
+    assert args(w=ctypes.c_void_p((1 << 20) + 16)) == hm.HM_ERR_ARG
+    assert args(wn=n - 1) == hm.HM_ERR_NOMEM
+

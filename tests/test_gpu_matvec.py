@@ -97,11 +97,33 @@ def test_csr_spmv_general_matrix():
     va = rng.standard_normal(nnz) + 1j * rng.standard_normal(nnz)
     x = rng.standard_normal(ncols) + 1j * rng.standard_normal(ncols)
     ref = sp.csr_matrix((va, ci, rp), shape=(nrows, ncols)) @ x
-    y = hm.csr_spmv(gpu(rp), gpu(ci), gpu(va), gpu(x))
+    y = hm.csr_spmv(gpu(rp), gpu(ci), gpu(va), gpu(x), ncols=ncols)
     torch.cuda.synchronize()
     y = host(y)
     assert np.all(y[lens == 0] == 0)
     assert relerr(y, ref) <= 1e-14
+
+
+def test_csr_spmv_column_outside_gives_nan_row():
+    """An entry whose column lies outside [0, ncols) is not read from x: its row
+    becomes NaN and every other row is the product."""
+    rng = np.random.default_rng(22)
+    nrows, ncols = 300, 200
+    rp = np.arange(0, 3 * nrows + 1, 3, dtype=np.int32)
+    ci = rng.integers(0, ncols, 3 * nrows).astype(np.int32)
+    bad = [5, 123, 299]
+    for r in bad:
+        ci[3 * r + 1] = ncols + 7 * r          # past the end of x
+    va = rng.standard_normal(3 * nrows) + 1j * rng.standard_normal(3 * nrows)
+    x = rng.standard_normal(ncols) + 1j * rng.standard_normal(ncols)
+    good = np.setdiff1d(np.arange(nrows), bad)
+    ci_ok = ci.copy()
+    for r in bad:
+        ci_ok[3 * r + 1] = 0
+    ref = sp.csr_matrix((va, ci_ok, rp), shape=(nrows, ncols)) @ x
+    y = host(hm.csr_spmv(gpu(rp), gpu(ci), gpu(va), gpu(x), ncols=ncols))
+    assert np.all(np.isnan(y[bad]))
+    assert relerr(y[good], ref[good]) <= 1e-14
 
 
 def test_matvec_forms_at_4097():
@@ -147,3 +169,26 @@ def test_matvec_forms_at_16385_sampled():
     idx = torch.from_numpy(rows).to(DEV)
     assert np.max(np.abs(host(v[idx]) - ref)) <= 1e-13 * scale
     assert np.max(np.abs(host(y[idx]) - ref)) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("bc", [hm.HM_BC_SOMMERFELD, hm.HM_BC_DIRICHLET])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (67, 45), (513, 257)])
+def test_true_residual_matches_oracle(bc, nx, ny):
+    """hm_residual: r = b - A u on every row and its norm against the oracle's
+    assembled operator (both boundary conditions), with and without r."""
+    h = 1.0 / (max(nx, ny) - 1)
+    k, u = medium(nx, ny, 3 * nx + ny)
+    rng = np.random.default_rng(nx + 7 * ny)
+    b = rng.standard_normal(nx * ny) + 1j * rng.standard_normal(nx * ny)
+    bcname = op.DIRICHLET if bc == hm.HM_BC_DIRICHLET else op.SOMMERFELD
+    A = op.five_point(nx, ny, h, k, 1.0, bc=bcname)
+    ref = b - A @ u
+    kd, bd, ud = gpu(k), gpu(b), gpu(u)
+    r = torch.empty_like(bd)
+    norms = host(hm.residual(nx, ny, h, kd, bd, ud, bc=bc, r=r))
+    assert relerr(host(r), ref) <= 1e-13
+    assert abs(norms[0] - np.linalg.norm(ref)) <= 1e-12 * np.linalg.norm(ref)
+    assert abs(norms[1] - np.linalg.norm(b)) <= 1e-12 * np.linalg.norm(b)
+    again = host(hm.residual(nx, ny, h, kd, bd, ud, bc=bc))
+    assert np.array_equal(again, norms)
+
