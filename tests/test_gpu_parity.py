@@ -438,10 +438,11 @@ def test_two_problems_are_independent():
     assert not torch.equal(ua, ub)
 
 
-@pytest.mark.parametrize("levels", [4, 5])
+@pytest.mark.parametrize("levels", [4, 5, 6])
 def test_deeper_hierarchies(levels):
-    """4- and 5-level MADP (the fourth- to sixth-level stencils of Appendix A):
-    one FGMRES step on every level below 2, Krylov CSLP on levels >= 3."""
+    """4- to 6-level MADP (the fourth- to sixth-level stencils of Appendix A;
+    six levels end on 5 x 5 nodes): one FGMRES step on every level below 2,
+    Krylov CSLP on levels >= 3."""
     nx = ny = 129
     h = 1.0 / 128
     k = medium(nx, ny, 20.0, 3, spread=0.2)

@@ -127,6 +127,16 @@ def gaussian_random_velocity(n, rng, mean=2500.0, std=500.0, corr=0.05):
     return np.clip(mean + std * g, 1000.0, 4000.0).ravel()
 
 
+def smooth_field(nx, ny, seed, sigma=2.0):
+    """Complex Gaussian noise on nx x ny nodes smoothed by a Gaussian of width
+    sigma nodes (reflecting edges): a smooth seeded test vector, the kind of
+    input a coarse level receives from the deflation restriction."""
+    rng = np.random.default_rng(seed)
+    re = ndimage.gaussian_filter(rng.standard_normal((ny, nx)), sigma, mode="reflect")
+    im = ndimage.gaussian_filter(rng.standard_normal((ny, nx)), sigma, mode="reflect")
+    return (re + 1j * im).ravel()
+
+
 @dataclass
 class Request:
     rid: int
