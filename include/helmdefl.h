@@ -322,6 +322,22 @@ hm_status hm_residual(int nx, int ny, double h, int bc, const double* k_dev, con
                       const void* u_dev, void* r_dev, double* norms_dev, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * true residual as hm_residual, with the reduction's partial sums in a static
+ * device array of the library (2048 complex128 = 32 KiB per device, held
+ * until the process ends) instead of a caller workspace.  It calls no
+ * allocating routine; the first call on a device looks the array's address
+ * up once.  Every grid size fits the array (the reduction uses at most 2048
+ * partials); a size that would not is rejected with HM_ERR_ARG.  All calls on
+ * one device share the array: calls that overlap in time on one device (two
+ * streams, two host threads) race and give wrong norms, so serialise them.
+ * Each call writes every partial it reads, so nothing needs clearing.
+ * Arguments, results and errors otherwise as hm_residual. */
+hm_status hm_residual_noalloc(int nx, int ny, double h, int bc, const double* k_dev,
+                              const void* b_dev, const void* u_dev, void* r_dev,
+                              double* norms_dev, void* stream);
+
 const char* hm_status_string(hm_status s);
 const char* hm_last_error(void);
 

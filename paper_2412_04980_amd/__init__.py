@@ -52,6 +52,7 @@ EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_
             "hm_set_basis_cache", "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
             "hm_batch_workspace_bytes", "hm_create_batch", "hm_batch_solve", "hm_batch_member",
             "hm_destroy_batch", "hm_residual_workspace_bytes", "hm_residual",
+            "hm_residual_noalloc",
             "hm_status_string", "hm_last_error"]
 
 MAX_BATCH = 16
@@ -128,6 +129,7 @@ def _load():
         "hm_destroy_batch": (I, [P]),
         "hm_residual_workspace_bytes": (ctypes.c_size_t, []),
         "hm_residual": (I, [I, I, D, I, P, P, P, P, P, P, ctypes.c_size_t, P]),
+        "hm_residual_noalloc": (I, [I, I, D, I, P, P, P, P, P, P]),
         "hm_status_string": (ctypes.c_char_p, [I]),
         "hm_last_error": (ctypes.c_char_p, []),
     }
@@ -384,7 +386,7 @@ def csr_spmv(row_ptr, col_idx, vals, x, ncols=None, out=None, stream=None):
     return y
 
 
-def _residual_args(nx, ny, k, b, u, r):
+def _residual_args(nx, ny, k, b, u, r, norms):
     n = nx * ny
     _f64(k, n, "k")
     _c128(b, n, "b", k.device)
@@ -393,13 +395,17 @@ def _residual_args(nx, ny, k, b, u, r):
         _c128(r, n, "r", k.device)
         if r.data_ptr() == u.data_ptr():
             raise ValueError("r must not alias u")
-    return torch.empty(2, dtype=torch.float64, device=k.device)
+    if norms is None:
+        return torch.empty(2, dtype=torch.float64, device=k.device)
+    return _f64(norms, 2, "norms", k.device)
 
 
-def residual(nx, ny, h, k, b, u, bc=HM_BC_SOMMERFELD, r=None, workspace=None, stream=None):
-    """(||b - A u||_2, ||b||_2) on the device as a float64 tensor of 2; r, if
-    given, receives b - A u (the 5-point operator of the finest level)."""
-    norms = _residual_args(nx, ny, k, b, u, r)
+def residual(nx, ny, h, k, b, u, bc=HM_BC_SOMMERFELD, r=None, norms=None, workspace=None,
+             stream=None):
+    """(||b - A u||_2, ||b||_2) on the device as a float64 tensor of 2 (norms, if
+    given, receives them); r, if given, receives b - A u (the 5-point operator
+    of the finest level)."""
+    norms = _residual_args(nx, ny, k, b, u, r, norms)
     nbytes = _lib.hm_residual_workspace_bytes()
     if workspace is None:
         workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=k.device)
@@ -411,6 +417,17 @@ def residual(nx, ny, h, k, b, u, bc=HM_BC_SOMMERFELD, r=None, workspace=None, st
                             ctypes.c_void_p(base + off), ctypes.c_size_t(workspace.numel() - off),
                             _stream(stream)))
     return norms
+
+
+def residual_noalloc(nx, ny, h, k, b, u, bc=HM_BC_SOMMERFELD, r=None, norms=None, stream=None):
+    """As residual(), through the entry point that allocates nothing (the
+    reduction uses the library's static scratch array).  norms: an optional
+    float64 GPU tensor of 2 that receives the result (else one is made)."""
+    out = _residual_args(nx, ny, k, b, u, r, norms)
+    _check(_lib.hm_residual_noalloc(int(nx), int(ny), float(h), int(bc), _ptr(k), _ptr(b),
+                                    _ptr(u), None if r is None else _ptr(r), _ptr(out),
+                                    _stream(stream)))
+    return out
 
 
 def destroy_problem(prob):

@@ -12,6 +12,15 @@
 
 #include "kernels.hpp"
 
+#include <mutex>
+#include <vector>
+
+// Reduction partials of the entry points that take no workspace
+// (hm_residual_noalloc): one copy per device, held until the process ends.
+// Host code never passes this name to a kernel (on the host it is only a
+// stand-in); it uses the device address from hipGetSymbolAddress.
+static __device__ __align__(256) hm::c128 scratch[hm::kMaxChunks];
+
 namespace hm {
 
 namespace {
@@ -1565,6 +1574,25 @@ hipError_t launch_residual_norm(const OpDesc<double>& d, const c128* u, const do
   k_residual_norm<<<nch, NT, 0, s>>>(d, u, k, b, r, n, clen, partials);
   k_residual_final<<<1, NT, 0, s>>>(partials, nch, norms);
   return hipGetLastError();
+}
+
+hipError_t scratch_address(c128** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static std::vector<c128*> addr;                // by device ordinal
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((size_t)dev >= addr.size()) addr.resize((size_t)dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = (c128*)p;
+  }
+  *ptr = addr[dev];
+  *bytes = sizeof(scratch);
+  return hipSuccess;
 }
 
 hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s) {

@@ -207,6 +207,9 @@ hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipS
 hipError_t launch_residual_norm(const OpDesc<double>& d, const c128* u, const double* k,
                                 const c128* b, c128* r, c128* partials, double* norms,
                                 hipStream_t s);
+// Device address and size of the library's static scratch array on the
+// current device (looked up once per device with hipGetSymbolAddress).
+hipError_t scratch_address(c128** ptr, size_t* bytes);
 // Validation of the wavenumber field: out[0] = number of entries that are not
 // finite or negative (as a double in the real part).
 hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipStream_t s);

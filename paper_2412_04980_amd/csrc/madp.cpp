@@ -1762,6 +1762,24 @@ hm_status hm_residual(int nx, int ny, double h, int bc, const double* k_dev, con
                          stream);
 }
 
+hm_status hm_residual_noalloc(int nx, int ny, double h, int bc, const double* k_dev,
+                              const void* b_dev, const void* u_dev, void* r_dev,
+                              double* norms_dev, void* stream) {
+  if (!residual_args_ok(nx, ny, h, bc, k_dev, b_dev, u_dev, r_dev, norms_dev)) return HM_ERR_ARG;
+  return guard([&]() -> hm_status {
+    c128* partials = nullptr;
+    size_t cap = 0;
+    HM_CHECK(scratch_address(&partials, &cap));
+    const size_t need = sizeof(c128) * (size_t)reduction_chunks((size_t)nx * (size_t)ny);
+    if (need > cap) {
+      g_last_error = "residual_noalloc: the reduction needs " + std::to_string(need) +
+                     " bytes of scratch, the static array holds " + std::to_string(cap);
+      return HM_ERR_ARG;
+    }
+    return residual_launch(nx, ny, h, bc, k_dev, b_dev, u_dev, r_dev, norms_dev, partials, stream);
+  });
+}
+
 hm_status hm_set_timing(hm_problem* p, unsigned mask, int every) {
   if (!p || every < 1) return HM_ERR_ARG;
   return guard([&]() -> hm_status {
