@@ -6,6 +6,7 @@
 // All grid arrays are row-major with x fastest; complex values interleaved.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <type_traits>
@@ -430,6 +431,175 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
   }
 }
 
+// Persistent form of the wide stencil for Sommerfeld boundaries.  A grid of
+// resident blocks walks the tiles (each XCD a contiguous range of them, as in
+// k_wide_tiled), and each block loads the next tile's grid values into
+// registers while it evaluates the current tile from LDS: the halo loads
+// overlap the arithmetic, and no partial second round of blocks is left at
+// the end.  Tile values are read at clamped positions, so a point one step
+// outside the grid in exactly one direction holds its boundary node's u_b and
+// k_b; its Sommerfeld ghost u_m + i 2H k_b u_b is completed once the mirror
+// u_m is in LDS.  The arithmetic of an output is that of k_wide_tiled.
+template <typename T, int R, int MODE>
+__global__ void __launch_bounds__(NT) k_wide_persist(OpDesc<T> d, const cx<T>* __restrict__ u,
+                                                     const T* __restrict__ k,
+                                                     const cx<T>* __restrict__ b,
+                                                     cx<T>* __restrict__ out, T omega,
+                                                     const c128* __restrict__ scal,
+                                                     cx<T>* __restrict__ vout, Batch z) {
+  constexpr int W = 2 * R + 1;
+  constexpr int SX = WT_X + 2 * R;
+  constexpr int SY = WT_Y + 2 * R;
+  constexpr int NP = SX * SY;
+  constexpr int PTS = (NP + NT - 1) / NT;      // tile points per thread
+  __shared__ cx<T> su[SY][SX];
+  __shared__ T sk[SY][SX];
+  HM_MEMBER(u); HM_MEMBER(k); HM_MEMBER(b); HM_MEMBER(out); HM_MEMBER(scal); HM_MEMBER(vout);
+  if (z.use_omega) omega = (T)z.omega[blockIdx.z];
+  const int nx = d.nx, ny = d.ny;
+  const int ntx = (nx + WT_X - 1) / WT_X, nty = (ny + WT_Y - 1) / WT_Y;
+  const int nt = ntx * nty;
+  const int per = (nt + 7) / 8;
+  const int nloc = (int)(gridDim.x >> 3);      // blocks per XCD
+  const int t_lo = (int)(blockIdx.x & 7) * per;
+  const int t_hi = min(t_lo + per, nt);
+  int tile = t_lo + (int)(blockIdx.x >> 3);
+  if (tile >= t_hi) return;
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  T sc = T(1);
+  if constexpr (MODE == ST_SCALED) sc = (T)(1.0 / scal[0].re);
+  cx<T> ru[PTS];
+  T rk[PTS];
+  auto fetch = [&](int t) {
+    const int x0 = (t % ntx) * WT_X - R, y0 = (t / ntx) * WT_Y - R;
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int idx = min(tid + q * NT, NP - 1);
+      const int r = idx / SX, c = idx - r * SX;
+      const int xc = min(max(x0 + c, 0), nx - 1), yc = min(max(y0 + r, 0), ny - 1);
+      const size_t p = (size_t)yc * nx + xc;
+      ru[q] = u[p];
+      rk[q] = k[p];
+    }
+  };
+  fetch(tile);
+  for (;;) {
+    const int x0 = (tile % ntx) * WT_X, y0 = (tile / ntx) * WT_Y;
+    const bool edge = x0 < R || y0 < R || x0 + WT_X + R > nx || y0 + WT_Y + R > ny;
+    __syncthreads();                             // the previous tile is no longer read
+#pragma unroll
+    for (int q = 0; q < PTS; ++q) {
+      const int idx = tid + q * NT;
+      if (idx < NP) {
+        const int r = idx / SX, c = idx - r * SX;
+        const int x = x0 - R + c, y = y0 - R + r;
+        const bool xin = (unsigned)x < (unsigned)nx, yin = (unsigned)y < (unsigned)ny;
+        cx<T> uv = mk(T(0), T(0));
+        T k2 = T(0);
+        if (xin && yin) {
+          uv = ru[q];
+          k2 = rk[q] * rk[q];
+        } else if ((yin && (x == -1 || x == nx)) || (xin && (y == -1 || y == ny))) {
+          const T c2 = d.two_H * rk[q];          // i 2H k_b u_b; the mirror is added below
+          uv = mk(-c2 * ru[q].im, c2 * ru[q].re);
+        }
+        // the ghost values are linear in u, so scaling the extended tile scales u
+        if constexpr (MODE == ST_SCALED) uv = sc * uv;
+        su[r][c] = uv;
+        sk[r][c] = k2;
+      }
+    }
+    if (edge) {                                  // uniform over the block
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PTS; ++q) {
+        const int idx = tid + q * NT;
+        if (idx < NP) {
+          const int r = idx / SX, c = idx - r * SX;
+          const int x = x0 - R + c, y = y0 - R + r;
+          const bool xin = (unsigned)x < (unsigned)nx, yin = (unsigned)y < (unsigned)ny;
+          if (yin && (x == -1 || x == nx)) su[r][c] = su[r][x < 0 ? c + 2 : c - 2] + su[r][c];
+          else if (xin && (y == -1 || y == ny)) su[r][c] = su[y < 0 ? r + 2 : r - 2][c] + su[r][c];
+        }
+      }
+    }
+    // the next tile's loads (this tile again for the last one: cached) are
+    // in flight during the arithmetic below
+    const int next = tile + nloc < t_hi ? tile + nloc : tile;
+    fetch(next);
+    __syncthreads();
+    const int tx = threadIdx.x;
+    const int x = x0 + tx;
+    const int ly0 = threadIdx.y * WT_R;
+    T lre[WT_R], lim[WT_R], kre[WT_R], kim[WT_R];
+#pragma unroll
+    for (int o = 0; o < WT_R; ++o) { lre[o] = lim[o] = kre[o] = kim[o] = T(0); }
+#pragma unroll 1
+    for (int rr = 0; rr < WT_R + 2 * R; ++rr) {
+      T tur = 0, tui = 0, mur = 0, mui = 0, mwr = 0, mwi = 0;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        const cx<T> uv = su[ly0 + rr][tx + a];
+        const T k2 = sk[ly0 + rr][tx + a];
+        const T ta = d.t1[a], ma = d.m1[a];
+        tur += ta * uv.re; tui += ta * uv.im;
+        mur += ma * uv.re; mui += ma * uv.im;
+        const T mk2 = ma * k2;
+        mwr += mk2 * uv.re; mwi += mk2 * uv.im;
+      }
+#pragma unroll
+      for (int o = 0; o < WT_R; ++o) {
+        const int bb = rr - o;
+        if (bb >= 0 && bb < W) {
+          const T mb = d.m1[bb], tb = d.t1[bb];
+          lre[o] += mb * tur + tb * mur;
+          lim[o] += mb * tui + tb * mui;
+          kre[o] += mb * mwr;
+          kim[o] += mb * mwi;
+        }
+      }
+    }
+    if (x < nx) {
+#pragma unroll
+      for (int o = 0; o < WT_R; ++o) {
+        const int y = y0 + ly0 + o;
+        if (y >= ny) break;
+        const size_t p = (size_t)y * nx + x;
+        const int cy = ly0 + o + R, cxl = tx + R;
+        const cx<T> uc = su[cy][cxl];
+        cx<T> au;
+        const bool bnd = x == 0 || y == 0 || x == nx - 1 || y == ny - 1;
+        if (bnd) {
+          const T k2 = sk[cy][cxl];
+          cx<T> s = mk(T(4) * uc.re, T(4) * uc.im);
+          s = s - su[cy][cxl - 1];
+          s = s - su[cy][cxl + 1];
+          s = s - su[cy - 1][cxl];
+          s = s - su[cy + 1][cxl];
+          const cx<T> sk2 = mk(d.sig_re * k2, d.sig_im * k2) * uc;
+          au = d.scale * (d.inv_H2 * s - sk2);
+        } else {
+          au = mk(lre[o] - (d.sig_re * kre[o] - d.sig_im * kim[o]),
+                  lim[o] - (d.sig_re * kim[o] + d.sig_im * kre[o]));
+        }
+        if constexpr (MODE == ST_APPLY) {
+          out[p] = au;
+        } else if constexpr (MODE == ST_SCALED) {
+          out[p] = au;
+          vout[p] = uc;
+        } else if constexpr (MODE == ST_RESID) {
+          out[p] = b[p] - au;
+        } else {
+          const cx<T> dg = bnd ? five_point_diag(d, k, x, y) : wide_diag<T, R>(d, k, x, y);
+          out[p] = uc + omega * cdiv(b[p] - au, dg);
+        }
+      }
+    }
+    if (next == tile) break;
+    tile = next;
+  }
+}
+
 template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_jacobi0(OpDesc<T> d, const T* __restrict__ k,
                                                 const cx<T>* __restrict__ b, cx<T>* __restrict__ x_out,
@@ -461,20 +631,30 @@ __device__ __forceinline__ bool on_bnd(int x, int y, int nx, int ny) {
 // ---- row-streaming transfers ------------------------------------------------
 // One-thread-per-output transfers read their 3x3 / 5x5 neighbourhoods with
 // stride-2 loads and stay far below the HBM rate.  These versions stream rows:
-// a block is four waves side by side, each owning 64 coarse columns, and walks
-// down TR coarse rows.  Every lane loads its own fine pair (2I, 2I+1) or coarse
-// value with coalesced loads, takes its neighbours' values across lanes
-// (lanes 0 and 63 load the values beyond the wave), filters horizontally and
-// combines rows vertically in registers, with the next rows' loads issued
-// before the current rows are processed.  Summation order (horizontal, then
-// vertical) is that of the separable weights.  Blocks go in the XCD-aware
-// tile order.
-constexpr int TR = 8;               // coarse rows per block
-constexpr int TCOLS = 256;          // coarse columns per block (4 waves x 64)
+// a block is four waves side by side walking down TR coarse rows.  Lane l of a
+// wave stands for coarse column I = I0 + l - 1; it loads its own fine pair
+// (2I, 2I+1) (restriction) or coarse value I (prolongation) with coalesced
+// loads and takes its neighbours' values across lanes.  Lanes 0 and 63 carry
+// only the halo, so a wave produces the TW = 62 columns of lanes 1..62.  Every
+// load reads a clamped address inside the grid and is masked afterwards (zero
+// outside the grid, and on the boundary for Dirichlet transfers): with no
+// branch around a load, the next rows' loads stay in flight while the current
+// rows are filtered.  Summation order (horizontal, then vertical) is that of
+// the separable weights.  Blocks go in the XCD-aware tile order.
+constexpr int TW = 62;              // coarse columns per wave (lanes 1..62)
+constexpr int TCOLS = 4 * TW;       // coarse columns per block
 
-inline unsigned sep_blocks(int nxc, int nyc) {
-  const size_t nt = (size_t)((nxc + TCOLS - 1) / TCOLS) * ((nyc + TR - 1) / TR);
+// blocks of a transfer with TRB coarse rows per block (8 per XCD turn)
+inline unsigned sep_blocks(int nxc, int nyc, int trb) {
+  const size_t nt = (size_t)((nxc + TCOLS - 1) / TCOLS) * ((nyc + trb - 1) / trb);
   return (unsigned)(8 * ((nt + 7) / 8));
+}
+// coarse rows per block: 8, or fewer on small grids so that the launch still
+// has about four blocks per compute unit
+inline int sep_rows(int nxc, int nyc) {
+  int trb = 8;
+  while (trb > 2 && sep_blocks(nxc, nyc, trb) < 1024) trb /= 2;
+  return trb;
 }
 
 template <typename T>
@@ -482,46 +662,40 @@ __device__ __forceinline__ cx<T> lane_val(const cx<T>& v, int src) {
   return mk(__shfl(v.re, src, 64), __shfl(v.im, src, 64));
 }
 
-// fine row values owned by one lane: its pair (2I, 2I+1) and, for lane 0, the
-// pair (2I-2, 2I-1) before the wave; for lane 63, the value 2I+2 after it
+// Value at (x, y) of an nx x ny field, zero unless lo <= x < nx - lo and
+// lo <= y < ny - lo; the load itself always reads a node of the grid.
+template <typename T>
+__device__ __forceinline__ cx<T> clamped_load(const cx<T>* __restrict__ f, int x, int y, int nx,
+                                              int ny, int lo) {
+  const int xc = min(max(x, 0), nx - 1), yc = min(max(y, 0), ny - 1);
+  const cx<T> v = f[(size_t)yc * nx + xc];
+  const bool in = x >= lo && x < nx - lo && y >= lo && y < ny - lo;
+  return in ? v : mk(T(0), T(0));
+}
+
+// fine row values owned by one lane: its pair (2I, 2I+1)
 template <typename T>
 struct FinePair {
-  cx<T> a, b, ea, eb;
+  cx<T> a, b;
 };
 
 template <typename T>
-__device__ __forceinline__ cx<T> masked_load(const cx<T>* __restrict__ f, int x, int y, int nx,
-                                             int ny, int lo) {
-  if (x >= lo && x < nx - lo && y >= lo && y < ny - lo) return f[(size_t)y * nx + x];
-  return mk(T(0), T(0));
-}
-
-template <typename T>
 __device__ __forceinline__ FinePair<T> load_fine_pair(const cx<T>* __restrict__ f, int I, int y,
-                                                      int nxf, int nyf, int lo, int lane) {
+                                                      int nxf, int nyf, int lo) {
   FinePair<T> r;
-  r.a = masked_load(f, 2 * I, y, nxf, nyf, lo);
-  r.b = masked_load(f, 2 * I + 1, y, nxf, nyf, lo);
-  r.ea = mk(T(0), T(0));
-  r.eb = mk(T(0), T(0));
-  if (lane == 0) {
-    r.ea = masked_load(f, 2 * I - 2, y, nxf, nyf, lo);
-    r.eb = masked_load(f, 2 * I - 1, y, nxf, nyf, lo);
-  } else if (lane == 63) {
-    r.ea = masked_load(f, 2 * I + 2, y, nxf, nyf, lo);
-  }
+  r.a = clamped_load(f, 2 * I, y, nxf, nyf, lo);
+  r.b = clamped_load(f, 2 * I + 1, y, nxf, nyf, lo);
   return r;
 }
 
-// horizontal filter of one fine row at coarse column I:
+// horizontal filter of one fine row at coarse column I (valid on lanes 1..62):
 //   H = 2: (f[2I-2] + 4 f[2I-1] + 6 f[2I] + 4 f[2I+1] + f[2I+2]) / 8
 //   H = 1: (f[2I-1] + 2 f[2I] + f[2I+1]) / 4
 template <typename Ti, typename To, int H>
 __device__ __forceinline__ cx<To> hfilter(const FinePair<Ti>& r, int lane) {
-  cx<Ti> pa = lane_val(r.a, lane - 1), pb = lane_val(r.b, lane - 1), na = lane_val(r.a, lane + 1);
-  if (lane == 0) { pa = r.ea; pb = r.eb; }
-  if (lane == 63) na = r.ea;
+  const cx<Ti> pb = lane_val(r.b, lane - 1);
   if constexpr (H == 2) {
+    const cx<Ti> pa = lane_val(r.a, lane - 1), na = lane_val(r.a, lane + 1);
     return mk(To(0.125) * (To)pa.re + To(0.5) * (To)pb.re + To(0.75) * (To)r.a.re +
                   To(0.5) * (To)r.b.re + To(0.125) * (To)na.re,
               To(0.125) * (To)pa.im + To(0.5) * (To)pb.im + To(0.75) * (To)r.a.im +
@@ -534,7 +708,7 @@ __device__ __forceinline__ cx<To> hfilter(const FinePair<Ti>& r, int lane) {
 
 // Restriction fine -> coarse: H = 2 is Z^T (p = [1 4 6 4 1]/8 per dimension),
 // H = 1 full weighting ([1 2 1]/4 per dimension).
-template <typename Ti, typename To, int H>
+template <typename Ti, typename To, int H, int TR>
 __global__ void __launch_bounds__(NT) k_restrict_rows(const cx<Ti>* __restrict__ f, int nxf, int nyf,
                                                       cx<To>* __restrict__ c, int nxc, int nyc,
                                                       int dir, Batch z) {
@@ -542,7 +716,8 @@ __global__ void __launch_bounds__(NT) k_restrict_rows(const cx<Ti>* __restrict__
   if (!xcd_tile((nxc + TCOLS - 1) / TCOLS, (nyc + TR - 1) / TR, tx, ty)) return;
   HM_MEMBER(f); HM_MEMBER(c);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int I = tx * TCOLS + w * 64 + lane;
+  const int I = tx * TCOLS + w * TW + lane - 1;
+  const bool owner = lane >= 1 && lane <= TW && I < nxc;
   const int J0 = ty * TR;
   const int lo = dir ? 1 : 0;
   const To vw[5] = {To(0.125), To(0.5), To(0.75), To(0.5), To(0.125)};
@@ -551,16 +726,17 @@ __global__ void __launch_bounds__(NT) k_restrict_rows(const cx<Ti>* __restrict__
   cx<To> win[2 * H + 1];
 #pragma unroll
   for (int t = 0; t < 2 * H - 1; ++t)            // rows 2 J0 - H .. 2 J0 + H - 2
-    win[t + 2] = hfilter<Ti, To, H>(load_fine_pair(f, I, 2 * J0 - H + t, nxf, nyf, lo, lane), lane);
-  FinePair<Ti> cur0 = load_fine_pair(f, I, 2 * J0 + H - 1, nxf, nyf, lo, lane);
-  FinePair<Ti> cur1 = load_fine_pair(f, I, 2 * J0 + H, nxf, nyf, lo, lane);
-#pragma unroll 1
+    win[t + 2] = hfilter<Ti, To, H>(load_fine_pair(f, I, 2 * J0 - H + t, nxf, nyf, lo), lane);
+  FinePair<Ti> cur0 = load_fine_pair(f, I, 2 * J0 + H - 1, nxf, nyf, lo);
+  FinePair<Ti> cur1 = load_fine_pair(f, I, 2 * J0 + H, nxf, nyf, lo);
+#pragma unroll
   for (int q = 0; q < TR; ++q) {
     const int J = J0 + q;
+    if (J >= nyc) break;                         // uniform over the block
     FinePair<Ti> nxt0 = cur0, nxt1 = cur1;
     if (q + 1 < TR) {                            // next rows in flight
-      nxt0 = load_fine_pair(f, I, 2 * J + H + 1, nxf, nyf, lo, lane);
-      nxt1 = load_fine_pair(f, I, 2 * J + H + 2, nxf, nyf, lo, lane);
+      nxt0 = load_fine_pair(f, I, 2 * J + H + 1, nxf, nyf, lo);
+      nxt1 = load_fine_pair(f, I, 2 * J + H + 2, nxf, nyf, lo);
     }
 #pragma unroll
     for (int t = 0; t < 2 * H - 1; ++t) win[t] = win[t + 2];
@@ -573,7 +749,7 @@ __global__ void __launch_bounds__(NT) k_restrict_rows(const cx<Ti>* __restrict__
       re += wt * win[t].re;
       im += wt * win[t].im;
     }
-    if (I < nxc && J < nyc) {
+    if (owner) {
       cx<To> out = mk(re, im);
       if (dir && on_bnd(I, J, nxc, nyc)) out = mk(To(0), To(0));
       c[(size_t)J * nxc + I] = out;
@@ -585,24 +761,13 @@ __global__ void __launch_bounds__(NT) k_restrict_rows(const cx<Ti>* __restrict__
 
 // Prolongation coarse -> fine.  ZDEF: deflation interpolation Z written to f
 // (fine 2I: (c[I-1] + 6 c[I] + c[I+1]) / 8, fine 2I+1: (c[I] + c[I+1]) / 2 per
-// dimension); otherwise bilinear interpolation added to f.  Each lane
-// produces the fine pair (2I, 2I+1) of its coarse column I.
-template <typename T>
-__device__ __forceinline__ void load_coarse(const cx<T>* __restrict__ c, int I, int J, int nxc,
-                                            int nyc, int lo, int lane, cx<T>& own, cx<T>& edge) {
-  own = masked_load(c, I, J, nxc, nyc, lo);
-  edge = mk(T(0), T(0));
-  if (lane == 0) edge = masked_load(c, I - 1, J, nxc, nyc, lo);
-  else if (lane == 63) edge = masked_load(c, I + 1, J, nxc, nyc, lo);
-}
-
+// dimension); otherwise bilinear interpolation added to f.  Lanes 1..62
+// produce the fine pair (2I, 2I+1) of their coarse column I.
 template <typename Ti, typename To, bool ZDEF>
-__device__ __forceinline__ void hinterp(const cx<Ti>& own, const cx<Ti>& edge, int lane,
-                                        cx<To>& ev, cx<To>& od) {
-  cx<Ti> pv = lane_val(own, lane - 1), nv = lane_val(own, lane + 1);
-  if (lane == 0) pv = edge;
-  if (lane == 63) nv = edge;
+__device__ __forceinline__ void hinterp(const cx<Ti>& own, int lane, cx<To>& ev, cx<To>& od) {
+  const cx<Ti> nv = lane_val(own, lane + 1);
   if constexpr (ZDEF) {
+    const cx<Ti> pv = lane_val(own, lane - 1);
     ev = mk(To(0.125) * (To)pv.re + To(0.75) * (To)own.re + To(0.125) * (To)nv.re,
             To(0.125) * (To)pv.im + To(0.75) * (To)own.im + To(0.125) * (To)nv.im);
   } else {
@@ -611,7 +776,23 @@ __device__ __forceinline__ void hinterp(const cx<Ti>& own, const cx<Ti>& edge, i
   od = mk(To(0.5) * (To)own.re + To(0.5) * (To)nv.re, To(0.5) * (To)own.im + To(0.5) * (To)nv.im);
 }
 
-template <typename Ti, typename To, bool ZDEF>
+// the four fine values (rows 2J, 2J+1; columns 2I, 2I+1) a lane updates, read
+// ahead of the bilinear correction (addresses clamped into the grid; values
+// off the grid are never stored back)
+template <typename T>
+__device__ __forceinline__ void load_fine_quad(const cx<T>* __restrict__ f, int I, int J, int nxf,
+                                               int nyf, cx<T> (&q)[2][2]) {
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int x = min(max(2 * I + side, 0), nxf - 1);
+      const int y = min(2 * J + par, nyf - 1);
+      q[par][side] = f[(size_t)y * nxf + x];
+    }
+}
+
+template <typename Ti, typename To, bool ZDEF, int TR>
 __global__ void __launch_bounds__(NT) k_prolong_rows(const cx<Ti>* __restrict__ c, int nxc, int nyc,
                                                      cx<To>* __restrict__ f, int nxf, int nyf,
                                                      int dir, Batch z) {
@@ -619,61 +800,78 @@ __global__ void __launch_bounds__(NT) k_prolong_rows(const cx<Ti>* __restrict__ 
   if (!xcd_tile((nxc + TCOLS - 1) / TCOLS, (nyc + TR - 1) / TR, tx, ty)) return;
   HM_MEMBER(c); HM_MEMBER(f);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int I = tx * TCOLS + w * 64 + lane;
+  const int I = tx * TCOLS + w * TW + lane - 1;
+  const bool owner = lane >= 1 && lane <= TW && I < nxc;
   const int J0 = ty * TR;
   const int lo = dir ? 1 : 0;
+  // Z: every coarse row of the block (J0 - 1 .. J0 + TR) is loaded before the
+  // first store, so no wait in the row loop is held up by the stores; the
+  // bilinear correction reads fine values too and streams rows instead
+  constexpr int NPRE = ZDEF ? TR + 2 : 3;
+  cx<Ti> crow[NPRE];
+#pragma unroll
+  for (int r = 0; r < NPRE; ++r) crow[r] = clamped_load(c, I, J0 - 1 + r, nxc, nyc, lo);
   // horizontal interpolants of coarse rows J-1, J, J+1: [row][even / odd]
   cx<To> hv[3][2];
-  cx<Ti> own, edge;
-  load_coarse(c, I, J0 - 1, nxc, nyc, lo, lane, own, edge);
-  hinterp<Ti, To, ZDEF>(own, edge, lane, hv[1][0], hv[1][1]);
-  load_coarse(c, I, J0, nxc, nyc, lo, lane, own, edge);
-  hinterp<Ti, To, ZDEF>(own, edge, lane, hv[2][0], hv[2][1]);
-  cx<Ti> cown, cedge;
-  load_coarse(c, I, J0 + 1, nxc, nyc, lo, lane, cown, cedge);
-#pragma unroll 1
+  hinterp<Ti, To, ZDEF>(crow[0], lane, hv[1][0], hv[1][1]);
+  hinterp<Ti, To, ZDEF>(crow[1], lane, hv[2][0], hv[2][1]);
+  cx<Ti> cur = crow[2];
+  cx<To> fcur[2][2];
+  if constexpr (!ZDEF) load_fine_quad(f, I, J0, nxf, nyf, fcur);
+#pragma unroll
   for (int q = 0; q < TR; ++q) {
     const int J = J0 + q;
-    cx<Ti> nown = cown, nedge = cedge;
-    if (q + 1 < TR) load_coarse(c, I, J + 2, nxc, nyc, lo, lane, nown, nedge);
+    if (J >= nyc) break;                         // uniform over the block
+    cx<Ti> nxt = cur;
+    cx<To> fnxt[2][2];
+    if (q + 1 < TR) {
+      if constexpr (ZDEF) {
+        nxt = crow[q + 3 < NPRE ? q + 3 : NPRE - 1];
+      } else {                                   // next rows in flight
+        nxt = clamped_load(c, I, J + 2, nxc, nyc, lo);
+        load_fine_quad(f, I, J + 1, nxf, nyf, fnxt);
+      }
+    }
     hv[0][0] = hv[1][0]; hv[0][1] = hv[1][1];
     hv[1][0] = hv[2][0]; hv[1][1] = hv[2][1];
-    hinterp<Ti, To, ZDEF>(cown, cedge, lane, hv[2][0], hv[2][1]);
-    if (I < nxc && J < nyc) {
+    hinterp<Ti, To, ZDEF>(cur, lane, hv[2][0], hv[2][1]);
 #pragma unroll
-      for (int par = 0; par < 2; ++par) {        // fine rows 2J, 2J+1
-        const int y = 2 * J + par;
-        if (y >= nyf) break;
+    for (int par = 0; par < 2; ++par) {          // fine rows 2J, 2J+1
+      const int y = 2 * J + par;
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {   // fine columns 2I, 2I+1
-          const int x = 2 * I + side;
-          if (x >= nxf) break;
-          cx<To> v;
-          if (par == 0) {
-            if constexpr (ZDEF) {
-              v = mk(To(0.125) * hv[0][side].re + To(0.75) * hv[1][side].re +
-                         To(0.125) * hv[2][side].re,
-                     To(0.125) * hv[0][side].im + To(0.75) * hv[1][side].im +
-                         To(0.125) * hv[2][side].im);
-            } else {
-              v = hv[1][side];
-            }
-          } else {
-            v = mk(To(0.5) * hv[1][side].re + To(0.5) * hv[2][side].re,
-                   To(0.5) * hv[1][side].im + To(0.5) * hv[2][side].im);
-          }
-          const size_t p = (size_t)y * nxf + x;
-          const bool fb = dir && on_bnd(x, y, nxf, nyf);
+      for (int side = 0; side < 2; ++side) {     // fine columns 2I, 2I+1
+        const int x = 2 * I + side;
+        cx<To> v;
+        if (par == 0) {
           if constexpr (ZDEF) {
-            f[p] = fb ? mk(To(0), To(0)) : v;
+            v = mk(To(0.125) * hv[0][side].re + To(0.75) * hv[1][side].re +
+                       To(0.125) * hv[2][side].re,
+                   To(0.125) * hv[0][side].im + To(0.75) * hv[1][side].im +
+                       To(0.125) * hv[2][side].im);
           } else {
-            if (!fb) f[p] = f[p] + v;
+            v = hv[1][side];
           }
+        } else {
+          v = mk(To(0.5) * hv[1][side].re + To(0.5) * hv[2][side].re,
+                 To(0.5) * hv[1][side].im + To(0.5) * hv[2][side].im);
+        }
+        if (!owner || x >= nxf || y >= nyf) continue;
+        const size_t p = (size_t)y * nxf + x;
+        const bool fb = dir && on_bnd(x, y, nxf, nyf);
+        if constexpr (ZDEF) {
+          f[p] = fb ? mk(To(0), To(0)) : v;
+        } else {
+          if (!fb) f[p] = fcur[par][side] + v;
         }
       }
     }
-    cown = nown;
-    cedge = nedge;
+    cur = nxt;
+    if constexpr (!ZDEF) {
+#pragma unroll
+      for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) fcur[par][side] = fnxt[par][side];
+    }
   }
 }
 
@@ -1275,6 +1473,27 @@ static unsigned wide_blocks(int nx, int ny) {
   return (unsigned)(8 * ((nt + 7) / 8));
 }
 
+// blocks of the persistent wide stencil: the blocks that fit on the device at
+// once (shared by the members of a batch), 8 per round-robin turn over the
+// XCDs, and no more per XCD than its range has tiles
+template <typename T, int R, int MODE>
+static unsigned persist_blocks(int nx, int ny, const Batch& z) {
+  static int resident = 0;                     // per kernel instance; same value on every call
+  if (resident == 0) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wide_persist<T, R, MODE>, NT, 0) !=
+            hipSuccess)
+      return 0;
+    resident = std::max(8, per_cu * ncu);
+  }
+  const int nt = ((nx + WT_X - 1) / WT_X) * ((ny + WT_Y - 1) / WT_Y);
+  const int per = (nt + 7) / 8;
+  const int nloc = std::max(1, std::min(per, resident / 8 / std::max(1, z.n)));
+  return (unsigned)(8 * nloc);
+}
+
 template <typename T>
 hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T* k, const cx<T>* b,
                           cx<T>* out, T omega, hipStream_t s, const Batch& z) {
@@ -1283,7 +1502,12 @@ hipError_t launch_stencil(const OpDesc<T>& d, int mode, const cx<T>* u, const T*
 #define HM_ST(R, M)                                                                           \
   if constexpr (R == 1) k_five_point<T, M><<<g, blk, 0, s>>>(d, u, k, b, out, omega, nullptr,    \
                                                              nullptr, z);                      \
-  else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega, nullptr, nullptr, z)
+  else if (d.bc == 0) {                                                                         \
+    const unsigned nb = persist_blocks<T, R, M>(d.nx, d.ny, z);                                 \
+    if (nb == 0) return hipErrorInvalidValue;                                                   \
+    k_wide_persist<T, R, M><<<zgrid(nb, z), blk, 0, s>>>(d, u, k, b, out, omega, nullptr,       \
+                                                         nullptr, z);                           \
+  } else k_wide_tiled<T, R, M><<<gw, blk, 0, s>>>(d, u, k, b, out, omega, nullptr, nullptr, z)
 #define HM_STR(R)                              \
   if (mode == ST_APPLY) HM_ST(R, ST_APPLY);    \
   else if (mode == ST_RESID) HM_ST(R, ST_RESID); \
@@ -1304,6 +1528,12 @@ hipError_t launch_stencil_scaled(const OpDesc<T>& d, const cx<T>* u, const T* k,
   const dim3 gw = zgrid(wide_blocks(d.nx, d.ny), z);
   if (d.R == 1)
     k_five_point<T, ST_SCALED><<<g, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout, z);
+  else if (d.R == 2 && d.bc == 0)
+    k_wide_persist<T, 2, ST_SCALED><<<zgrid(persist_blocks<T, 2, ST_SCALED>(d.nx, d.ny, z), z),
+                                      blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout, z);
+  else if (d.R == 3 && d.bc == 0)
+    k_wide_persist<T, 3, ST_SCALED><<<zgrid(persist_blocks<T, 3, ST_SCALED>(d.nx, d.ny, z), z),
+                                      blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout, z);
   else if (d.R == 2)
     k_wide_tiled<T, 2, ST_SCALED><<<gw, blk, 0, s>>>(d, u, k, nullptr, out, T(0), scal, vout, z);
   else if (d.R == 3)
@@ -1324,12 +1554,22 @@ hipError_t launch_jacobi0(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>*
   return hipGetLastError();
 }
 
+// a transfer kernel K<ARGS..., TRB> with the rows per block chosen for the grid
+#define HM_SEP_UNPACK(...) __VA_ARGS__
+#define HM_SEP_LAUNCH(K, TARGS, ...)                                                           \
+  do {                                                                                          \
+    const int trb_ = sep_rows(nxc, nyc);                                                        \
+    const dim3 g_ = zgrid(sep_blocks(nxc, nyc, trb_), z);                                       \
+    if (trb_ == 8) K<HM_SEP_UNPACK TARGS, 8><<<g_, NT, 0, s>>>(__VA_ARGS__);                    \
+    else if (trb_ == 4) K<HM_SEP_UNPACK TARGS, 4><<<g_, NT, 0, s>>>(__VA_ARGS__);               \
+    else K<HM_SEP_UNPACK TARGS, 2><<<g_, NT, 0, s>>>(__VA_ARGS__);                              \
+  } while (0)
+
 template <typename Ti, typename To>
 hipError_t launch_restrict_z(const cx<Ti>* f, int nxf, int nyf, cx<To>* c, int dir,
                              hipStream_t s, const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_restrict_rows<Ti, To, 2><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(f, nxf, nyf, c, nxc,
-                                                                           nyc, dir, z);
+  HM_SEP_LAUNCH(k_restrict_rows, (Ti, To, 2), f, nxf, nyf, c, nxc, nyc, dir, z);
   return hipGetLastError();
 }
 
@@ -1337,8 +1577,7 @@ template <typename Ti, typename To>
 hipError_t launch_prolong_z(const cx<Ti>* c, int nxf, int nyf, cx<To>* f, int dir,
                             hipStream_t s, const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_prolong_rows<Ti, To, true><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(c, nxc, nyc, f, nxf,
-                                                                             nyf, dir, z);
+  HM_SEP_LAUNCH(k_prolong_rows, (Ti, To, true), c, nxc, nyc, f, nxf, nyf, dir, z);
   return hipGetLastError();
 }
 
@@ -1346,8 +1585,7 @@ template <typename T>
 hipError_t launch_restrict_fw(const cx<T>* f, int nxf, int nyf, cx<T>* c, int dir, hipStream_t s,
                               const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_restrict_rows<T, T, 1><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(f, nxf, nyf, c, nxc, nyc,
-                                                                         dir, z);
+  HM_SEP_LAUNCH(k_restrict_rows, (T, T, 1), f, nxf, nyf, c, nxc, nyc, dir, z);
   return hipGetLastError();
 }
 
@@ -1355,8 +1593,7 @@ template <typename T>
 hipError_t launch_prolong_bilinear_add(const cx<T>* c, int nxf, int nyf, cx<T>* f, int dir,
                                        hipStream_t s, const Batch& z) {
   const int nxc = (nxf - 1) / 2 + 1, nyc = (nyf - 1) / 2 + 1;
-  k_prolong_rows<T, T, false><<<zgrid(sep_blocks(nxc, nyc), z), NT, 0, s>>>(c, nxc, nyc, f, nxf,
-                                                                            nyf, dir, z);
+  HM_SEP_LAUNCH(k_prolong_rows, (T, T, false), c, nxc, nyc, f, nxf, nyf, dir, z);
   return hipGetLastError();
 }
 
