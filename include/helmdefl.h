@@ -233,6 +233,17 @@ hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes,
  * problem. */
 hm_status hm_set_basis_cache(hm_problem* p, double basis_bytes, double recent_bytes);
 
+/* Device-resident Krylov solves on small coarse levels (the GMRES of the Krylov
+ * CSLP, Sec. 4.2, and GMRES coarsest multigrid solves): when a level's
+ * ghost-extended copy fits in LDS (up to about 65 x 65 nodes in FP64), each
+ * member's whole GMRES (operator, Gram-Schmidt, Givens rotations, stopping
+ * test, back substitution, x = V y) runs in one workgroup, with one launch and
+ * one host wait per solve instead of several launches and a wait per step.
+ * The same method and stopping rule (reading R11); rounding differs from the
+ * host-driven path in the order of the sums.  enable = 1 (default) or 0 (every
+ * level host-driven).  HM_ERR_ARG for a null problem. */
+hm_status hm_set_small_krylov(hm_problem* p, int enable);
+
 hm_status hm_destroy_problem(hm_problem* p);
 
 /* ---- Lockstep batches: several problems of one configuration per launch -----

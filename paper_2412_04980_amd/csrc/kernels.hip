@@ -358,8 +358,27 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
   T lre[WT_R], lim[WT_R], kre[WT_R], kim[WT_R];
 #pragma unroll
   for (int o = 0; o < WT_R; ++o) { lre[o] = lim[o] = kre[o] = kim[o] = T(0); }
+  // vertical weights without run-time indexing: a queue of m1/t1 shifted one
+  // row per pass and, per output o, the weights m1[rr - o], t1[rr - o] of the
+  // current pass (zero outside the stencil).  An index into the kernel
+  // arguments inside the loop made scalar loads whose waits also drained the
+  // tile's LDS reads.
+  T qm[W], qt[W], mo[WT_R], to[WT_R];
+#pragma unroll
+  for (int a = 0; a < W; ++a) { qm[a] = d.m1[a]; qt[a] = d.t1[a]; }
+#pragma unroll
+  for (int o = 0; o < WT_R; ++o) { mo[o] = T(0); to[o] = T(0); }
 #pragma unroll 1
   for (int rr = 0; rr < WT_R + 2 * R; ++rr) {
+    // this pass's weights: output o takes m1[rr - o]
+#pragma unroll
+    for (int o = WT_R - 1; o > 0; --o) { mo[o] = mo[o - 1]; to[o] = to[o - 1]; }
+    mo[0] = qm[0];
+    to[0] = qt[0];
+#pragma unroll
+    for (int a = 0; a + 1 < W; ++a) { qm[a] = qm[a + 1]; qt[a] = qt[a + 1]; }
+    qm[W - 1] = T(0);
+    qt[W - 1] = T(0);
     T tur = 0, tui = 0, mur = 0, mui = 0, mwr = 0, mwi = 0;
 #pragma unroll
     for (int a = 0; a < W; ++a) {
@@ -372,15 +391,11 @@ __global__ void __launch_bounds__(NT) k_wide_tiled(OpDesc<T> d, const cx<T>* __r
       mwr += mk2 * uv.re; mwi += mk2 * uv.im;
     }
 #pragma unroll
-    for (int o = 0; o < WT_R; ++o) {
-      const int bb = rr - o;                   // tap row (b + R)
-      if (bb >= 0 && bb < W) {
-        const T mb = d.m1[bb], tb = d.t1[bb];
-        lre[o] += mb * tur + tb * mur;
-        lim[o] += mb * tui + tb * mui;
-        kre[o] += mb * mwr;
-        kim[o] += mb * mwi;
-      }
+    for (int o = 0; o < WT_R; ++o) {           // tap row (b + R) = rr - o
+      lre[o] += mo[o] * tur + to[o] * mur;
+      lim[o] += mo[o] * tui + to[o] * mui;
+      kre[o] += mo[o] * mwr;
+      kim[o] += mo[o] * mwi;
     }
   }
   T are[WT_R], aim[WT_R];
@@ -534,8 +549,26 @@ __global__ void __launch_bounds__(NT) k_wide_persist(OpDesc<T> d, const cx<T>* _
     T lre[WT_R], lim[WT_R], kre[WT_R], kim[WT_R];
 #pragma unroll
     for (int o = 0; o < WT_R; ++o) { lre[o] = lim[o] = kre[o] = kim[o] = T(0); }
+    // vertical weights without run-time indexing: a queue of m1/t1 shifted one
+    // row per pass and, per output o, the weights m1[rr - o], t1[rr - o] of the
+    // current pass (zero outside the stencil).  An index into the kernel
+    // arguments inside the loop made scalar loads whose waits also drained the
+    // tile's LDS reads.
+    T qm[W], qt[W], mo[WT_R], to[WT_R];
+#pragma unroll
+    for (int a = 0; a < W; ++a) { qm[a] = d.m1[a]; qt[a] = d.t1[a]; }
+#pragma unroll
+    for (int o = 0; o < WT_R; ++o) { mo[o] = T(0); to[o] = T(0); }
 #pragma unroll 1
     for (int rr = 0; rr < WT_R + 2 * R; ++rr) {
+#pragma unroll
+      for (int o = WT_R - 1; o > 0; --o) { mo[o] = mo[o - 1]; to[o] = to[o - 1]; }
+      mo[0] = qm[0];
+      to[0] = qt[0];
+#pragma unroll
+      for (int a = 0; a + 1 < W; ++a) { qm[a] = qm[a + 1]; qt[a] = qt[a + 1]; }
+      qm[W - 1] = T(0);
+      qt[W - 1] = T(0);
       T tur = 0, tui = 0, mur = 0, mui = 0, mwr = 0, mwi = 0;
 #pragma unroll
       for (int a = 0; a < W; ++a) {
@@ -548,15 +581,11 @@ __global__ void __launch_bounds__(NT) k_wide_persist(OpDesc<T> d, const cx<T>* _
         mwr += mk2 * uv.re; mwi += mk2 * uv.im;
       }
 #pragma unroll
-      for (int o = 0; o < WT_R; ++o) {
-        const int bb = rr - o;
-        if (bb >= 0 && bb < W) {
-          const T mb = d.m1[bb], tb = d.t1[bb];
-          lre[o] += mb * tur + tb * mur;
-          lim[o] += mb * tui + tb * mui;
-          kre[o] += mb * mwr;
-          kim[o] += mb * mwi;
-        }
+      for (int o = 0; o < WT_R; ++o) {         // tap row (b + R) = rr - o
+        lre[o] += mo[o] * tur + to[o] * mur;
+        lim[o] += mo[o] * tui + to[o] * mui;
+        kre[o] += mo[o] * mwr;
+        kim[o] += mo[o] * mwi;
       }
     }
     if (x < nx) {
@@ -1450,6 +1479,367 @@ __global__ void __launch_bounds__(NT) k_csr_spmv(int nrows, int ncols, const int
   if (r < nrows) y[r] = mk(re, im);
 }
 
+// ---- small coarse levels: one Krylov solve per workgroup ----------------------
+// GMRES from x = 0 on the level's operator (the Krylov CSLP of Sec. 4.2, or a
+// multigrid coarsest solve), run to its stopping test by one workgroup of 1024
+// threads per member, with no host round trip per step: the operator applied
+// from a ghost-extended copy of the whole level in LDS, classical (or
+// modified) Gram-Schmidt with block reductions, the Givens rotations and the
+// stopping test of reading R11 on the device, back substitution and x = V y.
+// Used when the level fits in LDS; one launch replaces about five launches and
+// one host wait per step.  For the operator a thread takes tasks of SG_RB
+// vertically adjacent nodes of one column (rows reuse the stencil's row sums);
+// a wave's lanes take
+// consecutive columns; the Gram-Schmidt sweeps take nodes in row-major order
+// with the work vector w in global memory (both stay in the caches on these
+// sizes).
+constexpr int SG_NT = 512;
+constexpr int SG_WAVES = SG_NT / 64;
+constexpr int SG_RB = 3;           // nodes of a task (one column)
+constexpr int SG_G = 8;            // dots per block reduction (classical Gram-Schmidt)
+
+// Sum over the block of NV complex values per thread; every thread gets the
+// sums (fixed order: lanes by the wave reduction, then waves in order).  The
+// first 2 NV threads add the wave partials and publish the sums, which every
+// thread then reads once.
+template <int NV>
+__device__ __forceinline__ void sg_block_sum(double (&re)[NV], double (&im)[NV],
+                                             double* __restrict__ red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // the wave sums of every value, level by level (the shuffles of one level
+  // are independent and go out together; per value the order of wave_sum)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      re[v] += __shfl_xor(re[v], off, 64);
+      im[v] += __shfl_xor(im[v], off, 64);
+    }
+  }
+  double* part = red;                       // [2 NV][SG_WAVES]
+  double* sum = red + 2 * NV * SG_WAVES;    // [2 NV]
+  __syncthreads();                          // the previous sums have been read
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      part[(2 * v) * SG_WAVES + wid] = re[v];
+      part[(2 * v + 1) * SG_WAVES + wid] = im[v];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * NV) {
+    double acc = 0;
+    for (int w = 0; w < SG_WAVES; ++w) acc += part[threadIdx.x * SG_WAVES + w];
+    sum[threadIdx.x] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    re[v] = sum[2 * v];
+    im[v] = sum[2 * v + 1];
+  }
+}
+
+// Operator of the level at column x, rows y0 .. y0 + SG_RB - 1 (those inside the
+// grid), from the ghost-extended level in LDS (row stride sx, offset R).
+template <typename T, int R>
+__device__ __forceinline__ void sg_apply(const OpDesc<T>& d, const cx<T>* __restrict__ su,
+                                         const T* __restrict__ sk, int sx,
+                                         const cx<T>* __restrict__ ug, int x, int y0,
+                                         cx<T> (&out)[SG_RB]) {
+  constexpr int W = 2 * R + 1;
+  auto U = [&](int xx, int yy) { return su[(yy + R) * sx + xx + R]; };
+  auto K2 = [&](int xx, int yy) { return sk[(yy + R) * sx + xx + R]; };
+  T lre[SG_RB], lim[SG_RB], kre[SG_RB], kim[SG_RB];
+#pragma unroll
+  for (int o = 0; o < SG_RB; ++o) { lre[o] = lim[o] = kre[o] = kim[o] = T(0); }
+  if constexpr (R >= 2) {
+    // vertical weights without run-time indexing: a queue of m1/t1 shifted one
+    // row per pass and, per output o, the weights m1[rr - o], t1[rr - o] of the
+    // current pass (zero outside the stencil).  An index into the kernel
+    // arguments inside the loop made scalar loads whose waits also drained the
+    // tile's LDS reads.
+    T qm[W], qt[W], mo[SG_RB], to[SG_RB];
+#pragma unroll
+    for (int a = 0; a < W; ++a) { qm[a] = d.m1[a]; qt[a] = d.t1[a]; }
+#pragma unroll
+    for (int o = 0; o < SG_RB; ++o) { mo[o] = T(0); to[o] = T(0); }
+#pragma unroll 1
+    for (int rr = 0; rr < SG_RB + 2 * R; ++rr) {
+#pragma unroll
+      for (int o = SG_RB - 1; o > 0; --o) { mo[o] = mo[o - 1]; to[o] = to[o - 1]; }
+      mo[0] = qm[0];
+      to[0] = qt[0];
+#pragma unroll
+      for (int a = 0; a + 1 < W; ++a) { qm[a] = qm[a + 1]; qt[a] = qt[a + 1]; }
+      qm[W - 1] = T(0);
+      qt[W - 1] = T(0);
+      const int yy = y0 - R + rr;
+      if (yy < -R || yy >= d.ny + R) continue;
+      T tur = 0, tui = 0, mur = 0, mui = 0, mwr = 0, mwi = 0;
+#pragma unroll
+      for (int a = 0; a < W; ++a) {
+        const cx<T> uv = U(x - R + a, yy);
+        const T k2 = K2(x - R + a, yy);
+        const T ta = d.t1[a], ma = d.m1[a];
+        tur += ta * uv.re; tui += ta * uv.im;
+        mur += ma * uv.re; mui += ma * uv.im;
+        const T mk2 = ma * k2;
+        mwr += mk2 * uv.re; mwi += mk2 * uv.im;
+      }
+#pragma unroll
+      for (int o = 0; o < SG_RB; ++o) {        // tap row (b + R) = rr - o
+        lre[o] += mo[o] * tur + to[o] * mur;
+        lim[o] += mo[o] * tui + to[o] * mui;
+        kre[o] += mo[o] * mwr;
+        kim[o] += mo[o] * mwi;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < SG_RB; ++o) {
+    const int y = y0 + o;
+    if (y >= d.ny) break;
+    const cx<T> uc = U(x, y);
+    const bool bnd = x == 0 || y == 0 || x == d.nx - 1 || y == d.ny - 1;
+    if (bnd && d.bc) {
+      // Dirichlet boundary row d_b u_b; the ghost-extended copy holds zero there
+      out[o] = (d.scale * T(4) * d.inv_H2) * ug[(size_t)y * d.nx + x];
+    } else if (bnd || R == 1) {
+      const T k2 = K2(x, y);
+      cx<T> s = mk(T(4) * uc.re, T(4) * uc.im);
+      s = s - U(x - 1, y);
+      s = s - U(x + 1, y);
+      s = s - U(x, y - 1);
+      s = s - U(x, y + 1);
+      const cx<T> sk2 = mk(d.sig_re * k2, d.sig_im * k2) * uc;
+      out[o] = d.scale * (d.inv_H2 * s - sk2);
+    } else {
+      out[o] = mk(lre[o] - (d.sig_re * kre[o] - d.sig_im * kim[o]),
+                  lim[o] - (d.sig_re * kim[o] + d.sig_im * kre[o]));
+    }
+  }
+}
+
+// (ar, ai) += sum_{i < m} c_i V_i[p] in order, four basis loads in flight
+template <typename T>
+__device__ __forceinline__ void sg_combine(const cx<T>* __restrict__ V, int n, int p,
+                                           const c128* __restrict__ c, int m, double& ar,
+                                           double& ai) {
+  int i = 0;
+  for (; i + 4 <= m; i += 4) {
+    cx<T> v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = V[(size_t)(i + q) * n + p];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) upd_acc(ar, ai, c[i + q], v[q]);
+  }
+  for (; i < m; ++i) upd_acc(ar, ai, c[i], V[(size_t)i * n + p]);
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(SG_NT) k_gmres_small(OpDesc<T> d, const T* __restrict__ k,
+                                                       const cx<T>* __restrict__ b,
+                                                       cx<T>* __restrict__ x,
+                                                       cx<T>* __restrict__ V,
+                                                       cx<T>* __restrict__ w,
+                                                       c128* __restrict__ H, SmallGmresArgs ga,
+                                                       c128* __restrict__ info, Batch z) {
+  extern __shared__ double smem[];
+  HM_MEMBER(k); HM_MEMBER(b); HM_MEMBER(x); HM_MEMBER(V); HM_MEMBER(w); HM_MEMBER(H);
+  info = at_member(info, z.hz, z);
+  const int nx = d.nx, ny = d.ny;
+  const int n = nx * ny;
+  const int sx = nx + 2 * R, sy = ny + 2 * R;
+  const int ldh = ga.ldh;
+  const int maxit = ga.maxit[blockIdx.z];
+  const double tol = ga.tol[blockIdx.z];
+  const int tid = threadIdx.x;
+  // LDS: reduction scratch, control slots, Givens state, the ghost-extended
+  // level and its k^2
+  double* red = smem;                                    // 2 SG_G (SG_WAVES + 1)
+  double* ctl = red + 2 * SG_G * (SG_WAVES + 1);         // 4: stop, breakdown, estimate
+  c128* hc = (c128*)(ctl + 4);                           // ldh: the current column / y
+  c128* gs = hc + ldh;                                   // ldh: g
+  c128* sn = gs + ldh;                                   // ldh: rotation sines
+  double* cn = (double*)(sn + ldh);                      // ldh (even): rotation cosines
+  cx<T>* su = (cx<T>*)(cn + ((ldh + 1) & ~1));
+  T* sk = (T*)(su + (size_t)sx * sy);
+  const int ntask = nx * ((ny + SG_RB - 1) / SG_RB);
+  // k^2 of the level, ghost-extended once (the ghost wavenumber is zero)
+  for (int idx = tid; idx < sx * sy; idx += SG_NT) {
+    const int r = idx / sx, c = idx - r * sx;
+    cx<T> uv;
+    T k2;
+    ext_val(d, b, k, c - R, r - R, uv, k2);
+    sk[idx] = k2;
+  }
+  // beta = ||b||
+  double bre[1] = {0}, bim[1] = {0};
+  for (int p = tid; p < n; p += SG_NT) {
+    const cx<T> v = b[p];
+    bre[0] = fma((double)v.re, (double)v.re, bre[0]);
+    bre[0] = fma((double)v.im, (double)v.im, bre[0]);
+  }
+  sg_block_sum<1>(bre, bim, red);
+  const double beta = sqrt(bre[0]);
+  if (beta == 0.0 || maxit <= 0) {
+    for (int p = tid; p < n; p += SG_NT) x[p] = mk(T(0), T(0));
+    if (tid == 0) info[0] = mk(0.0, beta);
+    return;
+  }
+  {
+    const T s = (T)(1.0 / beta);
+    for (int p = tid; p < n; p += SG_NT) V[p] = s * b[p];
+  }
+  if (tid == 0) gs[0] = mk(beta, 0.0);
+  int m = 0;
+  for (int j = 0;; ++j) {
+    const cx<T>* vj = V + (size_t)j * n;
+    __syncthreads();                 // V_j written by every thread; LDS copy free
+    for (int idx = tid; idx < sx * sy; idx += SG_NT) {
+      const int r = idx / sx, c = idx - r * sx;
+      cx<T> uv;
+      T k2;
+      ext_val(d, vj, k, c - R, r - R, uv, k2);
+      su[idx] = uv;
+    }
+    __syncthreads();
+    // w = Op V_j, SG_RB nodes of one column per task
+    for (int task = tid; task < ntask; task += SG_NT) {
+      const int x0 = task % nx, y0 = (task / nx) * SG_RB;
+      cx<T> out[SG_RB];
+      sg_apply<T, R>(d, su, sk, sx, vj, x0, y0, out);
+#pragma unroll
+      for (int o = 0; o < SG_RB; ++o)
+        if (y0 + o < ny) w[(size_t)(y0 + o) * nx + x0] = out[o];
+    }
+    __syncthreads();                 // w complete
+    // orthogonalise against V_0 .. V_j
+    if (ga.mgs) {
+      for (int i = 0; i <= j; ++i) {
+        const cx<T>* vi = V + (size_t)i * n;
+        double re[1] = {0}, im[1] = {0};
+        for (int p = tid; p < n; p += SG_NT) dot_acc(re[0], im[0], vi[p], w[p]);
+        sg_block_sum<1>(re, im, red);
+        const c128 h = mk(re[0], im[0]);
+        if (tid == 0) hc[i] = h;
+        const cx<T> ht = cvt<T>(h);
+        for (int p = tid; p < n; p += SG_NT) w[p] = w[p] - ht * vi[p];
+        __syncthreads();
+      }
+    } else {
+      for (int i0 = 0; i0 <= j; i0 += SG_G) {
+        const int gm = j + 1 - i0 < SG_G ? j + 1 - i0 : SG_G;
+        double re[SG_G], im[SG_G];
+#pragma unroll
+        for (int g = 0; g < SG_G; ++g) { re[g] = 0; im[g] = 0; }
+        for (int p = tid; p < n; p += SG_NT) {
+          const cx<T> wv = w[p];
+          cx<T> vv[SG_G];
+#pragma unroll
+          for (int g = 0; g < SG_G; ++g)       // every load of the node in flight together
+            vv[g] = V[(size_t)(i0 + (g < gm ? g : 0)) * n + p];
+#pragma unroll
+          for (int g = 0; g < SG_G; ++g)
+            if (g < gm) dot_acc(re[g], im[g], vv[g], wv);
+        }
+        sg_block_sum<SG_G>(re, im, red);
+        if (tid == 0)
+          for (int g = 0; g < gm; ++g) hc[i0 + g] = mk(re[g], im[g]);
+      }
+      __syncthreads();               // hc complete
+      for (int p = tid; p < n; p += SG_NT) {
+        double ar = 0, ai = 0;
+        sg_combine(V, n, p, hc, j + 1, ar, ai);
+        const cx<T> wv = w[p];
+        w[p] = mk((T)((double)wv.re - ar), (T)((double)wv.im - ai));
+      }
+    }
+    double nre[1] = {0}, nim[1] = {0};
+    for (int p = tid; p < n; p += SG_NT) {
+      const cx<T> wv = w[p];
+      nre[0] = fma((double)wv.re, (double)wv.re, nre[0]);
+      nre[0] = fma((double)wv.im, (double)wv.im, nre[0]);
+    }
+    sg_block_sum<1>(nre, nim, red);
+    const double hn = sqrt(nre[0]);
+    // Givens rotations of the column (thread 0), the estimate |g_{j+1}|
+    if (tid == 0) {
+      c128* col = hc;                  // rotated in LDS, then stored as column j of H
+      col[j + 1] = mk(hn, 0.0);
+      for (int i = 0; i < j; ++i) {
+        const c128 a = col[i], bb = col[i + 1];
+        const c128 s = sn[i];
+        const double c = cn[i];
+        col[i] = mk(c * a.re, c * a.im) + s * bb;
+        col[i + 1] = mk(c * bb.re, c * bb.im) - cmulc(s, a);
+      }
+      const c128 a = col[j], bb = col[j + 1];
+      double c;
+      c128 s;
+      if (bb.re == 0.0 && bb.im == 0.0) {
+        c = 1.0; s = mk(0.0, 0.0);
+      } else if (a.re == 0.0 && a.im == 0.0) {
+        c = 0.0; s = mk(1.0, 0.0);
+      } else {
+        const double aa = hypot(a.re, a.im);
+        const double nrm = hypot(aa, hypot(bb.re, bb.im));
+        c = aa / nrm;
+        // s = (a / |a|) conj(b) / nrm
+        const c128 t = cmulc(bb, mk(a.re / aa, a.im / aa));
+        s = mk(t.re / nrm, t.im / nrm);
+      }
+      cn[j] = c;
+      sn[j] = s;
+      col[j] = mk(c * a.re, c * a.im) + s * bb;
+      col[j + 1] = mk(0.0, 0.0);
+      const c128 gj = gs[j];
+      gs[j + 1] = mk(0.0, 0.0) - cmulc(s, gj);  // -conj(s) g_j
+      gs[j] = mk(c * gj.re, c * gj.im);
+      for (int i = 0; i <= j; ++i) H[(size_t)j * ldh + i] = col[i];
+      const double est = hypot(gs[j + 1].re, gs[j + 1].im);
+      const bool broke = hn <= 1e-14 * beta;
+      ctl[0] = (broke || (tol >= 0.0 && est <= tol * beta) || j + 1 >= maxit) ? 1.0 : 0.0;
+      ctl[1] = broke ? 1.0 : 0.0;
+      ctl[2] = est;
+    }
+    __syncthreads();
+    const bool stop = ctl[0] != 0.0, broke = ctl[1] != 0.0;
+    if (!broke) {
+      const T s = (T)(1.0 / hn);
+      cx<T>* vn = V + (size_t)(j + 1) * n;
+      for (int p = tid; p < n; p += SG_NT) vn[p] = s * w[p];
+    }
+    if (stop) {
+      m = j + 1;
+      break;
+    }
+  }
+  // y from the rotated triangle (copied into the LDS the level used; thread 0
+  // back-substitutes, y overwrites hc), then x = V y
+  c128* tri = (c128*)su;                                 // m x m, column-major
+  for (int e = tid; e < m * m; e += SG_NT) {
+    const int col = e / m, row = e - col * m;
+    if (row <= col) tri[e] = H[(size_t)col * ldh + row];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = m - 1; i >= 0; --i) {
+      c128 acc = gs[i];
+      for (int kk = i + 1; kk < m; ++kk) acc = acc - tri[kk * m + i] * hc[kk];
+      hc[i] = cdiv(acc, tri[i * m + i]);
+    }
+    info[0] = mk((double)m, ctl[2] / beta);
+  }
+  __syncthreads();
+  for (int p = tid; p < n; p += SG_NT) {
+    double ar = 0, ai = 0;
+    sg_combine(V, n, p, hc, m, ar, ai);
+    x[p] = mk((T)ar, (T)ai);
+  }
+}
+
 }  // namespace
 
 // ============================ launchers ======================================
@@ -1802,6 +2192,54 @@ hipError_t launch_max_real(const double* a, size_t n, RedBuf rb, c128* out, hipS
   return hipGetLastError();
 }
 
+size_t small_gmres_lds(int nx, int ny, int R, size_t es, size_t ks, int cap) {
+  const size_t ldh = (size_t)cap + 2;
+  const size_t level = (size_t)(nx + 2 * R) * (ny + 2 * R) * (es + ks);
+  const size_t tri = (size_t)cap * cap * sizeof(c128);   // reuses the level's area at the end
+  return sizeof(double) * (2 * SG_G * (SG_WAVES + 1) + 4) + 3 * ldh * sizeof(c128) +
+         ((ldh + 1) & ~(size_t)1) * sizeof(double) + (level > tri ? level : tri);
+}
+
+template <typename T>
+bool small_gmres_fits(const OpDesc<T>& d, int cap) {
+  static int lds_max = -1;                     // per device type; the same on every call
+  if (lds_max < 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      v = 0;
+    lds_max = v;
+  }
+  return d.R >= 1 && d.R <= 3 && cap + 2 <= SmallGmresArgs::kMaxLdh &&
+         small_gmres_lds(d.nx, d.ny, d.R, sizeof(cx<T>), sizeof(T), cap) <= (size_t)lds_max;
+}
+
+template <typename T, int R>
+static hipError_t launch_gmres_small_r(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x,
+                                       cx<T>* V, cx<T>* w, c128* H, const SmallGmresArgs& ga,
+                                       c128* info, hipStream_t s, const Batch& z) {
+  const size_t lds = small_gmres_lds(d.nx, d.ny, R, sizeof(cx<T>), sizeof(T), ga.ldh - 2);
+  static size_t granted = 0;                   // dynamic LDS limit raised for this kernel
+  if (lds > granted) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_gmres_small<T, R>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    granted = lds;
+  }
+  k_gmres_small<T, R><<<zgrid(1, z), SG_NT, lds, s>>>(d, k, b, x, V, w, H, ga, info, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gmres_small(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x, cx<T>* V,
+                              cx<T>* w, c128* H, const SmallGmresArgs& ga, c128* info,
+                              hipStream_t s, const Batch& z) {
+  if (d.R == 1) return launch_gmres_small_r<T, 1>(d, k, b, x, V, w, H, ga, info, s, z);
+  if (d.R == 2) return launch_gmres_small_r<T, 2>(d, k, b, x, V, w, H, ga, info, s, z);
+  if (d.R == 3) return launch_gmres_small_r<T, 3>(d, k, b, x, V, w, H, ga, info, s, z);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_residual_norm(const OpDesc<double>& d, const c128* u, const double* k,
                                 const c128* b, c128* r, c128* partials, double* norms,
                                 hipStream_t s) {
@@ -1876,7 +2314,11 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
   template hipError_t launch_cgs_update_norm<T>(cx<T>*, const cx<T>*, size_t, int, const c128*,    \
                                                 size_t, RedBuf, c128*, hipStream_t);                \
   template hipError_t launch_norm<T>(const cx<T>*, size_t, RedBuf, c128*, hipStream_t, c128*,      \
-                                     const Batch&);
+                                     const Batch&);                                                 \
+  template bool small_gmres_fits<T>(const OpDesc<T>&, int);                                        \
+  template hipError_t launch_gmres_small<T>(const OpDesc<T>&, const T*, const cx<T>*, cx<T>*,       \
+                                            cx<T>*, cx<T>*, c128*, const SmallGmresArgs&, c128*,    \
+                                            hipStream_t, const Batch&);
 HM_INST_T(float)
 HM_INST_T(double)
 #undef HM_INST_T

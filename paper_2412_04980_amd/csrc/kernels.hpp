@@ -143,6 +143,31 @@ hipError_t launch_csr5_assemble(const OpDesc<double>& d, const double* k, int* r
 hipError_t launch_csr_spmv(int nrows, int ncols, const int* rowptr, const int* colidx,
                            const c128* vals, const c128* x, c128* y, hipStream_t s);
 
+// ---- small coarse levels: a whole GMRES solve in one workgroup per member ---
+// Parameters of one launch: member z (grid z) runs at most maxit[z] steps and
+// stops after step j when the Givens estimate |g_{j+1}| <= tol[z] ||b|| (tol < 0:
+// exactly maxit steps) or on breakdown; modified Gram-Schmidt if mgs.  ldh is
+// the column stride of the device Hessenberg H (cap + 2).
+struct SmallGmresArgs {
+  static constexpr int kMaxLdh = 512;
+  int ldh = 0;
+  int mgs = 0;
+  int maxit[kMaxBatch] = {};
+  double tol[kMaxBatch] = {};
+};
+// True when the level (operator d, basis capacity cap) fits the one-workgroup
+// solve: its ghost-extended copy in LDS.
+template <typename T>
+bool small_gmres_fits(const OpDesc<T>& d, int cap);
+// GMRES from x = 0 on d (wavenumber k) for the right-hand side b, basis V of
+// (cap+1) x N, work vector w (N), Hessenberg H; writes x and, in info[0] (pinned host memory of
+// each member, hz apart), (steps, final estimate / ||b||), or (0, ||b||) when no
+// step was taken.
+template <typename T>
+hipError_t launch_gmres_small(const OpDesc<T>& d, const T* k, const cx<T>* b, cx<T>* x, cx<T>* V,
+                              cx<T>* w, c128* H, const SmallGmresArgs& ga, c128* info,
+                              hipStream_t s, const Batch& z = Batch());
+
 // ---- reductions (double accumulation; results on the device) --------------
 struct RedBuf {
   c128* partials;   // >= kMaxChunks * (max dots) entries

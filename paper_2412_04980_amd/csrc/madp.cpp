@@ -219,6 +219,8 @@ struct hm_problem {
   double last_estimate = 0;
   // load hints of the Krylov CSLP's Gram-Schmidt passes (hm_set_basis_cache)
   CachePolicy cache;
+  // small coarse levels solved by one workgroup per member (hm_set_small_krylov)
+  bool small_krylov = true;
   // optional per-kernel-class timing with HIP events on the problem's stream
   unsigned timing_mask = 0;
   int timing_every = 1;                 // bracket every n-th launch of a class
@@ -447,10 +449,44 @@ static void apply_level(Ctx& c, const Act& a, const DefLevel& L, bool cslp, int 
 // overlap the next step.  When a member meets its tolerance at step j, its
 // speculative step j+1 has only written w, column j+1 and V_{j+2}, none of
 // which its solution uses.
+// The same solve when the level fits one workgroup (small_gmres_fits): every
+// step, the Givens rotations and the stopping test run on the device, one
+// workgroup per member, and the host waits once for the step counts.  A
+// member with b = 0 (x = 0, no step) takes no replayed count, as below.
+template <typename T>
+static void gmres_small(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
+                        int maxit, double tol, int kind, const cx<T>* b, cx<T>* x) {
+  hm_problem* p = c.p;
+  SmallGmresArgs ga;
+  ga.ldh = ws.cap + 2;
+  ga.mgs = p->cfg.cslp_orth == HM_ORTH_MODIFIED;
+  std::vector<int> forced(a0.size(), -1);
+  for (size_t t = 0; t < a0.size(); ++t) {
+    forced[t] = kind >= 0 ? forced_count(c.mem[a0[t]], kind) : -1;
+    ga.maxit[t] = forced[t] >= 0 ? forced[t] : maxit;
+    ga.tol[t] = forced[t] >= 0 ? -1.0 : tol;
+    if (ga.maxit[t] > ws.cap) throw ArgError("Krylov step count exceeds the workspace");
+  }
+  HM_CHECK(launch_gmres_small<T>(op, k, b, x, (cx<T>*)ws.V, (cx<T>*)ws.w, ws.H, ga, p->host_H,
+                                 p->s, members(c, a0)));
+  wait_stream(c);
+  for (size_t t = 0; t < a0.size(); ++t) {
+    hm_problem* q = c.mem[a0[t]];
+    const c128 info = q->host_H[0];
+    if (kind < 0) continue;
+    if (info.re == 0.0 && info.im == 0.0 && forced[t] >= 0) --q->rep_pos[kind];
+    q->rec[kind].push_back((int)info.re);
+  }
+}
+
 template <typename T>
 static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
                       int maxit, double tol, int kind, const cx<T>* b, cx<T>* x) {
   hm_problem* p = c.p;
+  if (p->small_krylov && small_gmres_fits<T>(op, ws.cap)) {
+    gmres_small<T>(c, a0, op, k, ws, maxit, tol, kind, b, x);
+    return;
+  }
   const size_t N = ws.N;
   cx<T>* V = (cx<T>*)ws.V;
   cx<T>* w = (cx<T>*)ws.w;
@@ -1802,6 +1838,12 @@ hm_status hm_set_basis_cache(hm_problem* p, double basis_bytes, double recent_by
   const CachePolicy def;
   p->cache.basis = basis_bytes < 0 ? def.basis : basis_bytes;
   p->cache.recent = recent_bytes < 0 ? def.recent : recent_bytes;
+  return HM_OK;
+}
+
+hm_status hm_set_small_krylov(hm_problem* p, int enable) {
+  if (!p) return HM_ERR_ARG;
+  p->small_krylov = enable != 0;
   return HM_OK;
 }
 

@@ -147,7 +147,9 @@ def test_batch_with_replayed_counts_and_timing():
     """Per-member replayed step counts (a member's fixed-count parity mode) and
     kernel timing on member 0 work inside a batch: every member equals its
     replayed solve alone bit for bit, and the timed classes record launches
-    whose bytes count every member of the launch."""
+    whose bytes count every member of the launch.  The coarsest level is
+    host-driven here (hm_set_small_krylov off): the one-workgroup solve of small
+    levels has no per-step launches to time."""
     n = 65
     h, ks = media(n, (1.0, 1.3), seed=13)
     cfg = hm.default_config(n, n, h)
@@ -156,6 +158,7 @@ def test_batch_with_replayed_counts_and_timing():
     recorded = []
     for k, b in zip(ks, bs):
         p = hm.create_problem(cfg, gpu(k))
+        hm.set_small_krylov(p, False)
         try:
             hm.fgmres_solve(p, gpu(b))
             recorded.append([hm.get_counts(p, kind) for kind in range(4)])
@@ -164,6 +167,7 @@ def test_batch_with_replayed_counts_and_timing():
     bt = hm.create_batch(cfg, [gpu(k) for k in ks])
     try:
         for m, counts in zip(bt.members, recorded):
+            hm.set_small_krylov(m, False)
             for kind in range(4):
                 hm.set_replay(m, kind, counts[kind])
         hm.set_timing(bt.members[0], (1 << 5) - 1, 1)
@@ -173,6 +177,7 @@ def test_batch_with_replayed_counts_and_timing():
         bt.close()
     for i, (k, b) in enumerate(zip(ks, bs)):
         p = hm.create_problem(cfg, gpu(k))
+        hm.set_small_krylov(p, False)
         try:
             for kind in range(4):
                 hm.set_replay(p, kind, recorded[i][kind])

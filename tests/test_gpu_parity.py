@@ -476,3 +476,39 @@ def test_deeper_hierarchies(levels):
     assert abs(info["outer_iters"] - info_ref["outer_iters"]) <= 1
     assert np.linalg.norm(host(u) - u_ref) / np.linalg.norm(u_ref) <= 1e-5
     assert info["rel_res_true"] <= 1e-6
+
+
+@pytest.mark.parametrize("precision", [hm.HM_FP64, hm.HM_MIXED_FP32, hm.HM_MIXED_FP32_ALL])
+def test_small_krylov_matches_host_driven(precision):
+    """The one-workgroup GMRES of small coarse levels (hm_set_small_krylov)
+    against the host-driven path on the 129^2, k = 20 workload, whose coarsest
+    level (33^2) takes it: the same step counts, the Krylov CSLP and replayed
+    preconditioner applications to rounding, and the same solve."""
+    nx = ny = 129
+    h = 1.0 / 128
+    k = np.full(nx * ny, 20.0)
+    tol = 1e-11 if precision != hm.HM_MIXED_FP32_ALL else 1e-5
+    a = make(nx, ny, h, k, precision=precision)
+    bh = make(nx, ny, h, k, precision=precision)
+    hm.set_small_krylov(bh, False)
+    try:
+        for seed in (90, 91):
+            x = workloads.smooth_field(33, 33, seed, sigma=1.5)
+            hm.reset_counts(a)
+            hm.reset_counts(bh)
+            ra = host(hm.apply_operator(a, 3, hm.HM_OP_CSLP, gpu(x)))
+            rb = host(hm.apply_operator(bh, 3, hm.HM_OP_CSLP, gpu(x)))
+            assert hm.get_counts(a, hm.KIND_CSLP) == hm.get_counts(bh, hm.KIND_CSLP)
+            assert relerr(ra, rb) <= tol
+        b = workloads.point_source(nx, ny, h, 64, 64)
+        hm.reset_counts(a)
+        hm.reset_counts(bh)
+        ua, ia = hm.fgmres_solve(a, gpu(b))
+        ub, ib = hm.fgmres_solve(bh, gpu(b))
+        assert ia["outer_iters"] == ib["outer_iters"]
+        assert hm.get_counts(a, hm.KIND_LEVEL2) == hm.get_counts(bh, hm.KIND_LEVEL2)
+        assert ia["rel_res_true"] <= 1e-6 and ib["rel_res_true"] <= 1e-6
+        assert relerr(host(ua), host(ub)) <= (1e-9 if precision == hm.HM_FP64 else 1e-5)
+    finally:
+        a.close()
+        bh.close()
