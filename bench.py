@@ -22,6 +22,12 @@ Other measurements, each one JSON line of its own:
     --shots        every right-hand side of --config I, sequential vs one lockstep batch
     --kernels      the component kernels of --config I one by one, with measured
                    copy / read-stream bandwidth ceilings
+    --counter-table CSV...  per-kernel averages of rocprofv3 --pmc counter
+                   collections; FETCH_SIZE / WRITE_SIZE scaled by the plain
+                   copies of --copy-calibration MIB run in the same process
+    --trace-table CSV   per-kernel, per-grid rates of the stencil and transfer
+                   kernels from a rocprofv3 kernel trace of a --config I solve
+                   (no GPU needed: reads the trace and prints a markdown table)
 """
 import argparse
 import json
@@ -69,6 +75,9 @@ def parse():
                     help="run the request-stream workload instead (Poisson arrivals of "
                          "solves on 257^2..2049^2 random media, FP32 preconditioner)")
     ap.add_argument("--requests", type=int, default=60)
+    ap.add_argument("--serving-leg", type=int, default=24, metavar="N",
+                    help="default line: also run the first N requests of the request stream "
+                         "at --rate (0: skip)")
     ap.add_argument("--rate", type=float, default=50.0, help="offered requests/s")
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--no-batching", action="store_true",
@@ -96,6 +105,17 @@ def parse():
                          "through the C ABI, with a plain copy and a read-only stream as "
                          "measured bandwidth ceilings")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--trace-table", metavar="CSV",
+                    help="print the per-grid rates of the stencil and transfer kernels in a "
+                         "rocprofv3 kernel-trace CSV of a --config I solve")
+    ap.add_argument("--counter-table", nargs="+", metavar="CSV",
+                    help="per-kernel averages of rocprofv3 --pmc counter CSVs (FETCH_SIZE and "
+                         "WRITE_SIZE calibrated by the copies of --copy-calibration MIB)")
+    ap.add_argument("--traffic-out", metavar="JSON",
+                    help="counter table: also write the calibrated bytes per launch of the "
+                         "Gram-Schmidt passes and the 7x7 scaled apply to this file")
+    ap.add_argument("--trace-min-side", type=int, default=1025,
+                    help="trace table: smallest grid side listed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a plain copy "
                          "kernel of known size, to calibrate hardware byte counters)")
@@ -131,6 +151,25 @@ def timed_solves(hm, torch, prob, b, steps, warmup, timing):
     if timing:
         hm.set_timing(prob, 0)
     return u, total, lat, infos, kt
+
+
+def gs_hbm_share(counts, n, es, cls):
+    """Share of the algorithmic bytes of a Gram-Schmidt pass class that come from
+    HBM under the cache-aware loads, estimated from the step counts of the
+    coarsest-level Krylov CSLP solves: at step j the pass reads m = j + 1 basis
+    vectors (plus w); when the basis exceeds the 256 MB plain-load limit, the
+    vectors older than the 200 MB recent window come from HBM and the rest (the
+    recent vectors, w) from the Infinity Cache; a smaller basis is cache-resident."""
+    vec = float(n) * es
+    recent = int(200.0 * 2**20 / vec)
+    alg = hbm = 0.0
+    for steps in counts:
+        for j in range(steps):
+            m = j + 1
+            alg += (m + 1 if cls == "cgs_dot" else m + 2) * vec
+            if (m + 1) * vec > 256.0 * 2**20:
+                hbm += max(0, m - recent) * vec
+    return hbm / alg if alg else None
 
 
 def cpu_baseline(problem, info, counts_l3):
@@ -189,15 +228,19 @@ def cpu_baseline(problem, info, counts_l3):
 
 
 def serving_bench(args):
+    print(json.dumps(run_serving(args, args.requests, args.rate)), flush=True)
+
+
+def run_serving(args, n_requests, rate):
     import torch
 
     import workloads
     from paper_2412_04980_amd.serving import GpuExecutor, Scheduler, jobs_from_requests, summarize
 
-    reqs = workloads.serving_stream(n_requests=args.requests, rate=args.rate, seed=4)
+    reqs = workloads.serving_stream(n_requests=n_requests, rate=rate, seed=4)
     jobs = jobs_from_requests(reqs)
     log("serving: %d requests, %d solves, offered %.1f req/s" %
-        (len(jobs), sum(len(j.rhs) for j in jobs), args.rate))
+        (len(jobs), sum(len(j.rhs) for j in jobs), rate))
     ex = GpuExecutor()
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
@@ -209,13 +252,24 @@ def serving_bench(args):
             one = type(j)(j.rid, 0.0, j.nx, j.ny, j.h, j.k, j.rhs[:1])
             ex(one) if args.no_batching else ex.run_group([one])
     torch.cuda.synchronize()
+    last = [time.perf_counter()]
+
+    def progress(done, total):
+        # a line every 25 requests or 30 s, so a long run shows it is alive
+        now = time.perf_counter()
+        if done == total or done % 25 == 0 or now - last[0] > 30.0:
+            last[0] = now
+            log("serving: %d / %d requests done" % (done, total))
+
     if args.no_batching:
-        sched = Scheduler(ex, ex.bytes_needed, budget, max_active=args.max_active, realtime=True)
+        sched = Scheduler(ex, ex.bytes_needed, budget, max_active=args.max_active, realtime=True,
+                          progress=progress)
     else:
         # same-size requests waiting together run as one lockstep batch
         sched = Scheduler(ex.run_group, ex.group_bytes, budget, max_active=args.max_active,
                           realtime=True, group_key=ex.group_key,
-                          max_members=min(args.max_members, 16), members=ex.members)
+                          max_members=min(args.max_members, 16), members=ex.members,
+                          progress=progress)
     t0 = time.perf_counter()
     res = sched.run(jobs)
     wall = time.perf_counter() - t0
@@ -232,7 +286,7 @@ def serving_bench(args):
     out = {"metric": "serving: solves/s + p50/p99 request latency (FP32 preconditioner, FP64 "
                      "FGMRES, rel. residual 1e-6)",
            "value": summ["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
-           "higher_is_better": True, "offered_requests_per_s": args.rate,
+           "higher_is_better": True, "offered_requests_per_s": rate, "requests": len(jobs),
            "max_active": args.max_active, "budget_bytes": budget, "data": "synthetic",
            "batching": {"lockstep": not args.no_batching, "groups": len(sched.groups),
                         "mean_requests_per_group": len(jobs) / max(1, len(sched.groups)),
@@ -240,7 +294,7 @@ def serving_bench(args):
            "config": {"workload": "serving stream (Poisson, random media, 257^2..2049^2)"},
            **summ, "by_grid": by_class,
            "max_concurrent": max(e[4] for e in sched.events)}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bandwidth_ceilings(torch, mib=1024, reps=20):
@@ -358,6 +412,228 @@ def kernels_bench(args):
            "config": {"workload": problem.name, "nx": problem.nx, "ny": problem.ny},
            "table": rows}
     print(json.dumps(out), flush=True)
+
+
+# ---- per-grid rates from a rocprofv3 kernel trace ------------------------------
+
+def _mg_sides(n):
+    """Multigrid sides below an n-node side: halve while n - 1 is even and the
+    coarse side keeps at least 3 nodes."""
+    out = [n]
+    while (n - 1) % 2 == 0 and (n - 1) // 2 + 1 >= 3:
+        n = (n - 1) // 2 + 1
+        out.append(n)
+    return out
+
+
+def _launch_shapes(nx, ny, levels):
+    """Every (nx, ny) grid a solve of this hierarchy launches kernels on: the
+    deflation levels and the multigrid levels below them."""
+    shapes, x, y = set(), nx, ny
+    for _ in range(levels):
+        xs, ys = _mg_sides(x), _mg_sides(y)
+        for i in range(min(len(xs), len(ys))):
+            shapes.add((xs[i], ys[i]))
+        x, y = (x - 1) // 2 + 1, (y - 1) // 2 + 1
+    return shapes
+
+
+# launch geometry of the stencil and transfer kernels, as the library computes
+# it: block tiles of 64 x 4 threads (two rows per thread for the 5-point and
+# wide kernels), eight-block XCD turns; transfers launch 256-thread blocks over
+# 248 coarse columns and TRB coarse rows
+def _ceil(a, b):
+    return (a + b - 1) // b
+
+
+def _xcd8(n):
+    return 8 * _ceil(n, 8)
+
+
+def _geometry(family, nx, ny, trb=None):
+    if family == "five_point":
+        return (64 * _xcd8(_ceil(nx, 64) * _ceil(ny, 8)), 4)
+    if family == "wide_tiled":
+        return (64 * _xcd8(_ceil(nx, 64) * _ceil(ny, 8)), 4)
+    if family == "jacobi0":
+        return (64 * _ceil(nx, 64), 4 * _ceil(ny, 4))
+    if family in ("restrict", "prolong"):
+        nxc, nyc = (nx - 1) // 2 + 1, (ny - 1) // 2 + 1
+        return (256 * _xcd8(_ceil(nxc, 248) * _ceil(nyc, trb)), 1)
+    return None
+
+
+def _trace_kernel(name):
+    """(family, label, bytes per fine point as a function of (es, kb), trb,
+    fixed level) for the kernels of the table, else None."""
+    import re
+    m = re.search(r"k_(five_point|wide_tiled|wide_persist|jacobi0|restrict_rows|prolong_rows)"
+                  r"<([^>]*)>", name)
+    if not m:
+        return None
+    fam, targs = m.group(1), [a.strip() for a in m.group(2).split(",")]
+    es = 16 if targs[0] == "double" else 8
+    kb = es // 2
+    mode_names = {0: "apply", 1: "resid", 2: "jacobi", 3: "scaled"}
+    mode_bytes = {0: 2 * es + kb, 1: 3 * es + kb, 2: 3 * es + kb, 3: 3 * es + kb}
+    if fam == "five_point":
+        md = int(targs[1])
+        return ("five_point", "k_five_point<%s,%s>" % (targs[0], mode_names[md]),
+                mode_bytes[md], None, None)
+    if fam in ("wide_tiled", "wide_persist"):
+        r, md = int(targs[1]), int(targs[2])
+        return (fam, "k_%s<%s,R=%d,%s>" % (fam, targs[0], r, mode_names[md]), mode_bytes[md],
+                None, r)
+    if fam == "jacobi0":
+        return ("jacobi0", "k_jacobi0<%s,R=%s>" % (targs[0], targs[1]), 2 * es + kb, None, None)
+    eo = 16 if targs[1] == "double" else 8
+    trb = int(targs[3])
+    if fam == "restrict_rows":
+        kind = "Z^T" if targs[2] == "2" else "full weighting"
+        return ("restrict", "restrict %s <%s,%s>" % (kind, targs[0], targs[1]),
+                es + eo / 4.0, trb, None)
+    zdef = targs[2] == "true"
+    kind = "Z" if zdef else "bilinear add"
+    return ("prolong", "prolong %s <%s,%s>" % (kind, targs[0], targs[1]),
+            (es / 4.0 + eo) if zdef else (es / 4.0 + 2 * eo), trb, None)
+
+
+def trace_table(args):
+    """Average duration and algorithmic-byte rate of every stencil and transfer
+    kernel of a solve, per grid, from the rocprofv3 kernel trace.  The grid of a
+    launch is found from its launch geometry among the grids of the workload's
+    hierarchy; the persistent wide stencils (whose block count follows the
+    device's occupancy) are placed by their stencil radius: 5x5 on level 2,
+    7x7 on level 3."""
+    import csv
+
+    import workloads
+    problem = workloads.config(args.config)
+    levels = 3
+    shapes = _launch_shapes(problem.nx, problem.ny, levels)
+    lvl = {l: ((problem.nx - 1) // 2 ** (l - 1) + 1, (problem.ny - 1) // 2 ** (l - 1) + 1)
+           for l in range(1, levels + 1)}
+    stats = {}
+    with open(args.trace_table) as f:
+        for row in csv.DictReader(f):
+            kk = _trace_kernel(row["Kernel_Name"])
+            if kk is None:
+                continue
+            fam, label, bpp, trb, radius = kk
+            gx, gy = int(row["Grid_Size_X"]), int(row["Grid_Size_Y"])
+            if fam == "wide_persist":
+                cand = [lvl[radius]] if radius in lvl else []
+            else:
+                cand = [s for s in shapes if _geometry(fam, s[0], s[1], trb) == (gx, gy)]
+            if len(cand) != 1:
+                continue
+            nx, ny = cand[0]
+            us = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3
+            e = stats.setdefault((label, nx, ny), [0, 0.0, bpp])
+            e[0] += 1
+            e[1] += us
+    print("| Kernel | Grid | Launches | Avg us | GB/s | of 8 TB/s |")
+    print("|---|---:|---:|---:|---:|---:|")
+    for (label, nx, ny), (n, tot, bpp) in sorted(stats.items(), key=lambda t: (-t[0][1], t[0][0])):
+        if min(nx, ny) < args.trace_min_side:
+            continue
+        avg = tot / n
+        gbs = bpp * nx * ny / (avg * 1e-6) / 1e9
+        side = "%d^2" % nx if nx == ny else "%dx%d" % (nx, ny)
+        print("| %s | %s | %d | %.1f | %.0f | %.2f |" % (label, side, n, avg, gbs,
+                                                        gbs / HBM_PEAK_GBS))
+
+
+# ---- per-kernel hardware counters from rocprofv3 --pmc collections -------------
+
+def _short_kernel(name):
+    import re
+    name = re.sub(r"^void ", "", name)
+    name = name.replace("hm::(anonymous namespace)::", "")
+    depth, out = 0, []
+    for ch in name:                      # drop the argument list
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+# kernel classes of the bench line and the kernels each one times
+TRAFFIC_CLASSES = {
+    "cgs_dot": ("k_multidot<double, true>", "k_multidot<double, false>"),
+    "cgs_update_norm": ("k_cgs_update_norm<double, true>", "k_cgs_update_norm<double, false>"),
+    "wide_stencil_apply": ("k_wide_persist<double, 3, 3>",),
+}
+
+
+def counter_table(args):
+    """Average of every counter per dispatch and kernel over the given rocprofv3
+    counter-collection CSVs.  FETCH_SIZE and WRITE_SIZE (KiB) are also given
+    as bytes scaled by what the same counter reads for the plain copies of
+    --copy-calibration MiB that ran first in the profiled process (the largest
+    copy dispatches); --traffic-out writes those bytes per launch for the
+    kernel classes of the bench line."""
+    import csv
+    import hashlib
+    from collections import defaultdict
+    sums = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(lambda: defaultdict(set))
+    copies = defaultdict(list)
+    for path in args.counter_table:
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                kname = _short_kernel(row["Kernel_Name"])
+                cname, val = row["Counter_Name"], float(row["Counter_Value"])
+                key = (path, row["Dispatch_Id"])
+                if kname.startswith("__amd_rocclr_copyBuffer"):
+                    copies[cname].append(val)
+                    continue
+                sums[kname][cname] += val
+                disp[kname][cname].add(key)
+    factor = {}
+    if args.copy_calibration:
+        true_kib = args.copy_calibration * 1024.0
+        for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+            if copies.get(cname):
+                big = sorted(copies[cname])[-3:]
+                factor[cname] = (sum(big) / len(big)) / true_kib
+    names = sorted({c for k in sums for c in sums[k]})
+    print("| kernel | dispatches | " + " | ".join("%s / dispatch" % c for c in names) +
+          "".join(" | %s MB (calibrated)" % c for c in names if c in factor) + " |")
+    print("|---|---:|" + "---:|" * (len(names) + sum(1 for c in names if c in factor)))
+    per = {}
+    for k in sorted(sums):
+        n = max(len(v) for v in disp[k].values())
+        avg = {c: sums[k][c] / max(1, len(disp[k][c])) for c in names if c in sums[k]}
+        per[k] = (n, avg)
+        cells = ["%.1f" % avg[c] if c in avg else "" for c in names]
+        cal = ["%.1f" % (avg[c] * 1024 / factor[c] / 1e6) if c in avg else ""
+               for c in names if c in factor]
+        print("| `%s` | %d | %s |" % (k, n, " | ".join(cells + cal)))
+    if factor:
+        print("\ncalibration: " + ", ".join("%s reads %.3f of the copied bytes" % (c, f)
+                                          for c, f in factor.items()))
+    if args.traffic_out and len(factor) == 2:
+        classes = {}
+        for cls, kernels in TRAFFIC_CLASSES.items():
+            present = [k for k in kernels if k in per]
+            if not present:
+                continue
+            n = sum(per[k][0] for k in present)
+            fetch = sum(per[k][1].get("FETCH_SIZE", 0.0) * per[k][0] for k in present) / n
+            write = sum(per[k][1].get("WRITE_SIZE", 0.0) * per[k][0] for k in present) / n
+            classes[cls] = {"kernel": " + ".join(present), "fetch_kib_per_dispatch": fetch,
+                            "write_kib_per_dispatch": write,
+                            "bytes_per_launch": 1024 * (fetch / factor["FETCH_SIZE"] +
+                                                        write / factor["WRITE_SIZE"])}
+        rec = {"fetch_factor": factor["FETCH_SIZE"], "write_factor": factor["WRITE_SIZE"],
+               "classes": classes,
+               "kernels_hip_sha256": hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest(),
+               "workload": "%s (FP64), one solve" % TRAFFIC_WORKLOAD}
+        with open(args.traffic_out, "w") as f:
+            json.dump(rec, f, indent=1)
 
 
 # Per-row byte and flop counts of the two matvec forms (complex128 vectors,
@@ -606,6 +882,12 @@ def main():
               "solves shard across GPUs with no exchange)",
               file=sys.stderr)
         sys.exit(2)
+    if args.trace_table:
+        trace_table(args)
+        return
+    if args.counter_table:
+        counter_table(args)
+        return
     import numpy as np
     import torch
 
@@ -654,6 +936,7 @@ def main():
     hm.reset_counts(prob)
     hm.fgmres_solve(prob, b, out=torch.empty_like(b))
     counts_l3 = hm.get_counts(prob, hm.KIND_CSLP)
+    shape_l3 = hm.level_shape(prob, cfg.levels)
     prob.close()
     lat_ms = np.array(lat) * 1e3
     info = infos[-1]
@@ -692,6 +975,22 @@ def main():
                            "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, problem.name),
                            "avg_launch_us": d["ms"] * 1e3 / max(d["launches"], 1),
                            "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1)}
+        res["roofline"]["bytes"] = ("algorithmic: every array read or written once, whether "
+                                    "HBM or the 256 MB Infinity Cache serves it")
+        if dom in ("cgs_dot", "cgs_update_norm"):
+            share = gs_hbm_share(counts_l3, shape_l3[0] * shape_l3[1], 16, dom)
+            if share is not None:
+                res["roofline"]["hbm_only_estimate"] = {
+                    "share_of_bytes": share, "achieved": d["GBps"] * share,
+                    "frac": d["GBps"] * share / HBM_PEAK_GBS,
+                    "model": "basis vectors older than the 200 MB recent window of bases above "
+                             "256 MB, per step of the recorded Krylov CSLP counts"}
+        # measured ceilings of this GPU (a plain copy, a read-only stream), taken
+        # after the timed region with the solver's memory released
+        ceil = bandwidth_ceilings(torch)
+        res["roofline"]["ceilings"] = ceil
+        res["roofline"]["frac_of_read_ceiling"] = d["GBps"] / ceil["read_GBps"]
+        res["roofline"]["frac_of_copy_ceiling"] = d["GBps"] / ceil["copy_GBps"]
         res["roofline"]["sampled_launches"] = d["launches"]
         res["roofline"]["sampling"] = "every %d-th launch of the class" % TIMING_EVERY
         res["kernel_classes"] = {c: {"est_ms_per_solve": v["ms"] * TIMING_EVERY / args.steps,
@@ -729,6 +1028,18 @@ def main():
             "outer_iters": infa[-1]["outer_iters"], "rel_res_true": infa[-1]["rel_res_true"],
             "rel_err_vs_fp64_solution": erra,
             "dtype": "f32 preconditioner incl. coarsest problem / f64 outer"}
+    if args.serving_leg > 0 and args.config == 1:
+        # a bounded run of the request stream (the serving workload), so the line
+        # also carries a serving measurement: requests over 257^2..2049^2 grids
+        torch.cuda.empty_cache()
+        srv = run_serving(args, args.serving_leg, args.rate)
+        res["serving"] = {key: srv[key] for key in (
+            "metric", "value", "unit", "offered_requests_per_s", "requests", "batching",
+            "config") if key in srv}
+        for key in ("p50_latency_ms", "p99_latency_ms", "mean_queue_wait_ms", "solves",
+                    "wall_s", "requests_per_s", "max_rel_res", "by_grid"):
+            if key in srv:
+                res["serving"][key] = srv[key]
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(problem, info, counts_l3)
     print(json.dumps(res), flush=True)

@@ -234,11 +234,13 @@ hm_status hm_get_timing(const hm_problem* p, int cls, double* ms, double* bytes,
 hm_status hm_set_basis_cache(hm_problem* p, double basis_bytes, double recent_bytes);
 
 /* Device-resident Krylov solves on small coarse levels (the GMRES of the Krylov
- * CSLP, Sec. 4.2, and GMRES coarsest multigrid solves): when a level's
- * ghost-extended copy fits in LDS (up to about 65 x 65 nodes in FP64), each
- * member's whole GMRES (operator, Gram-Schmidt, Givens rotations, stopping
- * test, back substitution, x = V y) runs in one workgroup, with one launch and
- * one host wait per solve instead of several launches and a wait per step.
+ * CSLP, Sec. 4.2, and GMRES coarsest multigrid solves): on a level of at most
+ * 1600 nodes whose ghost-extended copy fits in LDS (the 33 x 33 coarsest level
+ * of a 129^2 problem), each member's whole GMRES (operator, Gram-Schmidt,
+ * Givens rotations, stopping test, back substitution, x = V y) runs in one
+ * workgroup, with one launch and one host wait per solve instead of several
+ * launches and a wait per step.  Larger levels stay host-driven: there one
+ * compute unit streaming the basis is slower than the device-wide steps.
  * The same method and stopping rule (reading R11); rounding differs from the
  * host-driven path in the order of the sums.  enable = 1 (default) or 0 (every
  * level host-driven).  HM_ERR_ARG for a null problem. */

@@ -150,13 +150,20 @@ hipError_t launch_csr_spmv(int nrows, int ncols, const int* rowptr, const int* c
 // the column stride of the device Hessenberg H (cap + 2).
 struct SmallGmresArgs {
   static constexpr int kMaxLdh = 512;
+  // Largest level (nodes) taken by the one-workgroup solve.  One compute unit
+  // streams the basis, so the cost per step grows with the level while the
+  // host-driven steps spread over the device: measured per solve, the 33 x 33
+  // level of the 129^2 problem gains (12.0 -> 10.6 ms), the 65 x 65 level of a
+  // 257^2 problem loses (54 -> 99 ms), and so does a 76 x 126 multigrid coarsest
+  // grid in FP32.
+  static constexpr int kMaxNodes = 1600;
   int ldh = 0;
   int mgs = 0;
   int maxit[kMaxBatch] = {};
   double tol[kMaxBatch] = {};
 };
-// True when the level (operator d, basis capacity cap) fits the one-workgroup
-// solve: its ghost-extended copy in LDS.
+// True when the level (operator d, basis capacity cap) is taken by the
+// one-workgroup solve: at most kMaxNodes nodes, its ghost-extended copy in LDS.
 template <typename T>
 bool small_gmres_fits(const OpDesc<T>& d, int cap);
 // GMRES from x = 0 on d (wavenumber k) for the right-hand side b, basis V of

@@ -70,7 +70,7 @@ class Scheduler:
     (infos, solutions) pair per job of the group."""
 
     def __init__(self, execute, bytes_needed, budget_bytes, max_active=4, realtime=True,
-                 group_key=None, max_members=1, members=None):
+                 group_key=None, max_members=1, members=None, progress=None):
         if max_active < 1:
             raise ValueError("max_active must be >= 1")
         self.execute = execute
@@ -81,6 +81,7 @@ class Scheduler:
         self.group_key = group_key
         self.max_members = max(1, int(max_members))
         self.members = members or (lambda job: 1)
+        self.progress = progress       # called as progress(done, total) after each group
         self.events = []               # (time, kind, rid, in_use_bytes, active)
         self.groups = []               # rids of each admitted group, in admission order
 
@@ -141,6 +142,8 @@ class Scheduler:
                     state["error"] = e
                 self.events.append((clock(), "finish", group[0].rid, state["in_use"],
                                     state["active"]))
+                if self.progress is not None:
+                    self.progress(len(results), len(jobs))
                 cond.notify_all()
 
         pool = ThreadPoolExecutor(max_workers=self.max_active)

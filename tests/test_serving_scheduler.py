@@ -118,3 +118,14 @@ def test_grouping_takes_same_key_jobs_within_member_and_memory_limits():
                    members=lambda j: len(j.rhs))
     s2.run([gjob(i, 65) for i in range(5)])
     assert s2.groups == [[0, 1], [2, 3], [4]]
+
+
+def test_progress_callback_counts_every_request():
+    seen = []
+    ex = FakeExecutor()
+    s = Scheduler(ex, lambda j: j.meta["size"], budget_bytes=100, max_active=3, realtime=False,
+                  progress=lambda done, total: seen.append((done, total)))
+    s.run([job(i, 0.0, 10, work=0.005) for i in range(7)])
+    assert len(seen) == 7                        # one call per finished group (one job each)
+    assert [d for d, _ in seen] == sorted(d for d, _ in seen)
+    assert seen[-1] == (7, 7) and all(t == 7 for _, t in seen)
