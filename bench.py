@@ -243,7 +243,9 @@ def run_serving(args, n_requests, rate):
         (len(jobs), sum(len(j.rhs) for j in jobs), rate))
     ex = GpuExecutor()
     free, _ = torch.cuda.mem_get_info()
-    budget = int(0.8 * free)
+    # admission budget: a margin below the free memory for the allocator's
+    # rounding and for blocks cached at other sizes
+    budget = int(0.7 * free)
     # warm-up: one small request per grid class, not timed
     seen = set()
     for j in jobs:
@@ -293,7 +295,9 @@ def run_serving(args, n_requests, rate):
                         "max_members": 1 if args.no_batching else min(args.max_members, 16)},
            "config": {"workload": "serving stream (Poisson, random media, 257^2..2049^2)"},
            **summ, "by_grid": by_class,
-           "max_concurrent": max(e[4] for e in sched.events)}
+           "max_concurrent": max(e[4] for e in sched.events),
+           "level2_basis": {"%dx%d" % key[:2]: b for key, b in sorted(ex.basis.items())},
+           "level2_basis_regrows": ex.regrows, "allocator_retries": ex.oom_retries}
     return out
 
 
@@ -775,6 +779,8 @@ VARIANTS = [("MADP", {}),
             ("4 levels", {"levels": 4}),
             ("4 levels, W-cycle", {"levels": 4, "coarse_steps": 2}),
             ("4 levels, tol 0.3 on levels 2-3", {"levels": 4, "tol_levels": 3}),
+            ("5 levels", {"levels": 5}),
+            ("6 levels", {"levels": 6}),
             ("modified Gram-Schmidt in the Krylov CSLP", {"cslp_orth": 1})]
 
 
@@ -1037,7 +1043,8 @@ def main():
             "metric", "value", "unit", "offered_requests_per_s", "requests", "batching",
             "config") if key in srv}
         for key in ("p50_latency_ms", "p99_latency_ms", "mean_queue_wait_ms", "solves",
-                    "wall_s", "requests_per_s", "max_rel_res", "by_grid"):
+                    "wall_s", "requests_per_s", "max_rel_res", "by_grid", "level2_basis",
+                    "level2_basis_regrows", "allocator_retries"):
             if key in srv:
                 res["serving"][key] = srv[key]
     if not args.no_cpu_baseline:

@@ -52,7 +52,9 @@ typedef enum {
   HM_ERR_ARG = -1,        /* invalid argument (size, pointer, parameter)          */
   HM_ERR_NOMEM = -2,      /* workspace smaller than hm_workspace_bytes()          */
   HM_ERR_HIP = -3,        /* a HIP runtime call or kernel launch failed           */
-  HM_ERR_STATE = -4       /* call not valid in the problem's current state        */
+  HM_ERR_STATE = -4,      /* call not valid in the problem's current state        */
+  HM_ERR_BASIS = -5       /* a level-2 solve needed more basis vectors than the
+                             problem reserves (hm_config.level2_basis)            */
 } hm_status;
 
 /* Boundary condition on all four sides (Sec. 2.1).  HM_BC_DIRICHLET is the
@@ -109,7 +111,15 @@ typedef struct {
                             (the modified Gram-Schmidt of Algorithm 1, j+1
                             passes per step); same Krylov space and iterates in
                             exact arithmetic                                       */
-  int reserved[5];       /* must be zero                                            */
+  int level2_basis;      /* level-2 FGMRES basis vectors reserved in the workspace:
+                            0 = level2_maxit (default), else 1..level2_maxit.  A
+                            smaller basis shrinks the workspace (by 2 level-2
+                            vectors per step); a level-2 solve that reaches it
+                            before its tolerance and level2_maxit stops the call
+                            with HM_ERR_BASIS, and the caller re-creates the
+                            problem with a larger basis.  A call that succeeds
+                            returns the same results whatever the basis        */
+  int reserved[4];       /* must be zero                                            */
 } hm_config;
 
 enum { HM_ORTH_CLASSICAL = 0, HM_ORTH_MODIFIED = 1 };

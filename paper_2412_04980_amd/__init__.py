@@ -30,7 +30,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhelmdefl.so")
 
 HM_OK, HM_NOT_CONVERGED = 0, 1
-HM_ERR_ARG, HM_ERR_NOMEM, HM_ERR_HIP, HM_ERR_STATE = -1, -2, -3, -4
+HM_ERR_ARG, HM_ERR_NOMEM, HM_ERR_HIP, HM_ERR_STATE, HM_ERR_BASIS = -1, -2, -3, -4, -5
 HM_FP64, HM_MIXED_FP32, HM_MIXED_FP32_ALL = 0, 1, 2
 HM_BC_SOMMERFELD, HM_BC_DIRICHLET = 0, 1
 HM_ORTH_CLASSICAL, HM_ORTH_MODIFIED = 0, 1
@@ -68,7 +68,7 @@ class HmConfig(ctypes.Structure):
                 ("mg_nu_pre", ctypes.c_int), ("mg_nu_post", ctypes.c_int),
                 ("precision", ctypes.c_int), ("coarse_steps", ctypes.c_int),
                 ("tol_levels", ctypes.c_int), ("cslp_orth", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("level2_basis", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
     def replace(self, **kw):
         c = HmConfig()
@@ -144,7 +144,14 @@ def _load():
 _lib = _load()
 
 
+class BasisExhausted(HelmDeflError):
+    """A level-2 solve needed more basis vectors than the problem reserves
+    (config level2_basis): re-create the problem with a larger basis."""
+
+
 def _check(status):
+    if status == HM_ERR_BASIS:
+        raise BasisExhausted(status, _lib.hm_last_error().decode())
     if status < 0:
         raise HelmDeflError(status, _lib.hm_last_error().decode())
     return status

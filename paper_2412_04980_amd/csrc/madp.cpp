@@ -35,6 +35,10 @@ struct HipError : std::runtime_error {
 struct ArgError : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
+// a level-2 solve reached the reserved basis (hm_config.level2_basis)
+struct BasisError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
 
 #define HM_CHECK(...)                                                                      \
   do {                                                                                     \
@@ -695,7 +699,11 @@ static void fgmres_level(Ctx& c, const Act& a0, int lv, const cx<T>* b, cx<T>* x
   cx<T>* X = (cx<T>*)ws.X;
   cx<T>* w = (cx<T>*)ws.w;
   member_norms<T>(c, a0, b, N, ws.h);
-  std::vector<MemberKrylov> st = start_members<T>(c, a0, kind, maxit, tol, ws.cap, x, N);
+  // a basis smaller than the step cap (hm_config.level2_basis) limits the steps;
+  // a solve that needs more stops the call (BasisError) instead of returning a
+  // result the full basis would not give
+  const int lim = std::min(maxit, ws.cap);
+  std::vector<MemberKrylov> st = start_members<T>(c, a0, kind, lim, tol, ws.cap, x, N);
   if (st.empty()) return;
   std::vector<int> run, every;
   for (size_t t = 0; t < st.size(); ++t) {
@@ -744,7 +752,11 @@ static void fgmres_level(Ctx& c, const Act& a0, int lv, const cx<T>* b, cx<T>* x
       m.steps = j + 1;
       const bool broke = hc[j + 1].re <= 1e-14 * m.beta;
       if (!broke) scale.push_back(t);
-      if (broke || (m.tol >= 0 && est <= m.tol * m.beta) || j + 1 >= m.maxit) continue;
+      const bool met = m.tol >= 0 && est <= m.tol * m.beta;
+      if (!broke && !met && m.tol >= 0 && j + 1 >= m.maxit && m.maxit < maxit)
+        throw BasisError("a level-2 solve needs more than the " + std::to_string(ws.cap) +
+                         " basis vectors reserved (hm_config.level2_basis)");
+      if (broke || met || j + 1 >= m.maxit) continue;
       next.push_back(t);
     }
     if (!scale.empty())
@@ -959,6 +971,8 @@ static bool validate(const hm_config* c, std::string* why) {
   if (c->precision != HM_FP64 && c->precision != HM_MIXED_FP32 && c->precision != HM_MIXED_FP32_ALL)
     return bad("precision");
   if (c->outer_restart < 1 || c->outer_maxit < 1 || c->level2_maxit < 1) return bad("step caps");
+  if (c->level2_basis < 0 || c->level2_basis > c->level2_maxit)
+    return bad("level2_basis must be in [0, level2_maxit]");
   if (c->mg_nu_pre < 1 || c->mg_nu_post < 0) return bad("smoothing steps");
   if (!(c->tol_outer > 0) || !(c->tol_level2 > 0) || !(c->tol_cslp > 0) || !(c->maxit_coef > 0))
     return bad("tolerances");
@@ -1008,7 +1022,9 @@ static void plan(hm_problem* p, Carver& cv) {
       set_wide(D.M32, nx, ny, c.h, l, sig_m, c.bc);
     }
     if (l >= 2) {
-      D.fg.cap = tol_level(c, p->L, l) ? c.level2_maxit : c.coarse_steps;
+      D.fg.cap = !tol_level(c, p->L, l) ? c.coarse_steps
+                 : c.level2_basis > 0       ? c.level2_basis
+                                            : c.level2_maxit;
       D.fg.N = D.N;
       D.fg.V = cv.take<char>((size_t)(D.fg.cap + 1) * D.N * es);
       D.fg.X = cv.take<char>((size_t)D.fg.cap * D.N * es);
@@ -1335,6 +1351,9 @@ static hm_status guard(F&& f) {
   } catch (const HipError& e) {
     g_last_error = e.what();
     return HM_ERR_HIP;
+  } catch (const BasisError& e) {
+    g_last_error = e.what();
+    return HM_ERR_BASIS;
   } catch (const std::bad_alloc&) {
     g_last_error = "host allocation failed";
     return HM_ERR_NOMEM;
@@ -1863,6 +1882,7 @@ const char* hm_status_string(hm_status s) {
     case HM_ERR_NOMEM: return "workspace too small";
     case HM_ERR_HIP: return "HIP error";
     case HM_ERR_STATE: return "invalid state";
+    case HM_ERR_BASIS: return "level-2 basis exhausted";
   }
   return "unknown status";
 }

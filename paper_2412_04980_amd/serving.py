@@ -205,15 +205,38 @@ def summarize(results, wall_seconds):
     }
 
 
+def solve_with_regrow(run, basis, cap, exhausted):
+    """Calls run(basis) until it does not raise `exhausted`, doubling the
+    reserved level-2 basis each time (at most cap; 0 means cap already).
+    Returns (result, basis used, number of regrows)."""
+    grows = 0
+    while True:
+        try:
+            return run(basis), basis, grows
+        except exhausted:
+            if basis == 0 or basis >= cap:
+                raise
+            basis = min(2 * basis, cap)
+            grows += 1
+
+
 class GpuExecutor:
     """Runs one request on the GPU: uploads its medium, builds its hierarchy in a
     fresh workspace, solves every right-hand side, frees everything.  Each worker
     thread owns one stream (default priority).  run_group / group_bytes /
     group_key / members are the grouped counterparts for a Scheduler with
     grouping: the right-hand sides of the group's requests become the members
-    of lockstep batches of at most MAX_BATCH members."""
+    of lockstep batches of at most MAX_BATCH members.
 
-    def __init__(self, precision=None, keep_solutions=False, device="cuda:0", overrides=None):
+    Each grid class reserves a level-2 basis of level2_basis vectors (initially
+    `basis`, 0 = the full step cap) instead of the cap of 100: a solve that
+    needs more raises BasisExhausted, and the request is re-run on a problem
+    with twice the basis, which the class keeps from then on.  Results do not
+    depend on the basis; admission counts the basis the class has when the
+    group is admitted."""
+
+    def __init__(self, precision=None, keep_solutions=False, device="cuda:0", overrides=None,
+                 basis=16):
         import torch
 
         import paper_2412_04980_amd as hm
@@ -224,10 +247,37 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.overrides = dict(overrides or {})
         self._local = threading.local()
+        self._lock = threading.Lock()
+        self.basis0 = int(basis)
+        self.basis = {}                # grid class -> reserved level-2 basis
+        self.regrows = 0
+        self.oom_retries = 0
 
-    def config(self, job):
-        return self.hm.default_config(job.nx, job.ny, job.h, precision=self.precision,
-                                      **self.overrides)
+    def _basis(self, key):
+        with self._lock:
+            return self.basis.get(key, self.basis0)
+
+    def config(self, job, basis=None):
+        if basis is None:
+            basis = self._basis(self.group_key(job))
+        cfg = self.hm.default_config(job.nx, job.ny, job.h, precision=self.precision,
+                                     **self.overrides)
+        cfg.level2_basis = min(basis, cfg.level2_maxit)
+        return cfg
+
+    def _regrowing(self, job, run):
+        """run(cfg) with the class's basis, re-run with a larger one on
+        BasisExhausted; the class keeps the largest basis it needed."""
+        key = self.group_key(job)
+        cap = self.config(job, 0).level2_maxit
+        out, used, grows = solve_with_regrow(
+            lambda basis: self._retry_oom(lambda: run(self.config(job, basis))),
+            self._basis(key), cap, self.hm.BasisExhausted)
+        with self._lock:
+            self.regrows += grows
+            if used == 0 or used > self.basis.get(key, self.basis0):
+                self.basis[key] = used
+        return out
 
     def bytes_needed(self, job):
         n = job.nx * job.ny
@@ -255,21 +305,41 @@ class GpuExecutor:
         sols = [[None] * len(job.rhs) for job in jobs]
         with torch.cuda.stream(s):
             ks = [torch.from_numpy(job.k).to(self.device) for job in jobs]
-            cfg = self.config(jobs[0])
             for c0 in range(0, len(members), hm.MAX_BATCH):
                 chunk = members[c0:c0 + hm.MAX_BATCH]
-                bt = hm.create_batch(cfg, [ks[q] for q, _ in chunk], stream=s)
-                try:
-                    bs = [torch.from_numpy(jobs[q].rhs[r]).to(self.device) for q, r in chunk]
-                    us, out = hm.batch_solve(bt, bs, stream=s)
-                    for (q, r), u, d in zip(chunk, us, out):
-                        infos[q][r] = d
-                        if self.keep:
-                            sols[q][r] = u.cpu().numpy()
-                finally:
-                    s.synchronize()
-                    bt.close()
+
+                def run(cfg, chunk=chunk):
+                    bt = hm.create_batch(cfg, [ks[q] for q, _ in chunk], stream=s)
+                    try:
+                        bs = [torch.from_numpy(jobs[q].rhs[r]).to(self.device) for q, r in chunk]
+                        us, out = hm.batch_solve(bt, bs, stream=s)
+                        return [(u.cpu().numpy() if self.keep else None, d)
+                                for u, d in zip(us, out)]
+                    finally:
+                        s.synchronize()
+                        bt.close()
+
+                for (q, r), (u, d) in zip(chunk, self._regrowing(jobs[0], run)):
+                    infos[q][r] = d
+                    sols[q][r] = u
         return [(infos[q], sols[q] if self.keep else None) for q in range(len(jobs))]
+
+    def _retry_oom(self, fn, attempts=600, pause=0.05):
+        """fn(), retried while the device allocator reports out of memory: the
+        admission budget counts workspace bytes, but the caching allocator can
+        hold them in blocks of other sizes (workspaces of other classes and
+        batch sizes), so a fresh workspace may not fit until cached blocks are
+        released and other groups finish."""
+        for i in range(attempts):
+            try:
+                return fn()
+            except self.torch.OutOfMemoryError:
+                if i + 1 == attempts:
+                    raise
+                with self._lock:
+                    self.oom_retries += 1
+                self.torch.cuda.empty_cache()
+                time.sleep(pause)
 
     def _stream(self):
         s = getattr(self._local, "stream", None)
@@ -284,18 +354,24 @@ class GpuExecutor:
         infos, sols = [], []
         with torch.cuda.stream(s):
             k = torch.from_numpy(job.k).to(self.device)
-            prob = hm.create_problem(self.config(job), k, stream=s)
-            try:
-                u = torch.empty(job.nx * job.ny, dtype=torch.complex128, device=self.device)
-                for rhs in job.rhs:
-                    b = torch.from_numpy(rhs).to(self.device)
-                    _, info = hm.fgmres_solve(prob, b, out=u, stream=s)
-                    infos.append(info)
-                    if self.keep:
-                        sols.append(u.cpu().numpy())
-            finally:
-                s.synchronize()
-                prob.close()
+
+            def run(cfg):
+                infos, sols = [], []
+                prob = hm.create_problem(cfg, k, stream=s)
+                try:
+                    u = torch.empty(job.nx * job.ny, dtype=torch.complex128, device=self.device)
+                    for rhs in job.rhs:
+                        b = torch.from_numpy(rhs).to(self.device)
+                        _, info = hm.fgmres_solve(prob, b, out=u, stream=s)
+                        infos.append(info)
+                        if self.keep:
+                            sols.append(u.cpu().numpy())
+                finally:
+                    s.synchronize()
+                    prob.close()
+                return infos, sols
+
+            infos, sols = self._regrowing(job, run)
         return infos, (sols if self.keep else None)
 
 

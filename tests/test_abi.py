@@ -47,7 +47,8 @@ def test_workspace_bytes_validation():
     for bad in (dict(nx=130), dict(levels=1), dict(levels=7), dict(h=-1.0),
                 dict(precision=5), dict(outer_restart=0), dict(tol_outer=0.0), dict(bc=2),
                 dict(coarse_steps=0), dict(coarse_steps=17), dict(tol_levels=0),
-                dict(tol_levels=7), dict(cslp_orth=2), dict(cslp_orth=-1)):
+                dict(tol_levels=7), dict(cslp_orth=2), dict(cslp_orth=-1),
+                dict(level2_basis=-1), dict(level2_basis=101)):
         c = hm.default_config(129, 129, 1 / 128)
         for key, val in bad.items():
             setattr(c, key, val)
@@ -86,10 +87,48 @@ def test_variant_fields_size_the_coarse_workspaces():
     assert base < w < t
 
 
+def test_level2_basis_sizes_the_level2_workspace():
+    """level2_basis reserves fewer level-2 vectors: 0 is the step cap, and the
+    workspace shrinks by two level-2 vectors (basis V and its preconditioned X)
+    per step given up, plus the reduction partials sized by the largest basis."""
+    import paper_2412_04980_amd as hm
+    c = hm.default_config(257, 257, 1 / 256)
+    assert c.level2_basis == 0 and c.level2_maxit == 100
+    full = hm.workspace_bytes(c)
+    assert hm.workspace_bytes(hm.default_config(257, 257, 1 / 256, level2_basis=100)) == full
+    small = hm.workspace_bytes(hm.default_config(257, 257, 1 / 256, level2_basis=20))
+    n2 = 129 * 129
+    assert full - small >= 80 * 2 * 16 * n2
+    assert full - small < 80 * 2 * 16 * n2 + 2048 * 100 * 16
+
+
+def test_solve_with_regrow_doubles_the_basis_until_it_suffices():
+    from paper_2412_04980_amd.serving import solve_with_regrow
+
+    class Exhausted(Exception):
+        pass
+
+    tried = []
+
+    def run(basis):
+        tried.append(basis)
+        if 0 < basis < 11:                        # 0: the whole step cap
+            raise Exhausted()
+        return "ok"
+
+    assert solve_with_regrow(run, 2, 100, Exhausted) == ("ok", 16, 3)
+    assert tried == [2, 4, 8, 16]
+    tried.clear()
+    assert solve_with_regrow(run, 0, 100, Exhausted) == ("ok", 0, 0)
+    with pytest.raises(Exhausted):                # the cap itself is too small
+        solve_with_regrow(run, 3, 6, Exhausted)
+
+
 def test_status_strings():
     import paper_2412_04980_amd as hm
     assert hm.status_string(0) == "ok"
     assert hm.status_string(-2) == "workspace too small"
+    assert hm.status_string(hm.HM_ERR_BASIS) == "level-2 basis exhausted"
 
 
 def test_matvec_entry_points_reject_bad_sizes_on_the_host():
