@@ -49,7 +49,8 @@ TIMING_CLASSES = {HM_TK_CGS_DOT: "cgs_dot", HM_TK_CGS_UPDATE: "cgs_update_norm",
 EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_precond_apply",
             "hm_fgmres_solve", "hm_apply_operator", "hm_level_shape", "hm_set_replay",
             "hm_get_counts", "hm_reset_counts", "hm_set_timing", "hm_get_timing",
-            "hm_set_basis_cache", "hm_set_small_krylov", "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
+            "hm_set_basis_cache", "hm_set_small_krylov", "hm_set_krylov_pairs",
+            "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
             "hm_batch_workspace_bytes", "hm_create_batch", "hm_batch_solve", "hm_batch_member",
             "hm_destroy_batch", "hm_residual_workspace_bytes", "hm_residual",
             "hm_residual_noalloc",
@@ -117,6 +118,7 @@ def _load():
                               ctypes.POINTER(ctypes.c_long)]),
         "hm_set_basis_cache": (I, [P, D, D]),
         "hm_set_small_krylov": (I, [P, I]),
+        "hm_set_krylov_pairs": (I, [P, I]),
         "hm_destroy_problem": (I, [P]),
         "hm_matfree_apply": (I, [I, I, D, P, P, P, P]),
         "hm_csr_assemble": (I, [I, I, D, P, P, P, P, P]),
@@ -317,6 +319,11 @@ def reset_counts(prob):
 def set_small_krylov(prob, enable=True):
     """Device-resident (one workgroup) GMRES on small coarse levels, on or off."""
     _check(_lib.hm_set_small_krylov(prob.handle, 1 if enable else 0))
+
+
+def set_krylov_pairs(prob, enable=True):
+    """Two Arnoldi steps per read of the basis in the Krylov CSLP, on or off."""
+    _check(_lib.hm_set_krylov_pairs(prob.handle, 1 if enable else 0))
 
 
 def set_basis_cache(prob, basis_bytes=-1.0, recent_bytes=-1.0):

@@ -1168,6 +1168,125 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
   }
 }
 
+// ---- two Arnoldi steps per sweep over the basis --------------------------------
+// Pass A: the partial dots of z and y with NG left vectors vp[0..NG-1] over one
+// chunk, each thread two rows per pass (all loads of the two rows in flight).
+template <typename T, int NG, bool NTL>
+__device__ __forceinline__ void dot2_rows(const cx<T>* const* vp, const cx<T>* __restrict__ zv,
+                                          const cx<T>* __restrict__ yv, size_t lo, size_t hi,
+                                          double (*re)[G], double (*im)[G]) {
+  size_t i = lo + threadIdx.x;
+  for (; i + NT < hi; i += 2 * NT) {
+    const cx<T> za = zv[i], zb = zv[i + NT], ya = yv[i], yb = yv[i + NT];
+    cx<T> va[NG], vb[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      va[g] = NTL ? load_stream(vp[g] + i) : vp[g][i];
+      vb[g] = NTL ? load_stream(vp[g] + i + NT) : vp[g][i + NT];
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      dot_acc(re[0][g], im[0][g], va[g], za);
+      dot_acc(re[0][g], im[0][g], vb[g], zb);
+      dot_acc(re[1][g], im[1][g], va[g], ya);
+      dot_acc(re[1][g], im[1][g], vb[g], yb);
+    }
+  }
+  if (i < hi) {
+    const cx<T> za = zv[i], ya = yv[i];
+    cx<T> v[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) v[g] = NTL ? load_stream(vp[g] + i) : vp[g][i];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      dot_acc(re[0][g], im[0][g], v[g], za);
+      dot_acc(re[1][g], im[1][g], v[g], ya);
+    }
+  }
+}
+
+// Pass A of a pair of Arnoldi steps (z = M v_j, y = M z): the dots of z and y
+// with V_0..V_{m-1} and with z and y themselves, in one read of the basis.
+// Block = (chunk, group); group gi < ngv holds V_{4gi}..V_{4gi+3}, group ngv
+// holds (z, y).  Value r (m + 2) + i for right vector r (0: z, 1: y) and left
+// vector i (V_i for i < m, then z, y): partials[value * nchunks + chunk].  The
+// chunks, the XCD-aware block order and the load policy are those of k_multidot.
+template <typename T, bool STREAM>
+__global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, size_t ldv, int m,
+                                                  const cx<T>* __restrict__ zv,
+                                                  const cx<T>* __restrict__ yv, size_t n,
+                                                  size_t clen, c128* __restrict__ partials,
+                                                  int nchunks, int recent, Batch z) {
+  __shared__ double sh[NT / 64][4 * G];
+  HM_MEMBER(V); HM_MEMBER(zv); HM_MEMBER(yv); HM_MEMBER(partials);
+  const int ngv = (m + G - 1) / G, ngroups = ngv + 1;
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+  const int chunk = (local / ngroups) * 8 + xcd;
+  const int gi = local % ngroups;
+  const size_t lo = (size_t)chunk * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double re[2][G], im[2][G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) { re[0][g] = im[0][g] = re[1][g] = im[1][g] = 0; }
+  int first, gm;                                 // first value index, left vectors
+  if (gi < ngv) {
+    const int i0 = gi * G;
+    gm = m - i0 < G ? m - i0 : G;
+    first = i0;
+    const bool ntl = STREAM && i0 + gm <= m - recent;
+    const cx<T>* vp[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) vp[g] = V + (size_t)(i0 + (g < gm ? g : 0)) * ldv;
+    if (gm == 4) {
+      if (ntl) dot2_rows<T, 4, true>(vp, zv, yv, lo, hi, re, im);
+      else dot2_rows<T, 4, false>(vp, zv, yv, lo, hi, re, im);
+    } else if (gm == 3) {
+      if (ntl) dot2_rows<T, 3, true>(vp, zv, yv, lo, hi, re, im);
+      else dot2_rows<T, 3, false>(vp, zv, yv, lo, hi, re, im);
+    } else if (gm == 2) {
+      if (ntl) dot2_rows<T, 2, true>(vp, zv, yv, lo, hi, re, im);
+      else dot2_rows<T, 2, false>(vp, zv, yv, lo, hi, re, im);
+    } else {
+      if (ntl) dot2_rows<T, 1, true>(vp, zv, yv, lo, hi, re, im);
+      else dot2_rows<T, 1, false>(vp, zv, yv, lo, hi, re, im);
+    }
+  } else {
+    gm = 2;
+    first = m;
+    const cx<T>* vp[2] = {zv, yv};
+    dot2_rows<T, 2, false>(vp, zv, yv, lo, hi, re, im);
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      re[r][g] = wave_sum(re[r][g]);
+      im[r][g] = wave_sum(im[r][g]);
+    }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        sh[wid][2 * (r * G + g)] = re[r][g];
+        sh[wid][2 * (r * G + g) + 1] = im[r][g];
+      }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * G) {
+    const int r = threadIdx.x / G, g = threadIdx.x - r * G;
+    if (g < gm) {
+      double sr = 0, si = 0;
+      for (int w2 = 0; w2 < NT / 64; ++w2) {
+        sr += sh[w2][2 * (r * G + g)];
+        si += sh[w2][2 * (r * G + g) + 1];
+      }
+      partials[(size_t)(r * (m + 2) + first + g) * nchunks + chunk] = mk(sr, si);
+    }
+  }
+}
+
 // out[i] = sum_c partials[i*nchunks + c]; sqrt_re: out = sqrt(re)
 __global__ void __launch_bounds__(NT) k_final(const c128* __restrict__ partials, int nchunks,
                                               c128* __restrict__ out, int sqrt_re,
@@ -1293,6 +1412,69 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
     if (two) {
       const cx<T> n1 = mk((T)((double)w1.re - re1), (T)((double)w1.im - im1));
       w[i2] = n1;
+      acc = fma((double)n1.re, (double)n1.re, acc);
+      acc = fma((double)n1.im, (double)n1.im, acc);
+    }
+  }
+  const c128 s = block_sum(acc, 0.0, sh);
+  if (threadIdx.x == 0) partials[chunk] = s;
+}
+
+// Pass B of a pair of Arnoldi steps, one read of the basis:
+//   v_new = ca[m] z + sum_i ca[i] V_i       (written to V_m)
+//   w'    = ca[m] y + cg[m] z + sum_i cg[i] V_i   (written over z)
+// with the partial ||w'||^2 of one chunk; every thread takes two elements per
+// pass.  Chunks and load policy as k_cgs_update_norm.
+template <typename T, bool STREAM>
+__global__ void __launch_bounds__(NT) k_cgs_update2(cx<T>* __restrict__ zv,
+                                                    const cx<T>* __restrict__ yv,
+                                                    cx<T>* __restrict__ V, size_t ldv, int m,
+                                                    const c128* __restrict__ ca,
+                                                    const c128* __restrict__ cg, size_t n,
+                                                    size_t clen, c128* __restrict__ partials,
+                                                    int recent, Batch z) {
+  __shared__ double sh[2 * NT / 64];
+  HM_MEMBER(zv); HM_MEMBER(yv); HM_MEMBER(V); HM_MEMBER(ca); HM_MEMBER(cg); HM_MEMBER(partials);
+  const int chunk = (int)blockIdx.x;
+  const size_t lo = (size_t)chunk * clen;
+  const size_t hi = lo + clen < n ? lo + clen : n;
+  const c128 az = ca[m], gz = cg[m];
+  cx<T>* __restrict__ vnew = V + (size_t)m * ldv;
+  double acc = 0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += 2 * NT) {
+    const size_t i2 = i + NT;
+    const bool two = i2 < hi;
+    const cx<T> z0 = zv[i], y0 = yv[i];
+    const cx<T> z1 = two ? zv[i2] : mk(T(0), T(0)), y1 = two ? yv[i2] : mk(T(0), T(0));
+    double vr0 = 0, vi0 = 0, wr0 = 0, wi0 = 0, vr1 = 0, vi1 = 0, wr1 = 0, wi1 = 0;
+#pragma unroll 4
+    for (int j = 0; j < m; ++j) {
+      const c128 a = ca[j], c = cg[j];
+      const bool old = STREAM && j < m - recent;
+      const cx<T> v0 = old ? load_stream(V + (size_t)j * ldv + i) : V[(size_t)j * ldv + i];
+      upd_acc(vr0, vi0, a, v0);
+      upd_acc(wr0, wi0, c, v0);
+      if (two) {
+        const cx<T> v1 = old ? load_stream(V + (size_t)j * ldv + i2) : V[(size_t)j * ldv + i2];
+        upd_acc(vr1, vi1, a, v1);
+        upd_acc(wr1, wi1, c, v1);
+      }
+    }
+    upd_acc(vr0, vi0, az, z0);
+    upd_acc(wr0, wi0, az, y0);
+    upd_acc(wr0, wi0, gz, z0);
+    vnew[i] = mk((T)vr0, (T)vi0);
+    const cx<T> n0 = mk((T)wr0, (T)wi0);
+    zv[i] = n0;
+    acc = fma((double)n0.re, (double)n0.re, acc);
+    acc = fma((double)n0.im, (double)n0.im, acc);
+    if (two) {
+      upd_acc(vr1, vi1, az, z1);
+      upd_acc(wr1, wi1, az, y1);
+      upd_acc(wr1, wi1, gz, z1);
+      vnew[i2] = mk((T)vr1, (T)vi1);
+      const cx<T> n1 = mk((T)wr1, (T)wi1);
+      zv[i2] = n1;
       acc = fma((double)n1.re, (double)n1.re, acc);
       acc = fma((double)n1.im, (double)n1.im, acc);
     }
@@ -2171,6 +2353,48 @@ hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t 
   return hipGetLastError();
 }
 
+// Pass A of a pair of Arnoldi steps and its final sums: out[r (m + 2) + i] =
+// (left vector i)^H (right vector r), left vectors V_0..V_{m-1}, z, y; right
+// vectors z, y (also to the pinned host_out).
+template <typename T>
+hipError_t launch_multidot2(const cx<T>* V, size_t ldv, int m, const cx<T>* zv, const cx<T>* yv,
+                            size_t n, RedBuf rb, c128* out, c128* host_out, hipStream_t s,
+                            const Batch& z, const CachePolicy& cp) {
+  if (m <= 0) return hipErrorInvalidValue;
+  const size_t clen = multidot_chunk_len(n, m + G);
+  const int nch = (int)(((n + clen - 1) / clen + 7) & ~(size_t)7);
+  const dim3 g = zgrid(((m + G - 1) / G + 1) * nch, z);
+  const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
+  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis)
+    k_multidot2<T, true><<<g, NT, 0, s>>>(V, ldv, m, zv, yv, n, clen, rb.partials, nch, recent, z);
+  else
+    k_multidot2<T, false><<<g, NT, 0, s>>>(V, ldv, m, zv, yv, n, clen, rb.partials, nch, recent,
+                                           z);
+  k_final<<<zgrid(2 * (m + 2), z), NT, 0, s>>>(rb.partials, nch, out, 0, host_out, z);
+  return hipGetLastError();
+}
+
+// Pass B of a pair of Arnoldi steps and the norm of w' (sqrt to norm_out and
+// the pinned host_out).
+template <typename T>
+hipError_t launch_cgs_update2(cx<T>* zv, const cx<T>* yv, cx<T>* V, size_t ldv, int m,
+                              const c128* ca, const c128* cg, size_t n, RedBuf rb,
+                              c128* norm_out, c128* host_out, hipStream_t s, const Batch& z,
+                              const CachePolicy& cp) {
+  const int nch = update_chunks(n, rb);
+  const size_t clen = update_chunk_len(n);
+  const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
+  const dim3 g = zgrid(nch, z);
+  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis)
+    k_cgs_update2<T, true><<<g, NT, 0, s>>>(zv, yv, V, ldv, m, ca, cg, n, clen, rb.partials,
+                                            recent, z);
+  else
+    k_cgs_update2<T, false><<<g, NT, 0, s>>>(zv, yv, V, ldv, m, ca, cg, n, clen, rb.partials,
+                                             recent, z);
+  k_final<<<zgrid(1, z), NT, 0, s>>>(rb.partials, nch, norm_out, 1, host_out, z);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_cgs_update_norm(cx<T>* w, const cx<T>* V, size_t ldv, int m, const c128* h,
                                   size_t n, RedBuf rb, c128* out, hipStream_t s) {
@@ -2310,6 +2534,12 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
   template hipError_t launch_cgs_update_partial<T>(cx<T>*, const cx<T>*, size_t, int, const c128*, \
                                                    size_t, RedBuf, hipStream_t, const Batch&,       \
                                                    const CachePolicy&);                             \
+  template hipError_t launch_multidot2<T>(const cx<T>*, size_t, int, const cx<T>*, const cx<T>*,    \
+                                          size_t, RedBuf, c128*, c128*, hipStream_t, const Batch&,  \
+                                          const CachePolicy&);                                      \
+  template hipError_t launch_cgs_update2<T>(cx<T>*, const cx<T>*, cx<T>*, size_t, int,             \
+                                            const c128*, const c128*, size_t, RedBuf, c128*, c128*, \
+                                            hipStream_t, const Batch&, const CachePolicy&);         \
   template hipError_t launch_stencil_scaled<T>(const OpDesc<T>&, const cx<T>*, const T*,            \
                                                const c128*, cx<T>*, cx<T>*, hipStream_t,            \
                                                const Batch&);                                       \

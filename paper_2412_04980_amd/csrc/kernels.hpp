@@ -221,6 +221,21 @@ hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m
                                      size_t n, RedBuf rb, hipStream_t s,
                                      const Batch& z = Batch(),
                                      const CachePolicy& cp = CachePolicy());
+// Two Arnoldi steps per sweep over the basis (z = M v_j, y = M z).  Pass A:
+// out[r (m + 2) + i] = (left i)^H (right r) for the left vectors V_0..V_{m-1},
+// z, y and the right vectors z (r = 0), y (r = 1), also to host_out.  Needs
+// 2 (m + 2) kMaxChunks partials.
+template <typename T>
+hipError_t launch_multidot2(const cx<T>* V, size_t ldv, int m, const cx<T>* zv, const cx<T>* yv,
+                            size_t n, RedBuf rb, c128* out, c128* host_out, hipStream_t s,
+                            const Batch& z = Batch(), const CachePolicy& cp = CachePolicy());
+// Pass B: V_m = ca[m] z + sum_{i<m} ca[i] V_i ; z <- ca[m] y + cg[m] z +
+// sum_{i<m} cg[i] V_i ; norm_out[0] = host_out[0] = ||z|| (real part).
+template <typename T>
+hipError_t launch_cgs_update2(cx<T>* zv, const cx<T>* yv, cx<T>* V, size_t ldv, int m,
+                              const c128* ca, const c128* cg, size_t n, RedBuf rb,
+                              c128* norm_out, c128* host_out, hipStream_t s,
+                              const Batch& z = Batch(), const CachePolicy& cp = CachePolicy());
 // sum of the partials written by launch_cgs_update_partial over a vector of length n
 hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,
                                     c128* host_out = nullptr, const Batch& z = Batch());

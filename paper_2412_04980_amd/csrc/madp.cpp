@@ -225,6 +225,7 @@ struct hm_problem {
   CachePolicy cache;
   // small coarse levels solved by one workgroup per member (hm_set_small_krylov)
   bool small_krylov = true;
+  bool krylov_pairs = true;    // classical Gram-Schmidt: two Arnoldi steps per basis read
   // optional per-kernel-class timing with HIP events on the problem's stream
   unsigned timing_mask = 0;
   int timing_every = 1;                 // bracket every n-th launch of a class
@@ -483,12 +484,150 @@ static void gmres_small(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
   }
 }
 
+// The same GMRES with classical Gram-Schmidt, two Arnoldi steps per read of
+// the basis.  For the pair (j, j+1), z = M v_j and y = M z.  Pass A takes
+// [V_0..V_j, z, y]^H [z, y] in one read of the basis, which gives step j's
+// column a = V^H z with b_j^2 = z^H z - |a|^2 (b_j = ||z - V a||), and step
+// j+1's column without forming z' = M v_{j+1}: the Arnoldi relation
+// M V_{0..j-1} = V_{0..j} H makes M V a = V g + a_j z (g = H a_{0..j-1}), so
+//   V^H z' = (c - g - a_j a) / b_j,   v_{j+1}^H z' = (z^H y - a^H c) / b_j^2 - a_j
+// with c = V^H y.  Pass B forms v_{j+1} = (z - V a) / b_j and
+// w' = z' - [V, v_{j+1}] h' in one read of the basis, with ||w'||.  In exact
+// arithmetic these are the iterates of one-step classical Gram-Schmidt; the
+// basis is read once per step instead of twice.  A member that stops at the
+// first step of a pair, or whose step limit ends there, takes no pass B.
+template <typename T>
+static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
+                        int maxit, double tol, int kind, const cx<T>* b, cx<T>* x) {
+  hm_problem* p = c.p;
+  const size_t N = ws.N;
+  cx<T>* V = (cx<T>*)ws.V;
+  cx<T>* wb[2] = {(cx<T>*)ws.w, (cx<T>*)ws.w2};
+  member_norms<T>(c, a0, b, N, ws.h);
+  std::vector<MemberKrylov> st = start_members<T>(c, a0, kind, maxit, tol, ws.cap, x, N);
+  if (st.empty()) return;
+  const size_t ld = (size_t)ws.cap + 2;
+  for (const auto& m : st)
+    if ((size_t)(m.maxit + 2) * ld > p->host_H_cap) throw ArgError("Hessenberg mirror too small");
+  const double es = (double)sizeof(cx<T>);
+  const int tk_op = op.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE;
+  // raw Hessenberg columns of every member (column i at i * ld)
+  std::vector<std::vector<c128>> Hh(st.size(), std::vector<c128>(ld * (size_t)ws.cap));
+  std::vector<int> run;
+  for (size_t t = 0; t < st.size(); ++t)
+    if (st[t].maxit > 0) run.push_back((int)t);
+  const cx<T>* src = b;                                  // v_j = src / s_j
+  for (int j = 0; !run.empty(); j += 2) {
+    const Batch z = members(c, members_of(st, run));
+    const double nm = (double)run.size();
+    const c128* sc = j == 0 ? ws.h : ws.H + (size_t)(j - 1) * ld + j;
+    cx<T>* zb = src == wb[0] ? wb[1] : wb[0];
+    cx<T>* yb = src == b ? wb[1] : (cx<T>*)src;         // src is consumed by the first apply
+    const int m = j + 1;
+    timed(p, tk_op, nm * 3.5 * es * N, [&] {
+      return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, zb, p->s, z);
+    });
+    timed(p, tk_op, nm * 2.5 * es * N, [&] {
+      return launch_stencil<T>(op, ST_APPLY, zb, k, nullptr, yb, T(0), p->s, z);
+    });
+    timed(p, HM_TK_CGS_DOT, nm * (m + 2) * es * N, [&] {
+      return launch_multidot2<T>(V, N, m, zb, yb, N, rbuf(p, N), ws.H + (size_t)j * ld,
+                                 p->host_H + (size_t)j * ld, p->s, z, p->cache);
+    });
+    wait_stream(c);
+    // step j for every member; the coefficients of pass B for those that go on
+    std::vector<int> pair;
+    for (int t : run) {
+      MemberKrylov& mk_ = st[t];
+      const c128* d = c.mem[mk_.i]->host_H + (size_t)j * ld;
+      const c128* dz = d;                                  // [V; z; y]^H z
+      const c128* dy = d + (m + 2);                        // [V; z; y]^H y
+      std::vector<c128>& H = Hh[t];
+      c128* col = H.data() + (size_t)j * ld;
+      double aa = 0;
+      for (int i = 0; i < m; ++i) {
+        col[i] = dz[i];
+        aa += dz[i].re * dz[i].re + dz[i].im * dz[i].im;
+      }
+      const double b2 = dz[m].re - aa;                     // ||z - V a||^2
+      const double bj = b2 > 0 ? std::sqrt(b2) : 0.0;
+      col[m] = mk(bj, 0.0);
+      const double est = mk_.lsq.add(j, col);
+      mk_.steps = j + 1;
+      const bool broke = bj <= 1e-14 * mk_.beta;
+      if (broke || (mk_.tol >= 0 && est <= mk_.tol * mk_.beta) || j + 1 >= mk_.maxit) continue;
+      // step j+1's column from the Arnoldi relation, and pass B's coefficients
+      std::vector<c128> g(m, mk(0.0, 0.0));
+      for (int i = 0; i + 1 < m; ++i) {                    // g = H_{0..j, 0..j-1} a_{0..j-1}
+        const c128* hc = H.data() + (size_t)i * ld;
+        for (int r = 0; r <= i + 1; ++r) g[r] = g[r] + hc[r] * dz[i];
+      }
+      const c128 aj = dz[j];
+      c128 ac = mk(0.0, 0.0);                              // a^H c
+      for (int i = 0; i < m; ++i) ac = ac + cmulc(dz[i], dy[i]);
+      c128* col1 = H.data() + (size_t)(j + 1) * ld;
+      const double ib = 1.0 / bj;
+      for (int i = 0; i < m; ++i) col1[i] = ib * (dy[i] - g[i] - aj * dz[i]);
+      const c128 hn = (ib * ib) * (dy[m] - ac) - aj;       // v_{j+1}^H z'
+      col1[m] = hn;
+      // pinned staging: this pair's mirror columns, whose dots are no longer
+      // read (a is taken from the host copy col): ca then cg
+      c128* ca = c.mem[mk_.i]->host_H + (size_t)j * ld;
+      c128* cg = ca + ld;
+      for (int i = 0; i < m; ++i) {
+        ca[i] = (-ib) * col[i];
+        cg[i] = (-ib) * g[i] - col1[i] + col[i] * (ib * hn);
+      }
+      ca[m] = mk(ib, 0.0);
+      cg[m] = (-ib) * (aj + hn);
+      pair.push_back(t);
+    }
+    if (pair.empty()) break;
+    for (int t : pair) {
+      hm_problem* q = c.mem[st[t].i];
+      char* dev = (char*)(ws.H + (size_t)j * ld) + (long long)st[t].i * c.dz;
+      HM_CHECK(hipMemcpyAsync(dev, q->host_H + (size_t)j * ld, sizeof(c128) * (ld + m + 1),
+                              hipMemcpyHostToDevice, p->s));
+    }
+    const Batch zp = members(c, members_of(st, pair));
+    const double np = (double)pair.size();
+    timed(p, HM_TK_CGS_UPDATE, np * (m + 4) * es * N, [&] {
+      return launch_cgs_update2<T>(zb, yb, V, N, m, ws.H + (size_t)j * ld,
+                                   ws.H + (size_t)(j + 1) * ld, N, rbuf(p, N),
+                                   ws.H + (size_t)(j + 1) * ld + j + 2,
+                                   p->host_H + (size_t)(j + 1) * ld + j + 2, p->s, zp, p->cache);
+    });
+    wait_stream(c);
+    std::vector<int> next;
+    for (int t : pair) {
+      MemberKrylov& mk_ = st[t];
+      c128* col1 = Hh[t].data() + (size_t)(j + 1) * ld;
+      col1[j + 2] = c.mem[mk_.i]->host_H[(size_t)(j + 1) * ld + j + 2];
+      const double est = mk_.lsq.add(j + 1, col1);
+      mk_.steps = j + 2;
+      const bool broke = col1[j + 2].re <= 1e-14 * mk_.beta;
+      if (broke || (mk_.tol >= 0 && est <= mk_.tol * mk_.beta) || j + 2 >= mk_.maxit) continue;
+      next.push_back(t);
+    }
+    run.swap(next);
+    src = zb;                                              // w' of pass B
+  }
+  finish_members<T>(c, st, kind, V, N, x, 0);
+}
+
 template <typename T>
 static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
                       int maxit, double tol, int kind, const cx<T>* b, cx<T>* x) {
   hm_problem* p = c.p;
   if (p->small_krylov && small_gmres_fits<T>(op, ws.cap)) {
     gmres_small<T>(c, a0, op, k, ws, maxit, tol, kind, b, x);
+    return;
+  }
+  // the paired steps take step j+1's column from relations that hold to the
+  // basis's orthogonality: FP64 levels only (with an FP32 basis the k = 200
+  // solve took one outer step more and moved 2e-5 from the FP64 solution)
+  if (p->krylov_pairs && p->cfg.cslp_orth == HM_ORTH_CLASSICAL && sizeof(T) == sizeof(double)) {
+    gmres_pairs<T>(c, a0, op, k, ws, maxit, tol, kind, b, x);
     return;
   }
   const size_t N = ws.N;
@@ -1081,9 +1220,9 @@ static void plan(hm_problem* p, Carver& cv) {
         H.gm.w = cv.take<char>(last.N * es);
         H.gm.w2 = cv.take<char>(last.N * es);
         H.gm.h = cv.take<c128>(H.maxit + 2);
-        H.gm.H = cv.take<c128>((size_t)(H.maxit + 2) * H.maxit);
+        H.gm.H = cv.take<c128>((size_t)(H.maxit + 2) * (H.maxit + 2));
         mmax = std::max(mmax, H.maxit + 2);
-        p->host_H_cap = std::max(p->host_H_cap, (size_t)(H.maxit + 2) * H.maxit);
+        p->host_H_cap = std::max(p->host_H_cap, (size_t)(H.maxit + 2) * (H.maxit + 2));
       }
     } else {
       D.cslp_maxit = krylov_maxit(D.N, c.maxit_coef);
@@ -1093,9 +1232,9 @@ static void plan(hm_problem* p, Carver& cv) {
       D.cslp.w = cv.take<char>(D.N * es);
       D.cslp.w2 = cv.take<char>(D.N * es);
       D.cslp.h = cv.take<c128>(D.cslp_maxit + 2);
-      D.cslp.H = cv.take<c128>((size_t)(D.cslp_maxit + 2) * D.cslp_maxit);
+      D.cslp.H = cv.take<c128>((size_t)(D.cslp_maxit + 2) * (D.cslp_maxit + 2));
       mmax = std::max(mmax, D.cslp_maxit + 2);
-      p->host_H_cap = std::max(p->host_H_cap, (size_t)(D.cslp_maxit + 2) * D.cslp_maxit);
+      p->host_H_cap = std::max(p->host_H_cap, (size_t)(D.cslp_maxit + 2) * (D.cslp_maxit + 2));
     }
     if (l < p->L) {
       nx = (nx - 1) / 2 + 1;
@@ -1115,7 +1254,8 @@ static void plan(hm_problem* p, Carver& cv) {
     p->pin_v = cv.take<c64>(D1.N);
     p->pin_x = cv.take<c64>(D1.N);
   }
-  p->rb.partials = cv.take<c128>((size_t)kMaxChunks * (mmax + 2));
+  // two Arnoldi steps per sweep take 2 (m + 2) dots per reduction
+  p->rb.partials = cv.take<c128>((size_t)kMaxChunks * (2 * mmax + 4));
   p->rb.nchunks = 0;   // chosen per reduction from its length (rbuf)
   p->scal = cv.take<c128>(16);
   p->coef_cap = mmax + 2;
@@ -1863,6 +2003,12 @@ hm_status hm_set_basis_cache(hm_problem* p, double basis_bytes, double recent_by
 hm_status hm_set_small_krylov(hm_problem* p, int enable) {
   if (!p) return HM_ERR_ARG;
   p->small_krylov = enable != 0;
+  return HM_OK;
+}
+
+hm_status hm_set_krylov_pairs(hm_problem* p, int enable) {
+  if (!p) return HM_ERR_ARG;
+  p->krylov_pairs = enable != 0;
   return HM_OK;
 }
 

@@ -99,7 +99,7 @@ def test_level2_basis_sizes_the_level2_workspace():
     small = hm.workspace_bytes(hm.default_config(257, 257, 1 / 256, level2_basis=20))
     n2 = 129 * 129
     assert full - small >= 80 * 2 * 16 * n2
-    assert full - small < 80 * 2 * 16 * n2 + 2048 * 100 * 16
+    assert full - small < 80 * 2 * 16 * n2 + 2048 * 2 * 100 * 16
 
 
 def test_solve_with_regrow_doubles_the_basis_until_it_suffices():
