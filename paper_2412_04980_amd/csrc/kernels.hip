@@ -1171,10 +1171,10 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
 // ---- two Arnoldi steps per sweep over the basis --------------------------------
 // Pass A: the partial dots of z and y with NG left vectors vp[0..NG-1] over one
 // chunk, each thread two rows per pass (all loads of the two rows in flight).
-template <typename T, int NG, bool NTL>
+template <typename T, int NG, bool NTL, int GA>
 __device__ __forceinline__ void dot2_rows(const cx<T>* const* vp, const cx<T>* __restrict__ zv,
                                           const cx<T>* __restrict__ yv, size_t lo, size_t hi,
-                                          double (*re)[G], double (*im)[G]) {
+                                          double (*re)[GA], double (*im)[GA]) {
   size_t i = lo + threadIdx.x;
   for (; i + NT < hi; i += 2 * NT) {
     const cx<T> za = zv[i], zb = zv[i + NT], ya = yv[i], yb = yv[i + NT];
@@ -1207,44 +1207,43 @@ __device__ __forceinline__ void dot2_rows(const cx<T>* const* vp, const cx<T>* _
 
 // Pass A of a pair of Arnoldi steps (z = M v_j, y = M z): the dots of z and y
 // with V_0..V_{m-1} and with z and y themselves, in one read of the basis.
-// Block = (chunk, group); group gi < ngv holds V_{4gi}..V_{4gi+3}, group ngv
-// holds (z, y).  Value r (m + 2) + i for right vector r (0: z, 1: y) and left
-// vector i (V_i for i < m, then z, y): partials[value * nchunks + chunk].  The
-// chunks, the XCD-aware block order and the load policy are those of k_multidot.
+// Block = (chunk, group); group gi < ngv holds V_{GP gi}..V_{GP gi + GP - 1},
+// group ngv holds (z, y).  Value r (m + 2) + i for right vector r (0: z, 1: y)
+// and left vector i (V_i for i < m, then z, y): partials[value * nchunks +
+// chunk].  Two basis vectors per group keep the accumulators (and registers)
+// of a thread at those of the one-vector dot pass, so as many waves stay
+// resident; z and y are re-read per group from the caches.  The chunks, the
+// XCD-aware block order and the load policy are those of k_multidot.
+constexpr int GP = 2;
 template <typename T, bool STREAM>
 __global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, size_t ldv, int m,
                                                   const cx<T>* __restrict__ zv,
                                                   const cx<T>* __restrict__ yv, size_t n,
                                                   size_t clen, c128* __restrict__ partials,
                                                   int nchunks, int recent, Batch z) {
-  __shared__ double sh[NT / 64][4 * G];
+  __shared__ double sh[NT / 64][4 * GP];
   HM_MEMBER(V); HM_MEMBER(zv); HM_MEMBER(yv); HM_MEMBER(partials);
-  const int ngv = (m + G - 1) / G, ngroups = ngv + 1;
+  const int ngv = (m + GP - 1) / GP, ngroups = ngv + 1;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
   const int chunk = (local / ngroups) * 8 + xcd;
   const int gi = local % ngroups;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double re[2][G], im[2][G];
+  double re[2][GP], im[2][GP];
 #pragma unroll
-  for (int g = 0; g < G; ++g) { re[0][g] = im[0][g] = re[1][g] = im[1][g] = 0; }
+  for (int g = 0; g < GP; ++g) { re[0][g] = im[0][g] = re[1][g] = im[1][g] = 0; }
   int first, gm;                                 // first value index, left vectors
   if (gi < ngv) {
-    const int i0 = gi * G;
-    gm = m - i0 < G ? m - i0 : G;
+    const int i0 = gi * GP;
+    gm = m - i0 < GP ? m - i0 : GP;
     first = i0;
     const bool ntl = STREAM && i0 + gm <= m - recent;
-    const cx<T>* vp[G];
+    const cx<T>* vp[GP];
 #pragma unroll
-    for (int g = 0; g < G; ++g) vp[g] = V + (size_t)(i0 + (g < gm ? g : 0)) * ldv;
-    if (gm == 4) {
-      if (ntl) dot2_rows<T, 4, true>(vp, zv, yv, lo, hi, re, im);
-      else dot2_rows<T, 4, false>(vp, zv, yv, lo, hi, re, im);
-    } else if (gm == 3) {
-      if (ntl) dot2_rows<T, 3, true>(vp, zv, yv, lo, hi, re, im);
-      else dot2_rows<T, 3, false>(vp, zv, yv, lo, hi, re, im);
-    } else if (gm == 2) {
+    for (int g = 0; g < GP; ++g) vp[g] = V + (size_t)(i0 + (g < gm ? g : 0)) * ldv;
+    static_assert(GP == 2, "the group tails below cover GP = 2");
+    if (gm == 2) {
       if (ntl) dot2_rows<T, 2, true>(vp, zv, yv, lo, hi, re, im);
       else dot2_rows<T, 2, false>(vp, zv, yv, lo, hi, re, im);
     } else {
@@ -1260,7 +1259,7 @@ __global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, s
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
+    for (int g = 0; g < GP; ++g) {
       re[r][g] = wave_sum(re[r][g]);
       im[r][g] = wave_sum(im[r][g]);
     }
@@ -1268,19 +1267,19 @@ __global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, s
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        sh[wid][2 * (r * G + g)] = re[r][g];
-        sh[wid][2 * (r * G + g) + 1] = im[r][g];
+      for (int g = 0; g < GP; ++g) {
+        sh[wid][2 * (r * GP + g)] = re[r][g];
+        sh[wid][2 * (r * GP + g) + 1] = im[r][g];
       }
   }
   __syncthreads();
-  if (threadIdx.x < 2 * G) {
-    const int r = threadIdx.x / G, g = threadIdx.x - r * G;
+  if (threadIdx.x < 2 * GP) {
+    const int r = threadIdx.x / GP, g = threadIdx.x - r * GP;
     if (g < gm) {
       double sr = 0, si = 0;
       for (int w2 = 0; w2 < NT / 64; ++w2) {
-        sr += sh[w2][2 * (r * G + g)];
-        si += sh[w2][2 * (r * G + g) + 1];
+        sr += sh[w2][2 * (r * GP + g)];
+        si += sh[w2][2 * (r * GP + g) + 1];
       }
       partials[(size_t)(r * (m + 2) + first + g) * nchunks + chunk] = mk(sr, si);
     }
@@ -2363,7 +2362,7 @@ hipError_t launch_multidot2(const cx<T>* V, size_t ldv, int m, const cx<T>* zv, 
   if (m <= 0) return hipErrorInvalidValue;
   const size_t clen = multidot_chunk_len(n, m + G);
   const int nch = (int)(((n + clen - 1) / clen + 7) & ~(size_t)7);
-  const dim3 g = zgrid(((m + G - 1) / G + 1) * nch, z);
+  const dim3 g = zgrid(((m + GP - 1) / GP + 1) * nch, z);
   const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
   if ((double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis)
     k_multidot2<T, true><<<g, NT, 0, s>>>(V, ldv, m, zv, yv, n, clen, rb.partials, nch, recent, z);
