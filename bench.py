@@ -156,17 +156,22 @@ def timed_solves(hm, torch, prob, b, steps, warmup, timing):
 def gs_hbm_share(counts, n, es, cls):
     """Share of the algorithmic bytes of a Gram-Schmidt pass class that come from
     HBM under the cache-aware loads, estimated from the step counts of the
-    coarsest-level Krylov CSLP solves: at step j the pass reads m = j + 1 basis
-    vectors (plus w); when the basis exceeds the 256 MB plain-load limit, the
-    vectors older than the 200 MB recent window come from HBM and the rest (the
-    recent vectors, w) from the Infinity Cache; a smaller basis is cache-resident."""
+    coarsest-level Krylov CSLP solves (FP64: two Arnoldi steps per pair of
+    passes).  The pair at step j reads m = j + 1 basis vectors in pass A (with
+    z and y) and again in pass B (with z, y, and two vectors written), pass B
+    only when the solve goes on to step j + 1.  When the basis exceeds the
+    256 MB plain-load limit, the vectors older than the 200 MB recent window come
+    from HBM and the rest from the Infinity Cache; a smaller basis is
+    cache-resident."""
     vec = float(n) * es
     recent = int(200.0 * 2**20 / vec)
     alg = hbm = 0.0
     for steps in counts:
-        for j in range(steps):
+        for j in range(0, steps, 2):
             m = j + 1
-            alg += (m + 1 if cls == "cgs_dot" else m + 2) * vec
+            if cls == "cgs_update_norm" and j + 1 >= steps:
+                continue                      # the pair's second step is not taken
+            alg += (m + 2 if cls == "cgs_dot" else m + 4) * vec
             if (m + 1) * vec > 256.0 * 2**20:
                 hbm += max(0, m - recent) * vec
     return hbm / alg if alg else None
@@ -566,8 +571,10 @@ def _short_kernel(name):
 
 # kernel classes of the bench line and the kernels each one times
 TRAFFIC_CLASSES = {
-    "cgs_dot": ("k_multidot<double, true>", "k_multidot<double, false>"),
-    "cgs_update_norm": ("k_cgs_update_norm<double, true>", "k_cgs_update_norm<double, false>"),
+    "cgs_dot": ("k_multidot2<double, true>", "k_multidot2<double, false>",
+                "k_multidot<double, true>", "k_multidot<double, false>"),
+    "cgs_update_norm": ("k_cgs_update2<double, true>", "k_cgs_update2<double, false>",
+                        "k_cgs_update_norm<double, true>", "k_cgs_update_norm<double, false>"),
     "wide_stencil_apply": ("k_wide_persist<double, 3, 3>",),
 }
 
@@ -990,7 +997,8 @@ def main():
                     "share_of_bytes": share, "achieved": d["GBps"] * share,
                     "frac": d["GBps"] * share / HBM_PEAK_GBS,
                     "model": "basis vectors older than the 200 MB recent window of bases above "
-                             "256 MB, per step of the recorded Krylov CSLP counts"}
+                             "256 MB, per pass of the recorded Krylov CSLP counts (two steps per "
+                             "pair of passes)"}
         # measured ceilings of this GPU (a plain copy, a read-only stream), taken
         # after the timed region with the solver's memory released
         ceil = bandwidth_ceilings(torch)
