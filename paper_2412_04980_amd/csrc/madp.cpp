@@ -516,25 +516,38 @@ static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
   std::vector<int> run;
   for (size_t t = 0; t < st.size(); ++t)
     if (st[t].maxit > 0) run.push_back((int)t);
-  const cx<T>* src = b;                                  // v_j = src / s_j
-  for (int j = 0; !run.empty(); j += 2) {
-    const Batch z = members(c, members_of(st, run));
-    const double nm = (double)run.size();
+  // the front of the pair at step j for the members who: v_j = src / s_j with
+  // z = M v_j, y = M z, then pass A (the host reads its dots after the stream)
+  const cx<T>* src = b;
+  cx<T>* zb = nullptr;
+  cx<T>* yb = nullptr;
+  auto front = [&](int j, const std::vector<int>& who) {
+    const Batch z = members(c, members_of(st, who));
+    const double nm = (double)who.size();
     const c128* sc = j == 0 ? ws.h : ws.H + (size_t)(j - 1) * ld + j;
-    cx<T>* zb = src == wb[0] ? wb[1] : wb[0];
-    cx<T>* yb = src == b ? wb[1] : (cx<T>*)src;         // src is consumed by the first apply
-    const int m = j + 1;
+    zb = src == wb[0] ? wb[1] : wb[0];
+    yb = src == b ? wb[1] : (cx<T>*)src;                // src is consumed by the first apply
     timed(p, tk_op, nm * 3.5 * es * N, [&] {
       return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, zb, p->s, z);
     });
     timed(p, tk_op, nm * 2.5 * es * N, [&] {
       return launch_stencil<T>(op, ST_APPLY, zb, k, nullptr, yb, T(0), p->s, z);
     });
-    timed(p, HM_TK_CGS_DOT, nm * (m + 2) * es * N, [&] {
-      return launch_multidot2<T>(V, N, m, zb, yb, N, rbuf(p, N), ws.H + (size_t)j * ld,
+    timed(p, HM_TK_CGS_DOT, nm * (j + 3) * es * N, [&] {
+      return launch_multidot2<T>(V, N, j + 1, zb, yb, N, rbuf(p, N), ws.H + (size_t)j * ld,
                                  p->host_H + (size_t)j * ld, p->s, z, p->cache);
     });
-    wait_stream(c);
+  };
+  if (!run.empty()) front(0, run);
+  std::vector<int> fronted = run;                        // members whose front is enqueued
+  for (int j = 0; !run.empty(); j += 2) {
+    const int m = j + 1;
+    // members not enqueued ahead (expected to stop, but did not) get their front now
+    std::vector<int> late;
+    for (int t : run)
+      if (std::find(fronted.begin(), fronted.end(), t) == fronted.end()) late.push_back(t);
+    if (!late.empty()) front(j, late);
+    wait_stream(c);                                      // pass A of this pair
     // step j for every member; the coefficients of pass B for those that go on
     std::vector<int> pair;
     for (int t : run) {
@@ -554,6 +567,8 @@ static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
       col[m] = mk(bj, 0.0);
       const double est = mk_.lsq.add(j, col);
       mk_.steps = j + 1;
+      mk_.est2 = mk_.est1;
+      mk_.est1 = est;
       const bool broke = bj <= 1e-14 * mk_.beta;
       if (broke || (mk_.tol >= 0 && est <= mk_.tol * mk_.beta) || j + 1 >= mk_.maxit) continue;
       // step j+1's column from the Arnoldi relation, and pass B's coefficients
@@ -597,7 +612,23 @@ static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
                                    ws.H + (size_t)(j + 1) * ld + j + 2,
                                    p->host_H + (size_t)(j + 1) * ld + j + 2, p->s, zp, p->cache);
     });
-    wait_stream(c);
+    HM_CHECK(hipEventRecord(p->col_ev[0], p->s));
+    // the next pair's front goes in before the host reads this pair's second
+    // column, except for members expected to meet the tolerance at step j + 1
+    // (the estimates fall about geometrically: est_{j+1} ~ est_j^2 / est_{j-1});
+    // a member that stops at step j + 1 has only written its z, y, V_{j+2} and
+    // dots, none of which its solution uses
+    src = zb;                                            // w' of pass B
+    std::vector<int> spec;
+    for (int t : pair) {
+      const MemberKrylov& q = st[t];
+      const bool soon = q.tol >= 0 && q.est1 > 0 && q.est2 > 0 &&
+                        q.est1 * (q.est1 / q.est2) <= q.tol * q.beta;
+      if (j + 2 < q.maxit && !soon) spec.push_back(t);
+    }
+    if (!spec.empty()) front(j + 2, spec);
+    fronted = spec;
+    HM_CHECK(hipEventSynchronize(p->col_ev[0]));
     std::vector<int> next;
     for (int t : pair) {
       MemberKrylov& mk_ = st[t];
@@ -605,12 +636,13 @@ static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
       col1[j + 2] = c.mem[mk_.i]->host_H[(size_t)(j + 1) * ld + j + 2];
       const double est = mk_.lsq.add(j + 1, col1);
       mk_.steps = j + 2;
+      mk_.est2 = mk_.est1;
+      mk_.est1 = est;
       const bool broke = col1[j + 2].re <= 1e-14 * mk_.beta;
       if (broke || (mk_.tol >= 0 && est <= mk_.tol * mk_.beta) || j + 2 >= mk_.maxit) continue;
       next.push_back(t);
     }
     run.swap(next);
-    src = zb;                                              // w' of pass B
   }
   finish_members<T>(c, st, kind, V, N, x, 0);
 }
