@@ -258,15 +258,18 @@ hm_status hm_set_small_krylov(hm_problem* p, int enable);
 
 /* Two Arnoldi steps per read of the basis in the classical Gram-Schmidt GMRES of
  * the Krylov CSLP (Sec. 4.2) on FP64 levels that are not solved in one
- * workgroup (FP32 levels keep one step per two passes: the paired relations
- * hold only to the basis's orthogonality):
- * with z = M v_j and y = M z, one pass over the basis takes the dots of z and
- * y; step j+1's Hessenberg column follows from them through the Arnoldi
+ * workgroup: with z = M v_j and y = M z, one pass over the basis takes the dots
+ * of z and y; step j+1's Hessenberg column follows from them through the Arnoldi
  * relation, and a second pass forms v_{j+1} and step j+1's new vector.  The
  * iterates are those of one-step classical Gram-Schmidt in exact arithmetic
- * (reading R18); the basis is read once per step instead of twice.  enable =
- * 1 (default) or 0 (one step per two passes).  HM_ERR_ARG for a null problem. */
-hm_status hm_set_krylov_pairs(hm_problem* p, int enable);
+ * (reading R18); the basis is read once per step instead of twice.  FP32 levels
+ * keep one step per two passes (the paired relations hold only to the basis's
+ * orthogonality).  mode: HM_PAIRS_AUTO (default: levels of at least 50,000
+ * nodes, where the saved basis read outweighs the host's step between the
+ * passes), HM_PAIRS_ALWAYS, HM_PAIRS_OFF.  HM_ERR_ARG for a null problem or
+ * another mode. */
+enum { HM_PAIRS_OFF = 0, HM_PAIRS_AUTO = 1, HM_PAIRS_ALWAYS = 2 };
+hm_status hm_set_krylov_pairs(hm_problem* p, int mode);
 
 hm_status hm_destroy_problem(hm_problem* p);
 

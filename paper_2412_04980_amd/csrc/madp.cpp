@@ -225,7 +225,7 @@ struct hm_problem {
   CachePolicy cache;
   // small coarse levels solved by one workgroup per member (hm_set_small_krylov)
   bool small_krylov = true;
-  bool krylov_pairs = true;    // classical Gram-Schmidt: two Arnoldi steps per basis read
+  int krylov_pairs = HM_PAIRS_AUTO;   // two Arnoldi steps per basis read (hm_krylov_pairs)
   // optional per-kernel-class timing with HIP events on the problem's stream
   unsigned timing_mask = 0;
   int timing_every = 1;                 // bracket every n-th launch of a class
@@ -657,8 +657,15 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
   }
   // the paired steps take step j+1's column from relations that hold to the
   // basis's orthogonality: FP64 levels only (with an FP32 basis the k = 200
-  // solve took one outer step more and moved 2e-5 from the FP64 solution)
-  if (p->krylov_pairs && p->cfg.cslp_orth == HM_ORTH_CLASSICAL && sizeof(T) == sizeof(double)) {
+  // solve took one outer step more and moved 2e-5 from the FP64 solution).  By
+  // default only on levels of at least kPairsMinNodes nodes: below, the passes
+  // are latency-bound and the host's step between the two passes costs more
+  // than the basis read it saves (measured per solve: 129^2 level 111 -> 123 ms,
+  // 151 x 251 131 -> 139 ms; 257^2 271 -> 258 ms, 513^2 1337 -> 975 ms)
+  constexpr size_t kPairsMinNodes = 50000;
+  const bool pairs = p->krylov_pairs == HM_PAIRS_ALWAYS ||
+                     (p->krylov_pairs == HM_PAIRS_AUTO && ws.N >= kPairsMinNodes);
+  if (pairs && p->cfg.cslp_orth == HM_ORTH_CLASSICAL && sizeof(T) == sizeof(double)) {
     gmres_pairs<T>(c, a0, op, k, ws, maxit, tol, kind, b, x);
     return;
   }
@@ -2038,9 +2045,9 @@ hm_status hm_set_small_krylov(hm_problem* p, int enable) {
   return HM_OK;
 }
 
-hm_status hm_set_krylov_pairs(hm_problem* p, int enable) {
-  if (!p) return HM_ERR_ARG;
-  p->krylov_pairs = enable != 0;
+hm_status hm_set_krylov_pairs(hm_problem* p, int mode) {
+  if (!p || mode < HM_PAIRS_OFF || mode > HM_PAIRS_ALWAYS) return HM_ERR_ARG;
+  p->krylov_pairs = mode;
   return HM_OK;
 }
 

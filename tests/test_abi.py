@@ -160,6 +160,13 @@ def test_csr_spmv_binding_rejects_x_of_the_wrong_length():
         hm.csr_spmv(rp, ci, va, torch.zeros(4, dtype=torch.complex128), ncols=6)
 
 
+def test_krylov_pairs_modes():
+    import paper_2412_04980_amd as hm
+    assert (hm.PAIRS_OFF, hm.PAIRS_AUTO, hm.PAIRS_ALWAYS) == (0, 1, 2)
+    # a null problem is rejected without touching the device
+    assert hm._lib.hm_set_krylov_pairs(None, hm.PAIRS_AUTO) == hm.HM_ERR_ARG
+
+
 def test_set_basis_cache_rejects_bad_arguments_on_the_host():
     import paper_2412_04980_amd as hm
     nul = ctypes.c_void_p(0)
