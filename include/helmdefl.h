@@ -264,11 +264,11 @@ hm_status hm_set_small_krylov(hm_problem* p, int enable);
  * iterates are those of one-step classical Gram-Schmidt in exact arithmetic
  * (reading R18); the basis is read once per step instead of twice.  FP32 levels
  * keep one step per two passes (the paired relations hold only to the basis's
- * orthogonality).  mode: HM_PAIRS_AUTO (default: levels of at least 50,000
- * nodes, where the saved basis read outweighs the host's step between the
- * passes), HM_PAIRS_ALWAYS, HM_PAIRS_OFF.  HM_ERR_ARG for a null problem or
- * another mode. */
-enum { HM_PAIRS_OFF = 0, HM_PAIRS_AUTO = 1, HM_PAIRS_ALWAYS = 2 };
+ * orthogonality).  The columns and the second pass's coefficients are formed
+ * on the device between the passes, so a pair runs without the host.  mode:
+ * HM_PAIRS_ON (default) or HM_PAIRS_OFF (one step per two passes).  HM_ERR_ARG
+ * for a null problem or another mode. */
+enum { HM_PAIRS_OFF = 0, HM_PAIRS_ON = 1 };
 hm_status hm_set_krylov_pairs(hm_problem* p, int mode);
 
 hm_status hm_destroy_problem(hm_problem* p);

@@ -321,13 +321,12 @@ def set_small_krylov(prob, enable=True):
     _check(_lib.hm_set_small_krylov(prob.handle, 1 if enable else 0))
 
 
-PAIRS_OFF, PAIRS_AUTO, PAIRS_ALWAYS = 0, 1, 2
+PAIRS_OFF, PAIRS_ON = 0, 1
 
 
-def set_krylov_pairs(prob, mode=PAIRS_AUTO):
-    """Two Arnoldi steps per read of the basis in the Krylov CSLP: PAIRS_AUTO
-    (default; FP64 levels of at least 50,000 nodes), PAIRS_ALWAYS (every FP64
-    level) or PAIRS_OFF."""
+def set_krylov_pairs(prob, mode=PAIRS_ON):
+    """Two Arnoldi steps per read of the basis in the Krylov CSLP of FP64
+    levels: PAIRS_ON (default) or PAIRS_OFF."""
     _check(_lib.hm_set_krylov_pairs(prob.handle, int(mode)))
 
 

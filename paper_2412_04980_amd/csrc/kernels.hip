@@ -1482,6 +1482,76 @@ __global__ void __launch_bounds__(NT) k_cgs_update2(cx<T>* __restrict__ zv,
   if (threadIdx.x == 0) partials[chunk] = s;
 }
 
+// Between the passes of a pair of Arnoldi steps (one block per member): from
+// pass A's dots d = [V; z; y]^H [z; y] (d[0..m+1] with z, d[m+2..2m+3] with y;
+// m = j + 1) and the Hessenberg columns 0..j-1 in H (stride ld), the columns of
+// steps j and j+1 and pass B's coefficients:
+//   a = V^H z, b_j = (z^H z - |a|^2)^(1/2), g = H_{0..j, 0..j-1} a_{0..j-1},
+//   h' = (c - g - a_j a) / b_j with c = V^H y,  h'_{j+1} = (z^H y - a^H c) / b_j^2 - a_j,
+//   ca = (-a / b_j, 1 / b_j),  cg = (-g / b_j - h' + a h'_{j+1} / b_j, -(a_j + h'_{j+1}) / b_j).
+// Column j (rows 0..j+1) and column j+1 (rows 0..j+1) go to H and to the pinned
+// host mirror Hh (same layout); ca to coef[0..m], cg to coef[ld..ld+m].  b_j = 0
+// (breakdown) leaves non-finite coefficients, whose pass B output the solve
+// never uses (the host stops the member at step j).
+__global__ void __launch_bounds__(NT) k_pair_coef(const c128* __restrict__ d, c128* __restrict__ H,
+                                                  int ld, int j, c128* __restrict__ coef,
+                                                  c128* __restrict__ Hh, Batch z) {
+  __shared__ double sh[2 * NT / 64];
+  __shared__ c128 sc[2];                       // a^H c, 1 / b_j
+  __shared__ double sb;
+  HM_MEMBER(d); HM_MEMBER(H); HM_MEMBER(coef);
+  Hh = at_member(Hh, z.hz, z);
+  const int m = j + 1;
+  const c128* dz = d;
+  const c128* dy = d + (m + 2);
+  // |a|^2 and a^H c over the block
+  double aa = 0, acr = 0, aci = 0;
+  for (int i = threadIdx.x; i < m; i += NT) {
+    const c128 a = dz[i], c = dy[i];
+    aa = fma(a.re, a.re, fma(a.im, a.im, aa));
+    acr = fma(a.re, c.re, fma(a.im, c.im, acr));
+    aci = fma(a.re, c.im, fma(-a.im, c.re, aci));
+  }
+  const c128 s1 = block_sum(aa, 0.0, sh);
+  __syncthreads();
+  const c128 s2 = block_sum(acr, aci, sh);
+  if (threadIdx.x == 0) {
+    const double b2 = dz[m].re - s1.re;
+    sb = b2 > 0 ? sqrt(b2) : 0.0;
+    sc[0] = s2;
+  }
+  __syncthreads();
+  const double bj = sb, ib = 1.0 / bj;
+  const c128 aj = dz[j];
+  const c128 hn = (ib * ib) * (dy[m] - sc[0]) - aj;
+  c128* colj = H + (size_t)j * ld;
+  c128* colj1 = colj + ld;
+  c128* hj = Hh + (size_t)j * ld;
+  c128* hj1 = hj + ld;
+  for (int r = threadIdx.x; r <= m; r += NT) {
+    if (r < m) {
+      // g_r = sum_{i = max(0, r-1)}^{j-1} H[r, i] a_i
+      c128 g = mk(0.0, 0.0);
+      for (int i = r > 0 ? r - 1 : 0; i < j; ++i) g = g + H[(size_t)i * ld + r] * dz[i];
+      const c128 a = dz[r];
+      const c128 hv = ib * (dy[r] - g - aj * a);
+      colj[r] = a;
+      hj[r] = a;
+      colj1[r] = hv;
+      hj1[r] = hv;
+      coef[r] = (-ib) * a;
+      coef[ld + r] = (-ib) * g - hv + a * (ib * hn);
+    } else {
+      colj[m] = mk(bj, 0.0);
+      hj[m] = mk(bj, 0.0);
+      colj1[m] = hn;
+      hj1[m] = hn;
+      coef[m] = mk(ib, 0.0);
+      coef[ld + m] = (-ib) * (aj + hn);
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(NT) k_norm2(const cx<T>* __restrict__ x, size_t n, size_t clen,
                                               c128* __restrict__ partials, Batch z) {
@@ -2370,6 +2440,12 @@ hipError_t launch_multidot2(const cx<T>* V, size_t ldv, int m, const cx<T>* zv, 
     k_multidot2<T, false><<<g, NT, 0, s>>>(V, ldv, m, zv, yv, n, clen, rb.partials, nch, recent,
                                            z);
   k_final<<<zgrid(2 * (m + 2), z), NT, 0, s>>>(rb.partials, nch, out, 0, host_out, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_coef(const c128* dots, c128* H, int ld, int j, c128* coef, c128* host_H,
+                            hipStream_t s, const Batch& z) {
+  k_pair_coef<<<zgrid(1, z), NT, 0, s>>>(dots, H, ld, j, coef, host_H, z);
   return hipGetLastError();
 }
 

@@ -229,6 +229,12 @@ template <typename T>
 hipError_t launch_multidot2(const cx<T>* V, size_t ldv, int m, const cx<T>* zv, const cx<T>* yv,
                             size_t n, RedBuf rb, c128* out, c128* host_out, hipStream_t s,
                             const Batch& z = Batch(), const CachePolicy& cp = CachePolicy());
+// Between the passes (one block per member): from pass A's dots at `dots` and
+// the Hessenberg columns 0..j-1 of H (stride ld), columns j and j+1 (rows
+// 0..j+1) to H and to the pinned host_H, and pass B's coefficients (ca at
+// coef[0..j+1], cg at coef[ld..ld+j+1]).
+hipError_t launch_pair_coef(const c128* dots, c128* H, int ld, int j, c128* coef, c128* host_H,
+                            hipStream_t s, const Batch& z = Batch());
 // Pass B: V_m = ca[m] z + sum_{i<m} ca[i] V_i ; z <- ca[m] y + cg[m] z +
 // sum_{i<m} cg[i] V_i ; norm_out[0] = host_out[0] = ||z|| (real part).
 template <typename T>

@@ -72,6 +72,8 @@ struct KrylovWS {
   void* w2 = nullptr;  // GMRES: second work vector (ping-pong with w)
   c128* h = nullptr;   // device column / scalars, cap + 2
   c128* H = nullptr;   // GMRES: device Hessenberg, cap columns of stride cap + 2
+  c128* D = nullptr;   // paired steps: pass A's dots, 2 (cap + 2)
+  c128* C = nullptr;   // paired steps: pass B's coefficients, 2 (cap + 2)
 };
 
 struct MGLevel {
@@ -225,7 +227,7 @@ struct hm_problem {
   CachePolicy cache;
   // small coarse levels solved by one workgroup per member (hm_set_small_krylov)
   bool small_krylov = true;
-  int krylov_pairs = HM_PAIRS_AUTO;   // two Arnoldi steps per basis read (hm_krylov_pairs)
+  int krylov_pairs = HM_PAIRS_ON;     // two Arnoldi steps per basis read (hm_set_krylov_pairs)
   // optional per-kernel-class timing with HIP events on the problem's stream
   unsigned timing_mask = 0;
   int timing_every = 1;                 // bracket every n-th launch of a class
@@ -494,8 +496,12 @@ static void gmres_small(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
 // with c = V^H y.  Pass B forms v_{j+1} = (z - V a) / b_j and
 // w' = z' - [V, v_{j+1}] h' in one read of the basis, with ||w'||.  In exact
 // arithmetic these are the iterates of one-step classical Gram-Schmidt; the
-// basis is read once per step instead of twice.  A member that stops at the
-// first step of a pair, or whose step limit ends there, takes no pass B.
+// basis is read once per step instead of twice.
+// The columns and pass B's coefficients are formed on the device between the
+// passes (launch_pair_coef), so a pair runs without the host: the host reads
+// the columns of a pair from the pinned mirror for its stopping tests while
+// the next pair runs.  Work enqueued past a member's last step writes only
+// vectors and columns its solution does not use.
 template <typename T>
 static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
                         int maxit, double tol, int kind, const cx<T>* b, cx<T>* x) {
@@ -511,139 +517,97 @@ static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
     if ((size_t)(m.maxit + 2) * ld > p->host_H_cap) throw ArgError("Hessenberg mirror too small");
   const double es = (double)sizeof(cx<T>);
   const int tk_op = op.R == 1 ? HM_TK_FIVE_POINT : HM_TK_WIDE;
-  // raw Hessenberg columns of every member (column i at i * ld)
-  std::vector<std::vector<c128>> Hh(st.size(), std::vector<c128>(ld * (size_t)ws.cap));
   std::vector<int> run;
   for (size_t t = 0; t < st.size(); ++t)
     if (st[t].maxit > 0) run.push_back((int)t);
-  // the front of the pair at step j for the members who: v_j = src / s_j with
-  // z = M v_j, y = M z, then pass A (the host reads its dots after the stream)
+  // the pair at step j for the members who: v_j = src / s_j with z = M v_j,
+  // y = M z, pass A, the columns and coefficients, pass B with ||w'|| (pass B
+  // also when the member's step limit ends at step j: its output is not used)
   const cx<T>* src = b;
-  cx<T>* zb = nullptr;
-  cx<T>* yb = nullptr;
-  auto front = [&](int j, const std::vector<int>& who) {
+  auto enqueue_pair = [&](int j, const std::vector<int>& who) {
     const Batch z = members(c, members_of(st, who));
     const double nm = (double)who.size();
+    const int m = j + 1;
     const c128* sc = j == 0 ? ws.h : ws.H + (size_t)(j - 1) * ld + j;
-    zb = src == wb[0] ? wb[1] : wb[0];
-    yb = src == b ? wb[1] : (cx<T>*)src;                // src is consumed by the first apply
+    cx<T>* zb = src == wb[0] ? wb[1] : wb[0];
+    cx<T>* yb = src == b ? wb[1] : (cx<T>*)src;         // src is consumed by the first apply
     timed(p, tk_op, nm * 3.5 * es * N, [&] {
       return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, zb, p->s, z);
     });
     timed(p, tk_op, nm * 2.5 * es * N, [&] {
       return launch_stencil<T>(op, ST_APPLY, zb, k, nullptr, yb, T(0), p->s, z);
     });
-    timed(p, HM_TK_CGS_DOT, nm * (j + 3) * es * N, [&] {
-      return launch_multidot2<T>(V, N, j + 1, zb, yb, N, rbuf(p, N), ws.H + (size_t)j * ld,
-                                 p->host_H + (size_t)j * ld, p->s, z, p->cache);
+    timed(p, HM_TK_CGS_DOT, nm * (m + 2) * es * N, [&] {
+      return launch_multidot2<T>(V, N, m, zb, yb, N, rbuf(p, N), ws.D, nullptr, p->s, z,
+                                 p->cache);
+    });
+    HM_CHECK(launch_pair_coef(ws.D, ws.H, (int)ld, j, ws.C, p->host_H, p->s, z));
+    timed(p, HM_TK_CGS_UPDATE, nm * (m + 4) * es * N, [&] {
+      return launch_cgs_update2<T>(zb, yb, V, N, m, ws.C, ws.C + ld, N, rbuf(p, N),
+                                   ws.H + (size_t)(j + 1) * ld + j + 2,
+                                   p->host_H + (size_t)(j + 1) * ld + j + 2, p->s, z, p->cache);
     });
   };
-  if (!run.empty()) front(0, run);
-  std::vector<int> fronted = run;                        // members whose front is enqueued
-  for (int j = 0; !run.empty(); j += 2) {
-    const int m = j + 1;
-    // members not enqueued ahead (expected to stop, but did not) get their front now
-    std::vector<int> late;
-    for (int t : run)
-      if (std::find(fronted.begin(), fronted.end(), t) == fronted.end()) late.push_back(t);
-    if (!late.empty()) front(j, late);
-    wait_stream(c);                                      // pass A of this pair
-    // step j for every member; the coefficients of pass B for those that go on
-    std::vector<int> pair;
-    for (int t : run) {
-      MemberKrylov& mk_ = st[t];
-      const c128* d = c.mem[mk_.i]->host_H + (size_t)j * ld;
-      const c128* dz = d;                                  // [V; z; y]^H z
-      const c128* dy = d + (m + 2);                        // [V; z; y]^H y
-      std::vector<c128>& H = Hh[t];
-      c128* col = H.data() + (size_t)j * ld;
-      double aa = 0;
-      for (int i = 0; i < m; ++i) {
-        col[i] = dz[i];
-        aa += dz[i].re * dz[i].re + dz[i].im * dz[i].im;
-      }
-      const double b2 = dz[m].re - aa;                     // ||z - V a||^2
-      const double bj = b2 > 0 ? std::sqrt(b2) : 0.0;
-      col[m] = mk(bj, 0.0);
-      const double est = mk_.lsq.add(j, col);
-      mk_.steps = j + 1;
-      mk_.est2 = mk_.est1;
-      mk_.est1 = est;
-      const bool broke = bj <= 1e-14 * mk_.beta;
-      if (broke || (mk_.tol >= 0 && est <= mk_.tol * mk_.beta) || j + 1 >= mk_.maxit) continue;
-      // step j+1's column from the Arnoldi relation, and pass B's coefficients
-      std::vector<c128> g(m, mk(0.0, 0.0));
-      for (int i = 0; i + 1 < m; ++i) {                    // g = H_{0..j, 0..j-1} a_{0..j-1}
-        const c128* hc = H.data() + (size_t)i * ld;
-        for (int r = 0; r <= i + 1; ++r) g[r] = g[r] + hc[r] * dz[i];
-      }
-      const c128 aj = dz[j];
-      c128 ac = mk(0.0, 0.0);                              // a^H c
-      for (int i = 0; i < m; ++i) ac = ac + cmulc(dz[i], dy[i]);
-      c128* col1 = H.data() + (size_t)(j + 1) * ld;
-      const double ib = 1.0 / bj;
-      for (int i = 0; i < m; ++i) col1[i] = ib * (dy[i] - g[i] - aj * dz[i]);
-      const c128 hn = (ib * ib) * (dy[m] - ac) - aj;       // v_{j+1}^H z'
-      col1[m] = hn;
-      // pinned staging: this pair's mirror columns, whose dots are no longer
-      // read (a is taken from the host copy col): ca then cg
-      c128* ca = c.mem[mk_.i]->host_H + (size_t)j * ld;
-      c128* cg = ca + ld;
-      for (int i = 0; i < m; ++i) {
-        ca[i] = (-ib) * col[i];
-        cg[i] = (-ib) * g[i] - col1[i] + col[i] * (ib * hn);
-      }
-      ca[m] = mk(ib, 0.0);
-      cg[m] = (-ib) * (aj + hn);
-      pair.push_back(t);
-    }
-    if (pair.empty()) break;
-    for (int t : pair) {
-      hm_problem* q = c.mem[st[t].i];
-      char* dev = (char*)(ws.H + (size_t)j * ld) + (long long)st[t].i * c.dz;
-      HM_CHECK(hipMemcpyAsync(dev, q->host_H + (size_t)j * ld, sizeof(c128) * (ld + m + 1),
-                              hipMemcpyHostToDevice, p->s));
-    }
-    const Batch zp = members(c, members_of(st, pair));
-    const double np = (double)pair.size();
-    timed(p, HM_TK_CGS_UPDATE, np * (m + 4) * es * N, [&] {
-      return launch_cgs_update2<T>(zb, yb, V, N, m, ws.H + (size_t)j * ld,
-                                   ws.H + (size_t)(j + 1) * ld, N, rbuf(p, N),
-                                   ws.H + (size_t)(j + 1) * ld + j + 2,
-                                   p->host_H + (size_t)(j + 1) * ld + j + 2, p->s, zp, p->cache);
-    });
-    HM_CHECK(hipEventRecord(p->col_ev[0], p->s));
-    // the next pair's front goes in before the host reads this pair's second
-    // column, except for members expected to meet the tolerance at step j + 1
-    // (the estimates fall about geometrically: est_{j+1} ~ est_j^2 / est_{j-1});
-    // a member that stops at step j + 1 has only written its z, y, V_{j+2} and
-    // dots, none of which its solution uses
-    src = zb;                                            // w' of pass B
-    std::vector<int> spec;
-    for (int t : pair) {
+  // pairs enqueued one ahead of the host's stopping tests, except for members
+  // expected to meet the tolerance within the pair (the estimates fall about
+  // geometrically: est_{j+1} ~ est_j^2 / est_{j-1})
+  auto ahead_of = [&](int j, const std::vector<int>& who) {
+    std::vector<int> out;
+    for (int t : who) {
       const MemberKrylov& q = st[t];
       const bool soon = q.tol >= 0 && q.est1 > 0 && q.est2 > 0 &&
-                        q.est1 * (q.est1 / q.est2) <= q.tol * q.beta;
-      if (j + 2 < q.maxit && !soon) spec.push_back(t);
+                        q.est1 * (q.est1 / q.est2) * (q.est1 / q.est2) <= q.tol * q.beta;
+      if (j + 2 < q.maxit && !soon) out.push_back(t);
     }
-    if (!spec.empty()) front(j + 2, spec);
-    fronted = spec;
+    return out;
+  };
+  if (!run.empty()) {
+    enqueue_pair(0, run);
+    HM_CHECK(hipEventRecord(p->col_ev[0], p->s));
+  }
+  for (int j = 0; !run.empty(); j += 2) {
+    // the next pair for the members that will probably go on
+    std::vector<int> spec = ahead_of(j, run);
+    const cx<T>* src_next = src == wb[0] ? wb[1] : wb[0];   // z of pair j holds w'
+    if (!spec.empty()) {
+      src = src_next;
+      enqueue_pair(j + 2, spec);
+      HM_CHECK(hipEventRecord(p->col_ev[1], p->s));
+    }
+    // the columns of pair j: event col_ev[0] follows every launch of pair j
     HM_CHECK(hipEventSynchronize(p->col_ev[0]));
     std::vector<int> next;
-    for (int t : pair) {
-      MemberKrylov& mk_ = st[t];
-      c128* col1 = Hh[t].data() + (size_t)(j + 1) * ld;
-      col1[j + 2] = c.mem[mk_.i]->host_H[(size_t)(j + 1) * ld + j + 2];
-      const double est = mk_.lsq.add(j + 1, col1);
-      mk_.steps = j + 2;
-      mk_.est2 = mk_.est1;
-      mk_.est1 = est;
-      const bool broke = col1[j + 2].re <= 1e-14 * mk_.beta;
-      if (broke || (mk_.tol >= 0 && est <= mk_.tol * mk_.beta) || j + 2 >= mk_.maxit) continue;
+    for (int t : run) {
+      MemberKrylov& q = st[t];
+      const c128* hc = c.mem[q.i]->host_H + (size_t)j * ld;
+      double est = q.lsq.add(j, hc);
+      q.steps = j + 1;
+      q.est2 = q.est1;
+      q.est1 = est;
+      bool broke = hc[j + 1].re <= 1e-14 * q.beta;
+      if (broke || (q.tol >= 0 && est <= q.tol * q.beta) || j + 1 >= q.maxit) continue;
+      const c128* hc1 = hc + ld;
+      est = q.lsq.add(j + 1, hc1);
+      q.steps = j + 2;
+      q.est2 = q.est1;
+      q.est1 = est;
+      broke = hc1[j + 2].re <= 1e-14 * q.beta;
+      if (broke || (q.tol >= 0 && est <= q.tol * q.beta) || j + 2 >= q.maxit) continue;
       next.push_back(t);
     }
+    // members that go on without an enqueued pair j + 2 get it now
+    std::vector<int> late;
+    for (int t : next)
+      if (std::find(spec.begin(), spec.end(), t) == spec.end()) late.push_back(t);
+    if (!late.empty()) {
+      src = src_next;
+      enqueue_pair(j + 2, late);
+      HM_CHECK(hipEventRecord(p->col_ev[1], p->s));
+    }
+    std::swap(p->col_ev[0], p->col_ev[1]);
     run.swap(next);
   }
+  wait_stream(c);                                        // timing events of the pairs
   finish_members<T>(c, st, kind, V, N, x, 0);
 }
 
@@ -657,14 +621,8 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
   }
   // the paired steps take step j+1's column from relations that hold to the
   // basis's orthogonality: FP64 levels only (with an FP32 basis the k = 200
-  // solve took one outer step more and moved 2e-5 from the FP64 solution).  By
-  // default only on levels of at least kPairsMinNodes nodes: below, the passes
-  // are latency-bound and the host's step between the two passes costs more
-  // than the basis read it saves (measured per solve: 129^2 level 111 -> 123 ms,
-  // 151 x 251 131 -> 139 ms; 257^2 271 -> 258 ms, 513^2 1337 -> 975 ms)
-  constexpr size_t kPairsMinNodes = 50000;
-  const bool pairs = p->krylov_pairs == HM_PAIRS_ALWAYS ||
-                     (p->krylov_pairs == HM_PAIRS_AUTO && ws.N >= kPairsMinNodes);
+  // solve took one outer step more and moved 2e-5 from the FP64 solution)
+  const bool pairs = p->krylov_pairs == HM_PAIRS_ON;
   if (pairs && p->cfg.cslp_orth == HM_ORTH_CLASSICAL && sizeof(T) == sizeof(double)) {
     gmres_pairs<T>(c, a0, op, k, ws, maxit, tol, kind, b, x);
     return;
@@ -1260,6 +1218,8 @@ static void plan(hm_problem* p, Carver& cv) {
         H.gm.w2 = cv.take<char>(last.N * es);
         H.gm.h = cv.take<c128>(H.maxit + 2);
         H.gm.H = cv.take<c128>((size_t)(H.maxit + 2) * (H.maxit + 2));
+        H.gm.D = cv.take<c128>(2 * (size_t)(H.maxit + 2));
+        H.gm.C = cv.take<c128>(2 * (size_t)(H.maxit + 2));
         mmax = std::max(mmax, H.maxit + 2);
         p->host_H_cap = std::max(p->host_H_cap, (size_t)(H.maxit + 2) * (H.maxit + 2));
       }
@@ -1272,6 +1232,8 @@ static void plan(hm_problem* p, Carver& cv) {
       D.cslp.w2 = cv.take<char>(D.N * es);
       D.cslp.h = cv.take<c128>(D.cslp_maxit + 2);
       D.cslp.H = cv.take<c128>((size_t)(D.cslp_maxit + 2) * (D.cslp_maxit + 2));
+      D.cslp.D = cv.take<c128>(2 * (size_t)(D.cslp_maxit + 2));
+      D.cslp.C = cv.take<c128>(2 * (size_t)(D.cslp_maxit + 2));
       mmax = std::max(mmax, D.cslp_maxit + 2);
       p->host_H_cap = std::max(p->host_H_cap, (size_t)(D.cslp_maxit + 2) * (D.cslp_maxit + 2));
     }
@@ -2046,7 +2008,7 @@ hm_status hm_set_small_krylov(hm_problem* p, int enable) {
 }
 
 hm_status hm_set_krylov_pairs(hm_problem* p, int mode) {
-  if (!p || mode < HM_PAIRS_OFF || mode > HM_PAIRS_ALWAYS) return HM_ERR_ARG;
+  if (!p || (mode != HM_PAIRS_OFF && mode != HM_PAIRS_ON)) return HM_ERR_ARG;
   p->krylov_pairs = mode;
   return HM_OK;
 }

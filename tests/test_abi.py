@@ -162,9 +162,9 @@ def test_csr_spmv_binding_rejects_x_of_the_wrong_length():
 
 def test_krylov_pairs_modes():
     import paper_2412_04980_amd as hm
-    assert (hm.PAIRS_OFF, hm.PAIRS_AUTO, hm.PAIRS_ALWAYS) == (0, 1, 2)
+    assert (hm.PAIRS_OFF, hm.PAIRS_ON) == (0, 1)
     # a null problem is rejected without touching the device
-    assert hm._lib.hm_set_krylov_pairs(None, hm.PAIRS_AUTO) == hm.HM_ERR_ARG
+    assert hm._lib.hm_set_krylov_pairs(None, hm.PAIRS_ON) == hm.HM_ERR_ARG
 
 
 def test_set_basis_cache_rejects_bad_arguments_on_the_host():

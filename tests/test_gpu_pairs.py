@@ -1,6 +1,6 @@
-"""Two Arnoldi steps per read of the basis (hm_set_krylov_pairs; by default on
-FP64 levels of at least 50,000 nodes, forced on every FP64 level here) against
-the oracle and against one step per two passes.
+"""Two Arnoldi steps per read of the basis (hm_set_krylov_pairs, the default on
+FP64 levels solved host-driven) against the oracle and against one step per two
+passes.
 
 The paired steps derive the second step's Hessenberg column from the first
 step's dots through the Arnoldi relation, so they agree with one-step classical
@@ -43,7 +43,7 @@ def make(nx, ny, h, k, pairs=True, small=False, **overrides):
         setattr(cfg, key, val)
     p = hm.create_problem(cfg, gpu(k))
     hm.set_small_krylov(p, small)
-    hm.set_krylov_pairs(p, hm.PAIRS_ALWAYS if pairs else hm.PAIRS_OFF)
+    hm.set_krylov_pairs(p, hm.PAIRS_ON if pairs else hm.PAIRS_OFF)
     return p
 
 
@@ -124,8 +124,7 @@ def test_replayed_preconditioner_and_solve_with_pairs(grid):
 
 @pytest.mark.parametrize("precision", [hm.HM_FP64, hm.HM_MIXED_FP32, hm.HM_MIXED_FP32_ALL])
 def test_pairs_match_one_step_in_every_precision(precision):
-    """A 257^2 random medium with the paired steps forced on its 65^2 coarsest
-    level: when that level is FP64 (HM_FP64, HM_MIXED_FP32) the solve equals the
+    """A 257^2 random medium (65^2 coarsest level): when that level is FP64 (HM_FP64, HM_MIXED_FP32) the solve equals the
     one-step solve to rounding; with every level in FP32 both run one step per
     two passes, and the results are identical."""
     n = 257
@@ -163,7 +162,7 @@ def test_pairs_in_a_batch_equal_alone():
     try:
         for m in bt.members:
             hm.set_small_krylov(m, False)
-            hm.set_krylov_pairs(m, hm.PAIRS_ALWAYS)
+            hm.set_krylov_pairs(m, hm.PAIRS_ON)
         us, _ = hm.batch_solve(bt, [gpu(b) for b in bs])
         us = [host(u) for u in us]
     finally:
