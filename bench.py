@@ -153,25 +153,22 @@ def timed_solves(hm, torch, prob, b, steps, warmup, timing):
     return u, total, lat, infos, kt
 
 
-def gs_hbm_share(counts, n, es, cls):
+def gs_hbm_share(counts, n, es, cls, steps=3):
     """Share of the algorithmic bytes of a Gram-Schmidt pass class that come from
     HBM under the cache-aware loads, estimated from the step counts of the
-    coarsest-level Krylov CSLP solves (FP64: two Arnoldi steps per pair of
-    passes).  The pair at step j reads m = j + 1 basis vectors in pass A (with
-    z and y) and again in pass B (with z, y, and two vectors written), pass B
-    only when the solve goes on to step j + 1.  When the basis exceeds the
-    256 MB plain-load limit, the vectors older than the 200 MB recent window come
-    from HBM and the rest from the Infinity Cache; a smaller basis is
-    cache-resident."""
+    coarsest-level Krylov CSLP solves (FP64: `steps` Arnoldi steps per pair of
+    passes).  The block at step j reads m = j + 1 basis vectors in pass A (with
+    the `steps` vectors M^r v_j) and again in pass B (with them, and `steps`
+    vectors written).  When the basis exceeds the 256 MB plain-load limit, the
+    vectors older than the 200 MB recent window come from HBM and the rest from
+    the Infinity Cache; a smaller basis is cache-resident."""
     vec = float(n) * es
     recent = int(200.0 * 2**20 / vec)
     alg = hbm = 0.0
-    for steps in counts:
-        for j in range(0, steps, 2):
+    for count in counts:
+        for j in range(0, count, steps):
             m = j + 1
-            if cls == "cgs_update_norm" and j + 1 >= steps:
-                continue                      # the pair's second step is not taken
-            alg += (m + 2 if cls == "cgs_dot" else m + 4) * vec
+            alg += (m + steps if cls == "cgs_dot" else m + 2 * steps) * vec
             if (m + 1) * vec > 256.0 * 2**20:
                 hbm += max(0, m - recent) * vec
     return hbm / alg if alg else None
@@ -571,9 +568,11 @@ def _short_kernel(name):
 
 # kernel classes of the bench line and the kernels each one times
 TRAFFIC_CLASSES = {
-    "cgs_dot": ("k_multidot2<double, true>", "k_multidot2<double, false>",
+    "cgs_dot": ("k_multidots<double, true, 3>", "k_multidots<double, false, 3>",
+                "k_multidots<double, true, 2>", "k_multidots<double, false, 2>",
                 "k_multidot<double, true>", "k_multidot<double, false>"),
-    "cgs_update_norm": ("k_cgs_update2<double, true>", "k_cgs_update2<double, false>",
+    "cgs_update_norm": ("k_updates<double, true, 3>", "k_updates<double, false, 3>",
+                        "k_updates<double, true, 2>", "k_updates<double, false, 2>",
                         "k_cgs_update_norm<double, true>", "k_cgs_update_norm<double, false>"),
     "wide_stencil_apply": ("k_wide_persist<double, 3, 3>",),
 }
@@ -997,8 +996,8 @@ def main():
                     "share_of_bytes": share, "achieved": d["GBps"] * share,
                     "frac": d["GBps"] * share / HBM_PEAK_GBS,
                     "model": "basis vectors older than the 200 MB recent window of bases above "
-                             "256 MB, per pass of the recorded Krylov CSLP counts (two steps per "
-                             "pair of passes)"}
+                             "256 MB, per pass of the recorded Krylov CSLP counts (three steps "
+                             "per pair of passes)"}
         # measured ceilings of this GPU (a plain copy, a read-only stream), taken
         # after the timed region with the solver's memory released
         ceil = bandwidth_ceilings(torch)

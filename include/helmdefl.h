@@ -256,20 +256,22 @@ hm_status hm_set_basis_cache(hm_problem* p, double basis_bytes, double recent_by
  * level host-driven).  HM_ERR_ARG for a null problem. */
 hm_status hm_set_small_krylov(hm_problem* p, int enable);
 
-/* Two Arnoldi steps per read of the basis in the classical Gram-Schmidt GMRES of
- * the Krylov CSLP (Sec. 4.2) on FP64 levels that are not solved in one
- * workgroup: with z = M v_j and y = M z, one pass over the basis takes the dots
- * of z and y; step j+1's Hessenberg column follows from them through the Arnoldi
- * relation, and a second pass forms v_{j+1} and step j+1's new vector.  The
- * iterates are those of one-step classical Gram-Schmidt in exact arithmetic
- * (reading R18); the basis is read once per step instead of twice.  FP32 levels
- * keep one step per two passes (the paired relations hold only to the basis's
- * orthogonality).  The columns and the second pass's coefficients are formed
- * on the device between the passes, so a pair runs without the host.  mode:
- * HM_PAIRS_ON (default) or HM_PAIRS_OFF (one step per two passes).  HM_ERR_ARG
- * for a null problem or another mode. */
-enum { HM_PAIRS_OFF = 0, HM_PAIRS_ON = 1 };
-hm_status hm_set_krylov_pairs(hm_problem* p, int mode);
+/* Arnoldi steps per two passes over the basis in the classical Gram-Schmidt
+ * GMRES of the Krylov CSLP (Sec. 4.2) on FP64 levels that are not solved in one
+ * workgroup.  With steps = S > 1, the block of steps j..j+S-1 applies M to v_j
+ * and then S - 1 more times (Y_0 = M v_j, Y_{k+1} = M Y_k); one pass over the
+ * basis takes the inner products of [V_0..V_j, Y] with Y, classical
+ * Gram-Schmidt runs on the device in the coordinates of [V_0..V_j, Y] (M acting
+ * on V through the Hessenberg columns already formed), and a second pass forms
+ * v_{j+1}..v_{j+S-1} and the last step's new vector.  The iterates are those of
+ * one-step classical Gram-Schmidt in exact arithmetic (reading R18); the basis
+ * is read 2/S times per step instead of twice.  FP32 levels keep one step per
+ * two passes (the coordinate relations hold only to the basis's
+ * orthogonality).  steps: 1 (one step per two passes), 2 or
+ * HM_KRYLOV_STEPS_MAX = 3 (default).  HM_ERR_ARG for a null problem or another
+ * count. */
+#define HM_KRYLOV_STEPS_MAX 3
+hm_status hm_set_krylov_steps(hm_problem* p, int steps);
 
 hm_status hm_destroy_problem(hm_problem* p);
 

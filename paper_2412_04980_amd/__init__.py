@@ -49,7 +49,7 @@ TIMING_CLASSES = {HM_TK_CGS_DOT: "cgs_dot", HM_TK_CGS_UPDATE: "cgs_update_norm",
 EXPORTED = ["hm_default_config", "hm_workspace_bytes", "hm_create_problem", "hm_precond_apply",
             "hm_fgmres_solve", "hm_apply_operator", "hm_level_shape", "hm_set_replay",
             "hm_get_counts", "hm_reset_counts", "hm_set_timing", "hm_get_timing",
-            "hm_set_basis_cache", "hm_set_small_krylov", "hm_set_krylov_pairs",
+            "hm_set_basis_cache", "hm_set_small_krylov", "hm_set_krylov_steps",
             "hm_destroy_problem", "hm_matfree_apply", "hm_csr_assemble", "hm_csr_spmv",
             "hm_batch_workspace_bytes", "hm_create_batch", "hm_batch_solve", "hm_batch_member",
             "hm_destroy_batch", "hm_residual_workspace_bytes", "hm_residual",
@@ -118,7 +118,7 @@ def _load():
                               ctypes.POINTER(ctypes.c_long)]),
         "hm_set_basis_cache": (I, [P, D, D]),
         "hm_set_small_krylov": (I, [P, I]),
-        "hm_set_krylov_pairs": (I, [P, I]),
+        "hm_set_krylov_steps": (I, [P, I]),
         "hm_destroy_problem": (I, [P]),
         "hm_matfree_apply": (I, [I, I, D, P, P, P, P]),
         "hm_csr_assemble": (I, [I, I, D, P, P, P, P, P]),
@@ -321,13 +321,13 @@ def set_small_krylov(prob, enable=True):
     _check(_lib.hm_set_small_krylov(prob.handle, 1 if enable else 0))
 
 
-PAIRS_OFF, PAIRS_ON = 0, 1
+KRYLOV_STEPS_MAX = 3
 
 
-def set_krylov_pairs(prob, mode=PAIRS_ON):
-    """Two Arnoldi steps per read of the basis in the Krylov CSLP of FP64
-    levels: PAIRS_ON (default) or PAIRS_OFF."""
-    _check(_lib.hm_set_krylov_pairs(prob.handle, int(mode)))
+def set_krylov_steps(prob, steps=KRYLOV_STEPS_MAX):
+    """Arnoldi steps per two passes over the basis in the Krylov CSLP of FP64
+    levels: 1, 2 or KRYLOV_STEPS_MAX (default)."""
+    _check(_lib.hm_set_krylov_steps(prob.handle, int(steps)))
 
 
 def set_basis_cache(prob, basis_bytes=-1.0, recent_bytes=-1.0):

@@ -1168,96 +1168,102 @@ __global__ void __launch_bounds__(NT) k_multidot(const cx<T>* __restrict__ V, si
   }
 }
 
-// ---- two Arnoldi steps per sweep over the basis --------------------------------
-// Pass A: the partial dots of z and y with NG left vectors vp[0..NG-1] over one
-// chunk, each thread two rows per pass (all loads of the two rows in flight).
-template <typename T, int NG, bool NTL, int GA>
-__device__ __forceinline__ void dot2_rows(const cx<T>* const* vp, const cx<T>* __restrict__ zv,
-                                          const cx<T>* __restrict__ yv, size_t lo, size_t hi,
-                                          double (*re)[GA], double (*im)[GA]) {
+// ---- S Arnoldi steps per pair of sweeps over the basis (S = 1, 2, 3) ----------
+// Pass A reads the basis vectors GP per block.
+constexpr int GP = 2;
+// Pass A rows: the partial dots of the S right vectors Y_0..Y_{S-1} with NG left
+// vectors vp[0..NG-1] over one chunk, each thread two rows per pass.
+template <typename T, int NG, bool NTL, int S>
+__device__ __forceinline__ void dots_rows(const cx<T>* const* vp, const cx<T>* const* yp,
+                                          size_t lo, size_t hi, double (*re)[GP],
+                                          double (*im)[GP]) {
   size_t i = lo + threadIdx.x;
   for (; i + NT < hi; i += 2 * NT) {
-    const cx<T> za = zv[i], zb = zv[i + NT], ya = yv[i], yb = yv[i + NT];
-    cx<T> va[NG], vb[NG];
+    cx<T> ya[S], yb[S], va[NG], vb[NG];
+#pragma unroll
+    for (int r = 0; r < S; ++r) { ya[r] = yp[r][i]; yb[r] = yp[r][i + NT]; }
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
       va[g] = NTL ? load_stream(vp[g] + i) : vp[g][i];
       vb[g] = NTL ? load_stream(vp[g] + i + NT) : vp[g][i + NT];
     }
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      dot_acc(re[0][g], im[0][g], va[g], za);
-      dot_acc(re[0][g], im[0][g], vb[g], zb);
-      dot_acc(re[1][g], im[1][g], va[g], ya);
-      dot_acc(re[1][g], im[1][g], vb[g], yb);
-    }
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        dot_acc(re[r][g], im[r][g], va[g], ya[r]);
+        dot_acc(re[r][g], im[r][g], vb[g], yb[r]);
+      }
   }
   if (i < hi) {
-    const cx<T> za = zv[i], ya = yv[i];
-    cx<T> v[NG];
+    cx<T> y[S], v[NG];
+#pragma unroll
+    for (int r = 0; r < S; ++r) y[r] = yp[r][i];
 #pragma unroll
     for (int g = 0; g < NG; ++g) v[g] = NTL ? load_stream(vp[g] + i) : vp[g][i];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      dot_acc(re[0][g], im[0][g], v[g], za);
-      dot_acc(re[1][g], im[1][g], v[g], ya);
-    }
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+      for (int g = 0; g < NG; ++g) dot_acc(re[r][g], im[r][g], v[g], y[r]);
   }
 }
 
-// Pass A of a pair of Arnoldi steps (z = M v_j, y = M z): the dots of z and y
-// with V_0..V_{m-1} and with z and y themselves, in one read of the basis.
-// Block = (chunk, group); group gi < ngv holds V_{GP gi}..V_{GP gi + GP - 1},
-// group ngv holds (z, y).  Value r (m + 2) + i for right vector r (0: z, 1: y)
-// and left vector i (V_i for i < m, then z, y): partials[value * nchunks +
-// chunk].  Two basis vectors per group keep the accumulators (and registers)
-// of a thread at those of the one-vector dot pass, so as many waves stay
-// resident; z and y are re-read per group from the caches.  The chunks, the
-// XCD-aware block order and the load policy are those of k_multidot.
-constexpr int GP = 2;
-template <typename T, bool STREAM>
-__global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, size_t ldv, int m,
-                                                  const cx<T>* __restrict__ zv,
-                                                  const cx<T>* __restrict__ yv, size_t n,
+// Pass A of S Arnoldi steps (Y_0 = z = M v_j, Y_{k+1} = M Y_k): the dots of
+// Y_0..Y_{S-1} with V_0..V_{m-1} and with the Y themselves, in one read of the
+// basis.  Block = (chunk, group): group gi < ngv holds V_{GP gi}..V_{GP gi + 1},
+// the groups after it hold the Y, GP at a time.  Value r (m + S) + i for right
+// vector Y_r and left vector i (V_i for i < m, then Y_{i-m}):
+// partials[value * nchunks + chunk].  Chunks, block order and load policy as
+// k_multidot.
+template <typename T, bool STREAM, int S>
+__global__ void __launch_bounds__(NT) k_multidots(const cx<T>* __restrict__ V, size_t ldv, int m,
+                                                  const cx<T>* __restrict__ y0,
+                                                  const cx<T>* __restrict__ y1,
+                                                  const cx<T>* __restrict__ y2, size_t n,
                                                   size_t clen, c128* __restrict__ partials,
                                                   int nchunks, int recent, Batch z) {
-  __shared__ double sh[NT / 64][4 * GP];
-  HM_MEMBER(V); HM_MEMBER(zv); HM_MEMBER(yv); HM_MEMBER(partials);
-  const int ngv = (m + GP - 1) / GP, ngroups = ngv + 1;
+  __shared__ double sh[NT / 64][2 * S * GP];
+  HM_MEMBER(V); HM_MEMBER(y0); HM_MEMBER(y1); HM_MEMBER(y2); HM_MEMBER(partials);
+  const cx<T>* yp[3] = {y0, y1, y2};
+  constexpr int ngy = (S + GP - 1) / GP;
+  const int ngv = (m + GP - 1) / GP, ngroups = ngv + ngy;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
   const int chunk = (local / ngroups) * 8 + xcd;
   const int gi = local % ngroups;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double re[2][GP], im[2][GP];
+  double re[S][GP], im[S][GP];
 #pragma unroll
-  for (int g = 0; g < GP; ++g) { re[0][g] = im[0][g] = re[1][g] = im[1][g] = 0; }
-  int first, gm;                                 // first value index, left vectors
+  for (int r = 0; r < S; ++r)
+#pragma unroll
+    for (int g = 0; g < GP; ++g) re[r][g] = im[r][g] = 0;
+  int first, gm;                                 // first left index, left vectors
+  const cx<T>* vp[GP];
+  bool ntl = false;
   if (gi < ngv) {
-    const int i0 = gi * GP;
-    gm = m - i0 < GP ? m - i0 : GP;
-    first = i0;
-    const bool ntl = STREAM && i0 + gm <= m - recent;
-    const cx<T>* vp[GP];
+    first = gi * GP;
+    gm = m - first < GP ? m - first : GP;
+    ntl = STREAM && first + gm <= m - recent;
 #pragma unroll
-    for (int g = 0; g < GP; ++g) vp[g] = V + (size_t)(i0 + (g < gm ? g : 0)) * ldv;
-    static_assert(GP == 2, "the group tails below cover GP = 2");
-    if (gm == 2) {
-      if (ntl) dot2_rows<T, 2, true>(vp, zv, yv, lo, hi, re, im);
-      else dot2_rows<T, 2, false>(vp, zv, yv, lo, hi, re, im);
-    } else {
-      if (ntl) dot2_rows<T, 1, true>(vp, zv, yv, lo, hi, re, im);
-      else dot2_rows<T, 1, false>(vp, zv, yv, lo, hi, re, im);
-    }
+    for (int g = 0; g < GP; ++g) vp[g] = V + (size_t)(first + (g < gm ? g : 0)) * ldv;
   } else {
-    gm = 2;
-    first = m;
-    const cx<T>* vp[2] = {zv, yv};
-    dot2_rows<T, 2, false>(vp, zv, yv, lo, hi, re, im);
+    const int k0 = (gi - ngv) * GP;
+    first = m + k0;
+    gm = S - k0 < GP ? S - k0 : GP;
+#pragma unroll
+    for (int g = 0; g < GP; ++g) vp[g] = yp[k0 + (g < gm ? g : 0)];
+  }
+  static_assert(GP == 2, "the group tails below cover GP = 2");
+  if (gm == 2) {
+    if (ntl) dots_rows<T, 2, true, S>(vp, yp, lo, hi, re, im);
+    else dots_rows<T, 2, false, S>(vp, yp, lo, hi, re, im);
+  } else {
+    if (ntl) dots_rows<T, 1, true, S>(vp, yp, lo, hi, re, im);
+    else dots_rows<T, 1, false, S>(vp, yp, lo, hi, re, im);
   }
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < S; ++r)
 #pragma unroll
     for (int g = 0; g < GP; ++g) {
       re[r][g] = wave_sum(re[r][g]);
@@ -1265,7 +1271,7 @@ __global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, s
     }
   if (lane == 0) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < S; ++r)
 #pragma unroll
       for (int g = 0; g < GP; ++g) {
         sh[wid][2 * (r * GP + g)] = re[r][g];
@@ -1273,7 +1279,7 @@ __global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, s
       }
   }
   __syncthreads();
-  if (threadIdx.x < 2 * GP) {
+  if (threadIdx.x < S * GP) {
     const int r = threadIdx.x / GP, g = threadIdx.x - r * GP;
     if (g < gm) {
       double sr = 0, si = 0;
@@ -1281,7 +1287,7 @@ __global__ void __launch_bounds__(NT) k_multidot2(const cx<T>* __restrict__ V, s
         sr += sh[w2][2 * (r * GP + g)];
         si += sh[w2][2 * (r * GP + g) + 1];
       }
-      partials[(size_t)(r * (m + 2) + first + g) * nchunks + chunk] = mk(sr, si);
+      partials[(size_t)(r * (m + S) + first + g) * nchunks + chunk] = mk(sr, si);
     }
   }
 }
@@ -1419,137 +1425,77 @@ __global__ void __launch_bounds__(NT) k_cgs_update_norm(cx<T>* __restrict__ w, c
   if (threadIdx.x == 0) partials[chunk] = s;
 }
 
-// Pass B of a pair of Arnoldi steps, one read of the basis:
-//   v_new = ca[m] z + sum_i ca[i] V_i       (written to V_m)
-//   w'    = ca[m] y + cg[m] z + sum_i cg[i] V_i   (written over z)
-// with the partial ||w'||^2 of one chunk; every thread takes two elements per
-// pass.  Chunks and load policy as k_cgs_update_norm.
-template <typename T, bool STREAM>
-__global__ void __launch_bounds__(NT) k_cgs_update2(cx<T>* __restrict__ zv,
-                                                    const cx<T>* __restrict__ yv,
-                                                    cx<T>* __restrict__ V, size_t ldv, int m,
-                                                    const c128* __restrict__ ca,
-                                                    const c128* __restrict__ cg, size_t n,
-                                                    size_t clen, c128* __restrict__ partials,
-                                                    int recent, Batch z) {
+// Pass B of S Arnoldi steps, one read of the basis: with coefficient rows
+// C_t = coef + t cld (V_i at C_t[i], Y_k at C_t[m + k]),
+//   V_{m+t} = sum_i C_t[i] V_i + sum_k C_t[m+k] Y_k   (t = 0..S-2, new basis vectors)
+//   Y_0    <- sum_i C_{S-1}[i] V_i + sum_k C_{S-1}[m+k] Y_k   (the next unnormalised vector)
+// with the partial ||Y_0||^2 of one chunk; two elements per thread per pass.
+// Chunks and load policy as k_cgs_update_norm.
+template <typename T, bool STREAM, int S>
+__global__ void __launch_bounds__(NT) k_updates(cx<T>* __restrict__ y0,
+                                                const cx<T>* __restrict__ y1,
+                                                const cx<T>* __restrict__ y2,
+                                                cx<T>* __restrict__ V, size_t ldv, int m,
+                                                const c128* __restrict__ coef, int cld, size_t n,
+                                                size_t clen, c128* __restrict__ partials,
+                                                int recent, Batch z) {
   __shared__ double sh[2 * NT / 64];
-  HM_MEMBER(zv); HM_MEMBER(yv); HM_MEMBER(V); HM_MEMBER(ca); HM_MEMBER(cg); HM_MEMBER(partials);
+  HM_MEMBER(y0); HM_MEMBER(y1); HM_MEMBER(y2); HM_MEMBER(V); HM_MEMBER(coef);
+  HM_MEMBER(partials);
+  const cx<T>* yp[3] = {y0, y1, y2};
   const int chunk = (int)blockIdx.x;
   const size_t lo = (size_t)chunk * clen;
   const size_t hi = lo + clen < n ? lo + clen : n;
-  const c128 az = ca[m], gz = cg[m];
-  cx<T>* __restrict__ vnew = V + (size_t)m * ldv;
   double acc = 0;
   for (size_t i = lo + threadIdx.x; i < hi; i += 2 * NT) {
     const size_t i2 = i + NT;
     const bool two = i2 < hi;
-    const cx<T> z0 = zv[i], y0 = yv[i];
-    const cx<T> z1 = two ? zv[i2] : mk(T(0), T(0)), y1 = two ? yv[i2] : mk(T(0), T(0));
-    double vr0 = 0, vi0 = 0, wr0 = 0, wi0 = 0, vr1 = 0, vi1 = 0, wr1 = 0, wi1 = 0;
-#pragma unroll 4
+    double r0[S], q0[S], r1[S], q1[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) r0[t] = q0[t] = r1[t] = q1[t] = 0;
+#pragma unroll 2
     for (int j = 0; j < m; ++j) {
-      const c128 a = ca[j], c = cg[j];
       const bool old = STREAM && j < m - recent;
       const cx<T> v0 = old ? load_stream(V + (size_t)j * ldv + i) : V[(size_t)j * ldv + i];
-      upd_acc(vr0, vi0, a, v0);
-      upd_acc(wr0, wi0, c, v0);
-      if (two) {
-        const cx<T> v1 = old ? load_stream(V + (size_t)j * ldv + i2) : V[(size_t)j * ldv + i2];
-        upd_acc(vr1, vi1, a, v1);
-        upd_acc(wr1, wi1, c, v1);
+      const cx<T> v1 = two ? (old ? load_stream(V + (size_t)j * ldv + i2)
+                                  : V[(size_t)j * ldv + i2])
+                           : mk(T(0), T(0));
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        const c128 c = coef[(size_t)t * cld + j];
+        upd_acc(r0[t], q0[t], c, v0);
+        upd_acc(r1[t], q1[t], c, v1);
       }
     }
-    upd_acc(vr0, vi0, az, z0);
-    upd_acc(wr0, wi0, az, y0);
-    upd_acc(wr0, wi0, gz, z0);
-    vnew[i] = mk((T)vr0, (T)vi0);
-    const cx<T> n0 = mk((T)wr0, (T)wi0);
-    zv[i] = n0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      const cx<T> a = yp[k][i];
+      const cx<T> b = two ? yp[k][i2] : mk(T(0), T(0));
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        const c128 c = coef[(size_t)t * cld + m + k];
+        upd_acc(r0[t], q0[t], c, a);
+        upd_acc(r1[t], q1[t], c, b);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t + 1 < S; ++t) {
+      V[(size_t)(m + t) * ldv + i] = mk((T)r0[t], (T)q0[t]);
+      if (two) V[(size_t)(m + t) * ldv + i2] = mk((T)r1[t], (T)q1[t]);
+    }
+    const cx<T> n0 = mk((T)r0[S - 1], (T)q0[S - 1]);
+    y0[i] = n0;
     acc = fma((double)n0.re, (double)n0.re, acc);
     acc = fma((double)n0.im, (double)n0.im, acc);
     if (two) {
-      upd_acc(vr1, vi1, az, z1);
-      upd_acc(wr1, wi1, az, y1);
-      upd_acc(wr1, wi1, gz, z1);
-      vnew[i2] = mk((T)vr1, (T)vi1);
-      const cx<T> n1 = mk((T)wr1, (T)wi1);
-      zv[i2] = n1;
+      const cx<T> n1 = mk((T)r1[S - 1], (T)q1[S - 1]);
+      y0[i2] = n1;
       acc = fma((double)n1.re, (double)n1.re, acc);
       acc = fma((double)n1.im, (double)n1.im, acc);
     }
   }
   const c128 s = block_sum(acc, 0.0, sh);
   if (threadIdx.x == 0) partials[chunk] = s;
-}
-
-// Between the passes of a pair of Arnoldi steps (one block per member): from
-// pass A's dots d = [V; z; y]^H [z; y] (d[0..m+1] with z, d[m+2..2m+3] with y;
-// m = j + 1) and the Hessenberg columns 0..j-1 in H (stride ld), the columns of
-// steps j and j+1 and pass B's coefficients:
-//   a = V^H z, b_j = (z^H z - |a|^2)^(1/2), g = H_{0..j, 0..j-1} a_{0..j-1},
-//   h' = (c - g - a_j a) / b_j with c = V^H y,  h'_{j+1} = (z^H y - a^H c) / b_j^2 - a_j,
-//   ca = (-a / b_j, 1 / b_j),  cg = (-g / b_j - h' + a h'_{j+1} / b_j, -(a_j + h'_{j+1}) / b_j).
-// Column j (rows 0..j+1) and column j+1 (rows 0..j+1) go to H and to the pinned
-// host mirror Hh (same layout); ca to coef[0..m], cg to coef[ld..ld+m].  b_j = 0
-// (breakdown) leaves non-finite coefficients, whose pass B output the solve
-// never uses (the host stops the member at step j).
-__global__ void __launch_bounds__(NT) k_pair_coef(const c128* __restrict__ d, c128* __restrict__ H,
-                                                  int ld, int j, c128* __restrict__ coef,
-                                                  c128* __restrict__ Hh, Batch z) {
-  __shared__ double sh[2 * NT / 64];
-  __shared__ c128 sc[2];                       // a^H c, 1 / b_j
-  __shared__ double sb;
-  HM_MEMBER(d); HM_MEMBER(H); HM_MEMBER(coef);
-  Hh = at_member(Hh, z.hz, z);
-  const int m = j + 1;
-  const c128* dz = d;
-  const c128* dy = d + (m + 2);
-  // |a|^2 and a^H c over the block
-  double aa = 0, acr = 0, aci = 0;
-  for (int i = threadIdx.x; i < m; i += NT) {
-    const c128 a = dz[i], c = dy[i];
-    aa = fma(a.re, a.re, fma(a.im, a.im, aa));
-    acr = fma(a.re, c.re, fma(a.im, c.im, acr));
-    aci = fma(a.re, c.im, fma(-a.im, c.re, aci));
-  }
-  const c128 s1 = block_sum(aa, 0.0, sh);
-  __syncthreads();
-  const c128 s2 = block_sum(acr, aci, sh);
-  if (threadIdx.x == 0) {
-    const double b2 = dz[m].re - s1.re;
-    sb = b2 > 0 ? sqrt(b2) : 0.0;
-    sc[0] = s2;
-  }
-  __syncthreads();
-  const double bj = sb, ib = 1.0 / bj;
-  const c128 aj = dz[j];
-  const c128 hn = (ib * ib) * (dy[m] - sc[0]) - aj;
-  c128* colj = H + (size_t)j * ld;
-  c128* colj1 = colj + ld;
-  c128* hj = Hh + (size_t)j * ld;
-  c128* hj1 = hj + ld;
-  for (int r = threadIdx.x; r <= m; r += NT) {
-    if (r < m) {
-      // g_r = sum_{i = max(0, r-1)}^{j-1} H[r, i] a_i
-      c128 g = mk(0.0, 0.0);
-      for (int i = r > 0 ? r - 1 : 0; i < j; ++i) g = g + H[(size_t)i * ld + r] * dz[i];
-      const c128 a = dz[r];
-      const c128 hv = ib * (dy[r] - g - aj * a);
-      colj[r] = a;
-      hj[r] = a;
-      colj1[r] = hv;
-      hj1[r] = hv;
-      coef[r] = (-ib) * a;
-      coef[ld + r] = (-ib) * g - hv + a * (ib * hn);
-    } else {
-      colj[m] = mk(bj, 0.0);
-      hj[m] = mk(bj, 0.0);
-      colj1[m] = hn;
-      hj1[m] = hn;
-      coef[m] = mk(ib, 0.0);
-      coef[ld + m] = (-ib) * (aj + hn);
-    }
-  }
 }
 
 template <typename T>
@@ -2422,51 +2368,307 @@ hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t 
   return hipGetLastError();
 }
 
-// Pass A of a pair of Arnoldi steps and its final sums: out[r (m + 2) + i] =
-// (left vector i)^H (right vector r), left vectors V_0..V_{m-1}, z, y; right
-// vectors z, y (also to the pinned host_out).
+// Between the passes of S Arnoldi steps (one block per member): Arnoldi in the
+// coordinates of B = [V_0..V_j, Y_0..Y_{S-1}] (m = j + 1 basis vectors, taken
+// as orthonormal) with the inner products of pass A (d[r (m + S) + i] =
+// (left i)^H Y_r), G = B^H B.  M acts on coordinates through the Hessenberg
+// columns 0..j-1 in H (M V_i = V H_{., i}), M v_j = Y_0 and M Y_k = Y_{k+1}.
+// Step j + t (t < S) takes w = M q_{j+t}, h = <q_l, w>_G for every earlier
+// vector (classical Gram-Schmidt, one pass), w -= sum h_l q_l and, for
+// t < S - 1, q_{j+t+1} = w / <w, w>_G^(1/2); the last step's subdiagonal entry
+// is the explicit norm that pass B takes.  Columns j..j+S-1 go to H and the
+// pinned mirror Hh; pass B's coefficient rows (the coordinates of
+// q_{j+1}..q_{j+S-1} and of the last w) to coef, cld apart.  Coordinates in
+// LDS: nb = m + S <= kCoefMax.
+// The kernel is one workgroup whose time is latency.  The coordinate work
+// (O(m S) per step) runs in wave 0 alone, lane l holding rows l, l + 64, ...,
+// so its sums are wave reductions without barriers; the products with H
+// (t >= 1, O(m^2)) are split evenly over every wave.
+constexpr int kCoefMax = 512;
+constexpr int NC = 512;
+constexpr int NWC = NC / 64;
+
+// Sums over one wave of NV complex values (valid in every lane); the
+// butterfly steps of all values interleaved.
+template <int NV>
+__device__ __forceinline__ void wave_sums(c128 (&v)[NV]) {
+  double r[2 * NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    r[2 * q] = v[q].re;
+    r[2 * q + 1] = v[q].im;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < 2 * NV; ++q) r[q] += __shfl_xor(r[q], off, 64);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = mk(r[2 * q], r[2 * q + 1]);
+}
+
+// Orders the LDS accesses of one wave (its lanes run in lockstep and its LDS
+// operations complete in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int S>
+__global__ void __launch_bounds__(NC) k_coefs(const c128* __restrict__ d, c128* __restrict__ H,
+                                              int ld, int j, c128* __restrict__ coef, int cld,
+                                              c128* __restrict__ Hh, Batch z) {
+  __shared__ c128 Dl[S * kCoefMax];             // pass A's dots
+  __shared__ c128 Q[S][kCoefMax];               // q_{j+1}.. (t < S - 1) and the last w
+  __shared__ c128 Gw[kCoefMax];                 // G w (rows < m)
+  __shared__ c128 part[NWC][kCoefMax];          // per-wave partial rows of H p
+  HM_MEMBER(d); HM_MEMBER(H); HM_MEMBER(coef);
+  Hh = at_member(Hh, z.hz, z);
+  const int m = j + 1, nb = m + S, tid = threadIdx.x, lane = tid & 63;
+  const bool w0 = tid < 64;
+  for (int i = tid; i < S * nb; i += NC) Dl[i] = d[i];
+  __syncthreads();
+  auto VY = [&](int i, int k) { return Dl[k * nb + i]; };        // V_i^H Y_k
+  auto YY = [&](int k, int l) { return Dl[l * nb + m + k]; };    // Y_k^H Y_l
+  // (wave 0) G P into Gw (rows < m, lane-owned) and gy (rows m.., every lane),
+  // with out[s] = <L_s, P>_G for the NL coordinate rows L_s
+  auto gram_dots = [&](const c128* P, auto& out, const c128* const* L, c128 (&gy)[S]) {
+    constexpr int NL = sizeof(out) / sizeof(c128);
+    c128 v[S + NL];
+#pragma unroll
+    for (int q = 0; q < S + NL; ++q) v[q] = mk(0.0, 0.0);
+    for (int i = lane; i < m; i += 64) {
+      c128 g = P[i];
+      const c128 pi = P[i];
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        const c128 vy = VY(i, k);
+        g = g + vy * P[m + k];
+        v[k] = v[k] + cmulc(vy, pi);
+      }
+      Gw[i] = g;
+#pragma unroll
+      for (int s2 = 0; s2 < NL; ++s2) v[S + s2] = v[S + s2] + cmulc(L[s2][i], g);
+    }
+    wave_sums<S + NL>(v);
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+      c128 g = v[k];
+#pragma unroll
+      for (int l = 0; l < S; ++l) g = g + YY(k, l) * P[m + l];
+      gy[k] = g;
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < NL; ++s2) {
+      c128 o = v[S + s2];
+#pragma unroll
+      for (int k = 0; k < S; ++k) o = o + cmulc(L[s2][m + k], gy[k]);
+      out[s2] = o;
+    }
+  };
+  // (every wave) rows < m of M P, sum_{i = max(0, r-1)}^{j-1} H[r, i] P_i, into
+  // out.  The work is the (row band of 64, column) pairs whose column reaches
+  // the band, in band-major order, split evenly over the waves; a wave reads
+  // one column of a band per load (coalesced), sixteen loads in flight, and
+  // stores its sum for a band into its own partial row; the partials are
+  // added in wave order (the result does not depend on timing).
+  auto h_product = [&](const c128* P, c128* out) {
+    const int nbands = (m + 63) >> 6;
+    auto lo = [&](int bb) { return bb > 0 ? 64 * bb - 1 : 0; };
+    int T = 0;
+    for (int bb = 0; bb < nbands; ++bb) T += j > lo(bb) ? j - lo(bb) : 0;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    c128* mine = part[wv];
+    for (int r = lane; r < m; r += 64) mine[r] = mk(0.0, 0.0);
+    const int beg = (int)((long long)T * wv / NWC), end = (int)((long long)T * (wv + 1) / NWC);
+    int b = 0, i = 0, rem = beg;
+    for (; b < nbands; ++b) {
+      const int len = j > lo(b) ? j - lo(b) : 0;
+      if (rem < len) {
+        i = lo(b) + rem;
+        break;
+      }
+      rem -= len;
+    }
+    int bcur = b;
+    c128 acc = mk(0.0, 0.0);
+    auto flush = [&](int bb) {
+      const int r = 64 * bb + lane;
+      if (r < m) mine[r] = acc;                // each band once per wave
+    };
+    for (int cnt = end - beg; cnt > 0; cnt -= 16) {
+      c128 hv[16];
+      int bq[16], iq[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        bq[q] = b;
+        iq[q] = i;
+        const int r = 64 * b + lane;
+        hv[q] = (q < cnt && r < m && i + 1 >= r) ? H[(size_t)i * ld + r] : mk(0.0, 0.0);
+        if (q < cnt && ++i == j) {
+          ++b;
+          i = lo(b);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (q < cnt) {
+          if (bq[q] != bcur) {
+            flush(bcur);
+            acc = mk(0.0, 0.0);
+            bcur = bq[q];
+          }
+          acc = acc + hv[q] * P[iq[q]];
+        }
+      }
+    }
+    if (end > beg) flush(bcur);
+    __syncthreads();
+    if (w0)
+      for (int r = lane; r < m; r += 64) {
+        c128 g = part[0][r];
+        for (int w = 1; w < NWC; ++w) g = g + part[w][r];
+        out[r] = g;
+      }
+  };
+  c128* W = Q[S - 1];                           // w of the current step (last row reused)
+#pragma unroll 1
+  for (int t = 0; t < S; ++t) {
+    // w = M q_{j+t}
+    if (t > 0) {
+      __syncthreads();                          // q_{j+t} (wave 0) for every wave
+      h_product(Q[t - 1], W);                   // W is not Q[t - 1] (t - 1 < S - 1)
+    }
+    if (!w0) continue;
+    if (t == 0) {
+      for (int i = lane; i < nb; i += 64) W[i] = mk(i == m ? 1.0 : 0.0, 0.0);
+    } else {
+      const c128* P = Q[t - 1];                 // its last Y coordinate is 0
+      for (int i = lane; i < nb; i += 64)
+        if (i >= m) W[i] = i == m ? P[j] : P[i - 1];
+    }
+    wave_lds_order();
+    // h: <e_l, w>_G = (G w)_l for l <= j; <q_{j+1+s}, w>_G for s < t
+    c128 gy[S];
+    c128 hs[S > 1 ? S - 1 : 1];
+    const c128* L[S > 1 ? S - 1 : 1];
+#pragma unroll
+    for (int s2 = 0; s2 < (S > 1 ? S - 1 : 1); ++s2) {
+      L[s2] = Q[s2];
+      hs[s2] = mk(0.0, 0.0);
+    }
+    if (t == 0) {
+      c128 none[1];
+      const c128* L0[1] = {W};
+      gram_dots(W, none, L0, gy);               // (the dot is not used)
+    } else if (S >= 2 && t == 1) {
+      c128 h1[1];
+      gram_dots(W, h1, L, gy);
+      hs[0] = h1[0];
+    } else if (S >= 3 && t == 2) {
+      c128 h2[2];
+      gram_dots(W, h2, L, gy);
+      hs[0] = h2[0];
+      hs[1] = h2[1];
+    }
+    c128* col = H + (size_t)(j + t) * ld;
+    c128* hcol = Hh + (size_t)(j + t) * ld;
+    for (int l = lane; l <= j; l += 64) {
+      col[l] = Gw[l];
+      hcol[l] = Gw[l];
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int s2 = 0; s2 < t; ++s2) {
+        col[j + 1 + s2] = hs[s2];
+        hcol[j + 1 + s2] = hs[s2];
+      }
+    }
+    wave_lds_order();                           // w's Y part read by every lane
+    // w -= sum_l h_l q_l (the e_l part first, then the earlier q's)
+    for (int i = lane; i < nb; i += 64) {
+      c128 v = W[i];
+      if (i <= j) v = v - Gw[i];
+#pragma unroll
+      for (int s2 = 0; s2 < t; ++s2) v = v - hs[s2] * Q[s2][i];
+      W[i] = v;
+    }
+    wave_lds_order();
+    if (t + 1 < S) {
+      c128 ww[1];
+      const c128* LW[1] = {W};
+      gram_dots(W, ww, LW, gy);
+      const double bt = ww[0].re > 0 ? sqrt(ww[0].re) : 0.0, ib = 1.0 / bt;
+      if (lane == 0) {
+        col[j + t + 1] = mk(bt, 0.0);
+        hcol[j + t + 1] = mk(bt, 0.0);
+      }
+      for (int i = lane; i < nb; i += 64) Q[t][i] = ib * W[i];
+      wave_lds_order();
+    }
+  }
+  // pass B's rows (wave 0): q_{j+1}..q_{j+S-1}, then the last w
+  if (w0)
+    for (int t = 0; t < S; ++t)
+      for (int i = lane; i < nb; i += 64) coef[(size_t)t * cld + i] = Q[t][i];
+}
+
+// Pass A of S Arnoldi steps and its final sums: out[r (m + S) + i].
 template <typename T>
-hipError_t launch_multidot2(const cx<T>* V, size_t ldv, int m, const cx<T>* zv, const cx<T>* yv,
-                            size_t n, RedBuf rb, c128* out, c128* host_out, hipStream_t s,
-                            const Batch& z, const CachePolicy& cp) {
-  if (m <= 0) return hipErrorInvalidValue;
+hipError_t launch_multidots(int S, const cx<T>* V, size_t ldv, int m, const cx<T>* y0,
+                            const cx<T>* y1, const cx<T>* y2, size_t n, RedBuf rb, c128* out,
+                            hipStream_t s, const Batch& z, const CachePolicy& cp) {
+  if (m <= 0 || S < 1 || S > 3) return hipErrorInvalidValue;
   const size_t clen = multidot_chunk_len(n, m + G);
   const int nch = (int)(((n + clen - 1) / clen + 7) & ~(size_t)7);
-  const dim3 g = zgrid(((m + GP - 1) / GP + 1) * nch, z);
+  const int ngroups = (m + GP - 1) / GP + (S + GP - 1) / GP;
+  const dim3 g = zgrid(ngroups * nch, z);
   const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
-  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis)
-    k_multidot2<T, true><<<g, NT, 0, s>>>(V, ldv, m, zv, yv, n, clen, rb.partials, nch, recent, z);
-  else
-    k_multidot2<T, false><<<g, NT, 0, s>>>(V, ldv, m, zv, yv, n, clen, rb.partials, nch, recent,
-                                           z);
-  k_final<<<zgrid(2 * (m + 2), z), NT, 0, s>>>(rb.partials, nch, out, 0, host_out, z);
+  const bool st = (double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis;
+#define HM_MD(SS)                                                                                 \
+  if (st) k_multidots<T, true, SS><<<g, NT, 0, s>>>(V, ldv, m, y0, y1, y2, n, clen, rb.partials, \
+                                                    nch, recent, z);                           \
+  else k_multidots<T, false, SS><<<g, NT, 0, s>>>(V, ldv, m, y0, y1, y2, n, clen, rb.partials,  \
+                                                  nch, recent, z);
+  if (S == 1) { HM_MD(1) } else if (S == 2) { HM_MD(2) } else { HM_MD(3) }
+#undef HM_MD
+  k_final<<<zgrid(S * (m + S), z), NT, 0, s>>>(rb.partials, nch, out, 0, nullptr, z);
   return hipGetLastError();
 }
 
-hipError_t launch_pair_coef(const c128* dots, c128* H, int ld, int j, c128* coef, c128* host_H,
-                            hipStream_t s, const Batch& z) {
-  k_pair_coef<<<zgrid(1, z), NT, 0, s>>>(dots, H, ld, j, coef, host_H, z);
-  return hipGetLastError();
-}
-
-// Pass B of a pair of Arnoldi steps and the norm of w' (sqrt to norm_out and
+// Pass B of S Arnoldi steps and the norm of the new Y_0 (sqrt to norm_out and
 // the pinned host_out).
 template <typename T>
-hipError_t launch_cgs_update2(cx<T>* zv, const cx<T>* yv, cx<T>* V, size_t ldv, int m,
-                              const c128* ca, const c128* cg, size_t n, RedBuf rb,
-                              c128* norm_out, c128* host_out, hipStream_t s, const Batch& z,
-                              const CachePolicy& cp) {
+hipError_t launch_updates(int S, cx<T>* y0, const cx<T>* y1, const cx<T>* y2, cx<T>* V,
+                          size_t ldv, int m, const c128* coef, int cld, size_t n, RedBuf rb,
+                          c128* norm_out, c128* host_out, hipStream_t s, const Batch& z,
+                          const CachePolicy& cp) {
+  if (S < 1 || S > 3) return hipErrorInvalidValue;
   const int nch = update_chunks(n, rb);
   const size_t clen = update_chunk_len(n);
   const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
   const dim3 g = zgrid(nch, z);
-  if ((double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis)
-    k_cgs_update2<T, true><<<g, NT, 0, s>>>(zv, yv, V, ldv, m, ca, cg, n, clen, rb.partials,
-                                            recent, z);
-  else
-    k_cgs_update2<T, false><<<g, NT, 0, s>>>(zv, yv, V, ldv, m, ca, cg, n, clen, rb.partials,
-                                             recent, z);
+  const bool st = (double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis;
+#define HM_UP(SS)                                                                                \
+  if (st) k_updates<T, true, SS><<<g, NT, 0, s>>>(y0, y1, y2, V, ldv, m, coef, cld, n, clen,    \
+                                                  rb.partials, recent, z);                     \
+  else k_updates<T, false, SS><<<g, NT, 0, s>>>(y0, y1, y2, V, ldv, m, coef, cld, n, clen,      \
+                                                rb.partials, recent, z);
+  if (S == 1) { HM_UP(1) } else if (S == 2) { HM_UP(2) } else { HM_UP(3) }
+#undef HM_UP
   k_final<<<zgrid(1, z), NT, 0, s>>>(rb.partials, nch, norm_out, 1, host_out, z);
+  return hipGetLastError();
+}
+
+int coefs_max_basis() { return kCoefMax; }
+
+hipError_t launch_coefs(int S, const c128* dots, c128* H, int ld, int j, c128* coef, int cld,
+                        c128* host_H, hipStream_t s, const Batch& z) {
+  if (j + 1 + S > kCoefMax) return hipErrorInvalidValue;
+  if (S == 1) k_coefs<1><<<zgrid(1, z), NC, 0, s>>>(dots, H, ld, j, coef, cld, host_H, z);
+  else if (S == 2) k_coefs<2><<<zgrid(1, z), NC, 0, s>>>(dots, H, ld, j, coef, cld, host_H, z);
+  else if (S == 3) k_coefs<3><<<zgrid(1, z), NC, 0, s>>>(dots, H, ld, j, coef, cld, host_H, z);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -2609,12 +2811,12 @@ hipError_t launch_check_k(const double* k, size_t n, RedBuf rb, c128* out, hipSt
   template hipError_t launch_cgs_update_partial<T>(cx<T>*, const cx<T>*, size_t, int, const c128*, \
                                                    size_t, RedBuf, hipStream_t, const Batch&,       \
                                                    const CachePolicy&);                             \
-  template hipError_t launch_multidot2<T>(const cx<T>*, size_t, int, const cx<T>*, const cx<T>*,    \
-                                          size_t, RedBuf, c128*, c128*, hipStream_t, const Batch&,  \
-                                          const CachePolicy&);                                      \
-  template hipError_t launch_cgs_update2<T>(cx<T>*, const cx<T>*, cx<T>*, size_t, int,             \
-                                            const c128*, const c128*, size_t, RedBuf, c128*, c128*, \
-                                            hipStream_t, const Batch&, const CachePolicy&);         \
+  template hipError_t launch_multidots<T>(int, const cx<T>*, size_t, int, const cx<T>*,            \
+                                          const cx<T>*, const cx<T>*, size_t, RedBuf, c128*,        \
+                                          hipStream_t, const Batch&, const CachePolicy&);          \
+  template hipError_t launch_updates<T>(int, cx<T>*, const cx<T>*, const cx<T>*, cx<T>*, size_t,   \
+                                        int, const c128*, int, size_t, RedBuf, c128*, c128*,        \
+                                        hipStream_t, const Batch&, const CachePolicy&);            \
   template hipError_t launch_stencil_scaled<T>(const OpDesc<T>&, const cx<T>*, const T*,            \
                                                const c128*, cx<T>*, cx<T>*, hipStream_t,            \
                                                const Batch&);                                       \

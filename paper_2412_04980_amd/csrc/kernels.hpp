@@ -221,27 +221,28 @@ hipError_t launch_cgs_update_partial(cx<T>* w, const cx<T>* V, size_t ldv, int m
                                      size_t n, RedBuf rb, hipStream_t s,
                                      const Batch& z = Batch(),
                                      const CachePolicy& cp = CachePolicy());
-// Two Arnoldi steps per sweep over the basis (z = M v_j, y = M z).  Pass A:
-// out[r (m + 2) + i] = (left i)^H (right r) for the left vectors V_0..V_{m-1},
-// z, y and the right vectors z (r = 0), y (r = 1), also to host_out.  Needs
-// 2 (m + 2) kMaxChunks partials.
+// S Arnoldi steps per pair of passes over the basis (S = 1, 2, 3; Y_0 = M v_j,
+// Y_{k+1} = M Y_k).  Pass A: out[r (m + S) + i] = (left i)^H Y_r for the left
+// vectors V_0..V_{m-1}, Y_0..Y_{S-1}; needs S (m + S) kMaxChunks partials.
 template <typename T>
-hipError_t launch_multidot2(const cx<T>* V, size_t ldv, int m, const cx<T>* zv, const cx<T>* yv,
-                            size_t n, RedBuf rb, c128* out, c128* host_out, hipStream_t s,
-                            const Batch& z = Batch(), const CachePolicy& cp = CachePolicy());
-// Between the passes (one block per member): from pass A's dots at `dots` and
-// the Hessenberg columns 0..j-1 of H (stride ld), columns j and j+1 (rows
-// 0..j+1) to H and to the pinned host_H, and pass B's coefficients (ca at
-// coef[0..j+1], cg at coef[ld..ld+j+1]).
-hipError_t launch_pair_coef(const c128* dots, c128* H, int ld, int j, c128* coef, c128* host_H,
-                            hipStream_t s, const Batch& z = Batch());
-// Pass B: V_m = ca[m] z + sum_{i<m} ca[i] V_i ; z <- ca[m] y + cg[m] z +
-// sum_{i<m} cg[i] V_i ; norm_out[0] = host_out[0] = ||z|| (real part).
+hipError_t launch_multidots(int S, const cx<T>* V, size_t ldv, int m, const cx<T>* y0,
+                            const cx<T>* y1, const cx<T>* y2, size_t n, RedBuf rb, c128* out,
+                            hipStream_t s, const Batch& z = Batch(),
+                            const CachePolicy& cp = CachePolicy());
+// Between the passes (one block per member): Arnoldi in the coordinates of
+// [V_0..V_j, Y] from pass A's dots; columns j..j+S-1 of H (stride ld) and of
+// the pinned host_H, except the last subdiagonal entry; pass B's coefficient
+// rows at coef, cld apart.  j + 1 + S <= coefs_max_basis().
+int coefs_max_basis();
+hipError_t launch_coefs(int S, const c128* dots, c128* H, int ld, int j, c128* coef, int cld,
+                        c128* host_H, hipStream_t s, const Batch& z = Batch());
+// Pass B: V_{m+t} (t < S - 1) and the new Y_0 from the coefficient rows, with
+// norm_out[0] = host_out[0] = ||Y_0|| (real part).
 template <typename T>
-hipError_t launch_cgs_update2(cx<T>* zv, const cx<T>* yv, cx<T>* V, size_t ldv, int m,
-                              const c128* ca, const c128* cg, size_t n, RedBuf rb,
-                              c128* norm_out, c128* host_out, hipStream_t s,
-                              const Batch& z = Batch(), const CachePolicy& cp = CachePolicy());
+hipError_t launch_updates(int S, cx<T>* y0, const cx<T>* y1, const cx<T>* y2, cx<T>* V,
+                          size_t ldv, int m, const c128* coef, int cld, size_t n, RedBuf rb,
+                          c128* norm_out, c128* host_out, hipStream_t s,
+                          const Batch& z = Batch(), const CachePolicy& cp = CachePolicy());
 // sum of the partials written by launch_cgs_update_partial over a vector of length n
 hipError_t launch_update_norm_final(size_t n, RedBuf rb, c128* out, hipStream_t s,
                                     c128* host_out = nullptr, const Batch& z = Batch());

@@ -72,8 +72,9 @@ struct KrylovWS {
   void* w2 = nullptr;  // GMRES: second work vector (ping-pong with w)
   c128* h = nullptr;   // device column / scalars, cap + 2
   c128* H = nullptr;   // GMRES: device Hessenberg, cap columns of stride cap + 2
-  c128* D = nullptr;   // paired steps: pass A's dots, 2 (cap + 2)
-  c128* C = nullptr;   // paired steps: pass B's coefficients, 2 (cap + 2)
+  void* w3 = nullptr;  // S-step GMRES: third work vector
+  c128* D = nullptr;   // S-step GMRES: pass A's dots, 3 (cap + 4)
+  c128* C = nullptr;   // S-step GMRES: pass B's coefficient rows, 3 (cap + 4)
 };
 
 struct MGLevel {
@@ -227,7 +228,7 @@ struct hm_problem {
   CachePolicy cache;
   // small coarse levels solved by one workgroup per member (hm_set_small_krylov)
   bool small_krylov = true;
-  int krylov_pairs = HM_PAIRS_ON;     // two Arnoldi steps per basis read (hm_set_krylov_pairs)
+  int krylov_steps = HM_KRYLOV_STEPS_MAX;   // Arnoldi steps per two basis passes
   // optional per-kernel-class timing with HIP events on the problem's stream
   unsigned timing_mask = 0;
   int timing_every = 1;                 // bracket every n-th launch of a class
@@ -486,33 +487,31 @@ static void gmres_small(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
   }
 }
 
-// The same GMRES with classical Gram-Schmidt, two Arnoldi steps per read of
-// the basis.  For the pair (j, j+1), z = M v_j and y = M z.  Pass A takes
-// [V_0..V_j, z, y]^H [z, y] in one read of the basis, which gives step j's
-// column a = V^H z with b_j^2 = z^H z - |a|^2 (b_j = ||z - V a||), and step
-// j+1's column without forming z' = M v_{j+1}: the Arnoldi relation
-// M V_{0..j-1} = V_{0..j} H makes M V a = V g + a_j z (g = H a_{0..j-1}), so
-//   V^H z' = (c - g - a_j a) / b_j,   v_{j+1}^H z' = (z^H y - a^H c) / b_j^2 - a_j
-// with c = V^H y.  Pass B forms v_{j+1} = (z - V a) / b_j and
-// w' = z' - [V, v_{j+1}] h' in one read of the basis, with ||w'||.  In exact
-// arithmetic these are the iterates of one-step classical Gram-Schmidt; the
-// basis is read once per step instead of twice.
-// The columns and pass B's coefficients are formed on the device between the
-// passes (launch_pair_coef), so a pair runs without the host: the host reads
-// the columns of a pair from the pinned mirror for its stopping tests while
-// the next pair runs.  Work enqueued past a member's last step writes only
-// vectors and columns its solution does not use.
+// The same GMRES with S Arnoldi steps (S = 2, 3; the last block of a solve may
+// be shorter) per two reads of the basis.
+// For the block of steps j..j+S-1, Y_0 = M v_j and Y_{k+1} = M Y_k.  Pass A
+// takes [V_0..V_j, Y]^H Y in one read of the basis; with it, classical
+// Gram-Schmidt runs in the coordinates of [V_0..V_j, Y] on the device
+// (launch_coefs: M acts on V through the Hessenberg columns already formed),
+// giving the columns j..j+S-2 whole and column j+S-1 up to its subdiagonal
+// entry; pass B forms v_{j+1}..v_{j+S-1} and the last step's w in one read of
+// the basis, with ||w||.  In exact arithmetic these are the iterates of
+// one-step classical Gram-Schmidt.  The host reads the columns of a block
+// from the pinned mirror while the next block runs; work enqueued past a
+// member's last step writes only vectors and columns its solution does not
+// use.
 template <typename T>
-static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
-                        int maxit, double tol, int kind, const cx<T>* b, cx<T>* x) {
+static void gmres_sstep(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, KrylovWS& ws,
+                        int maxit, double tol, int kind, int S, const cx<T>* b, cx<T>* x) {
   hm_problem* p = c.p;
   const size_t N = ws.N;
   cx<T>* V = (cx<T>*)ws.V;
-  cx<T>* wb[2] = {(cx<T>*)ws.w, (cx<T>*)ws.w2};
+  cx<T>* wb[3] = {(cx<T>*)ws.w, (cx<T>*)ws.w2, (cx<T>*)ws.w3};
   member_norms<T>(c, a0, b, N, ws.h);
   std::vector<MemberKrylov> st = start_members<T>(c, a0, kind, maxit, tol, ws.cap, x, N);
   if (st.empty()) return;
   const size_t ld = (size_t)ws.cap + 2;
+  const int cld = ws.cap + 4;
   for (const auto& m : st)
     if ((size_t)(m.maxit + 2) * ld > p->host_H_cap) throw ArgError("Hessenberg mirror too small");
   const double es = (double)sizeof(cx<T>);
@@ -520,94 +519,103 @@ static void gmres_pairs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, 
   std::vector<int> run;
   for (size_t t = 0; t < st.size(); ++t)
     if (st[t].maxit > 0) run.push_back((int)t);
-  // the pair at step j for the members who: v_j = src / s_j with z = M v_j,
-  // y = M z, pass A, the columns and coefficients, pass B with ||w'|| (pass B
-  // also when the member's step limit ends at step j: its output is not used)
-  const cx<T>* src = b;
-  auto enqueue_pair = [&](int j, const std::vector<int>& who) {
+  // steps of the block at j: S, fewer only where the workspace ends.  The
+  // blocks do not depend on a member's step limit (steps past it are not
+  // used), so a member's rounding is the same alone and in a batch.
+  auto block_len = [&](int j) { return std::min(S, ws.cap - j); };
+  // source of the next block: b, then the buffer that holds the last block's w
+  // (index si); the block's Y_0 never takes the source's buffer, Y_1 may (the
+  // source is consumed by the first apply)
+  int si = -1;
+  auto enqueue_block = [&](int j, int s, const std::vector<int>& who) {
     const Batch z = members(c, members_of(st, who));
     const double nm = (double)who.size();
     const int m = j + 1;
     const c128* sc = j == 0 ? ws.h : ws.H + (size_t)(j - 1) * ld + j;
-    cx<T>* zb = src == wb[0] ? wb[1] : wb[0];
-    cx<T>* yb = src == b ? wb[1] : (cx<T>*)src;         // src is consumed by the first apply
+    const cx<T>* src = si < 0 ? b : wb[si];
+    const int i0 = si < 0 ? 0 : (si + 1) % 3;
+    cx<T>* y[3] = {wb[i0], si < 0 ? wb[1] : wb[si], si < 0 ? wb[2] : wb[(si + 2) % 3]};
     timed(p, tk_op, nm * 3.5 * es * N, [&] {
-      return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, zb, p->s, z);
+      return launch_stencil_scaled<T>(op, src, k, sc, V + (size_t)j * N, y[0], p->s, z);
     });
-    timed(p, tk_op, nm * 2.5 * es * N, [&] {
-      return launch_stencil<T>(op, ST_APPLY, zb, k, nullptr, yb, T(0), p->s, z);
-    });
-    timed(p, HM_TK_CGS_DOT, nm * (m + 2) * es * N, [&] {
-      return launch_multidot2<T>(V, N, m, zb, yb, N, rbuf(p, N), ws.D, nullptr, p->s, z,
+    for (int r = 1; r < s; ++r)
+      timed(p, tk_op, nm * 2.5 * es * N, [&] {
+        return launch_stencil<T>(op, ST_APPLY, y[r - 1], k, nullptr, y[r], T(0), p->s, z);
+      });
+    timed(p, HM_TK_CGS_DOT, nm * (m + s) * es * N, [&] {
+      return launch_multidots<T>(s, V, N, m, y[0], y[1], y[2], N, rbuf(p, N), ws.D, p->s, z,
                                  p->cache);
     });
-    HM_CHECK(launch_pair_coef(ws.D, ws.H, (int)ld, j, ws.C, p->host_H, p->s, z));
-    timed(p, HM_TK_CGS_UPDATE, nm * (m + 4) * es * N, [&] {
-      return launch_cgs_update2<T>(zb, yb, V, N, m, ws.C, ws.C + ld, N, rbuf(p, N),
-                                   ws.H + (size_t)(j + 1) * ld + j + 2,
-                                   p->host_H + (size_t)(j + 1) * ld + j + 2, p->s, z, p->cache);
+    HM_CHECK(launch_coefs(s, ws.D, ws.H, (int)ld, j, ws.C, cld, p->host_H, p->s, z));
+    timed(p, HM_TK_CGS_UPDATE, nm * (m + 2 * s) * es * N, [&] {
+      return launch_updates<T>(s, y[0], y[1], y[2], V, N, m, ws.C, cld, N, rbuf(p, N),
+                               ws.H + (size_t)(j + s - 1) * ld + j + s,
+                               p->host_H + (size_t)(j + s - 1) * ld + j + s, p->s, z, p->cache);
     });
+    si = i0;
   };
-  // pairs enqueued one ahead of the host's stopping tests, except for members
-  // expected to meet the tolerance within the pair (the estimates fall about
-  // geometrically: est_{j+1} ~ est_j^2 / est_{j-1})
-  auto ahead_of = [&](int j, const std::vector<int>& who) {
+  // blocks enqueued one ahead of the host's stopping tests, except for members
+  // expected to meet the tolerance within the block (the estimates fall about
+  // geometrically)
+  auto ahead_of = [&](int j, int s, const std::vector<int>& who) {
     std::vector<int> out;
     for (int t : who) {
       const MemberKrylov& q = st[t];
-      const bool soon = q.tol >= 0 && q.est1 > 0 && q.est2 > 0 &&
-                        q.est1 * (q.est1 / q.est2) * (q.est1 / q.est2) <= q.tol * q.beta;
-      if (j + 2 < q.maxit && !soon) out.push_back(t);
+      double f = q.est1;
+      if (q.est1 > 0 && q.est2 > 0)
+        for (int r = 0; r < s; ++r) f *= q.est1 / q.est2;
+      const bool soon = q.tol >= 0 && q.est1 > 0 && q.est2 > 0 && f <= q.tol * q.beta;
+      if (j + s < q.maxit && !soon) out.push_back(t);
     }
     return out;
   };
+  int s = 0;
   if (!run.empty()) {
-    enqueue_pair(0, run);
+    s = block_len(0);
+    enqueue_block(0, s, run);
     HM_CHECK(hipEventRecord(p->col_ev[0], p->s));
   }
-  for (int j = 0; !run.empty(); j += 2) {
-    // the next pair for the members that will probably go on
-    std::vector<int> spec = ahead_of(j, run);
-    const cx<T>* src_next = src == wb[0] ? wb[1] : wb[0];   // z of pair j holds w'
+  for (int j = 0; !run.empty();) {
+    // the next block for the members that will probably go on
+    std::vector<int> spec = ahead_of(j, s, run);
+    const int si_next = si;                             // holds the w of block j
+    const int s_next = block_len(j + s);
     if (!spec.empty()) {
-      src = src_next;
-      enqueue_pair(j + 2, spec);
+      enqueue_block(j + s, s_next, spec);
       HM_CHECK(hipEventRecord(p->col_ev[1], p->s));
     }
-    // the columns of pair j: event col_ev[0] follows every launch of pair j
+    // the columns of block j: event col_ev[0] follows every launch of block j
     HM_CHECK(hipEventSynchronize(p->col_ev[0]));
     std::vector<int> next;
     for (int t : run) {
       MemberKrylov& q = st[t];
-      const c128* hc = c.mem[q.i]->host_H + (size_t)j * ld;
-      double est = q.lsq.add(j, hc);
-      q.steps = j + 1;
-      q.est2 = q.est1;
-      q.est1 = est;
-      bool broke = hc[j + 1].re <= 1e-14 * q.beta;
-      if (broke || (q.tol >= 0 && est <= q.tol * q.beta) || j + 1 >= q.maxit) continue;
-      const c128* hc1 = hc + ld;
-      est = q.lsq.add(j + 1, hc1);
-      q.steps = j + 2;
-      q.est2 = q.est1;
-      q.est1 = est;
-      broke = hc1[j + 2].re <= 1e-14 * q.beta;
-      if (broke || (q.tol >= 0 && est <= q.tol * q.beta) || j + 2 >= q.maxit) continue;
-      next.push_back(t);
+      bool go = true;
+      for (int r = 0; r < s && go; ++r) {
+        const c128* hc = c.mem[q.i]->host_H + (size_t)(j + r) * ld;
+        const double est = q.lsq.add(j + r, hc);
+        q.steps = j + r + 1;
+        q.est2 = q.est1;
+        q.est1 = est;
+        const bool broke = hc[j + r + 1].re <= 1e-14 * q.beta;
+        if (broke || (q.tol >= 0 && est <= q.tol * q.beta) || j + r + 1 >= q.maxit) go = false;
+      }
+      if (go) next.push_back(t);
     }
-    // members that go on without an enqueued pair j + 2 get it now
+    // members that go on without an enqueued block get it now (from block j's w)
     std::vector<int> late;
     for (int t : next)
       if (std::find(spec.begin(), spec.end(), t) == spec.end()) late.push_back(t);
     if (!late.empty()) {
-      src = src_next;
-      enqueue_pair(j + 2, late);
+      si = si_next;                                     // the same buffers as spec's block
+      enqueue_block(j + s, s_next, late);
       HM_CHECK(hipEventRecord(p->col_ev[1], p->s));
     }
     std::swap(p->col_ev[0], p->col_ev[1]);
     run.swap(next);
+    j += s;
+    s = s_next;
   }
-  wait_stream(c);                                        // timing events of the pairs
+  wait_stream(c);                                        // timing events of the blocks
   finish_members<T>(c, st, kind, V, N, x, 0);
 }
 
@@ -619,12 +627,13 @@ static void gmres_cgs(Ctx& c, const Act& a0, const OpDesc<T>& op, const T* k, Kr
     gmres_small<T>(c, a0, op, k, ws, maxit, tol, kind, b, x);
     return;
   }
-  // the paired steps take step j+1's column from relations that hold to the
-  // basis's orthogonality: FP64 levels only (with an FP32 basis the k = 200
-  // solve took one outer step more and moved 2e-5 from the FP64 solution)
-  const bool pairs = p->krylov_pairs == HM_PAIRS_ON;
-  if (pairs && p->cfg.cslp_orth == HM_ORTH_CLASSICAL && sizeof(T) == sizeof(double)) {
-    gmres_pairs<T>(c, a0, op, k, ws, maxit, tol, kind, b, x);
+  // the blocks of steps take the later steps' columns from relations that hold
+  // to the basis's orthogonality: FP64 levels only (with an FP32 basis the
+  // k = 200 solve took one outer step more and moved 2e-5 from the FP64
+  // solution)
+  if (p->krylov_steps > 1 && p->cfg.cslp_orth == HM_ORTH_CLASSICAL &&
+      sizeof(T) == sizeof(double) && ws.cap + 1 + p->krylov_steps <= coefs_max_basis()) {
+    gmres_sstep<T>(c, a0, op, k, ws, maxit, tol, kind, p->krylov_steps, b, x);
     return;
   }
   const size_t N = ws.N;
@@ -1216,10 +1225,11 @@ static void plan(hm_problem* p, Carver& cv) {
         H.gm.V = cv.take<char>((size_t)(H.maxit + 1) * last.N * es);
         H.gm.w = cv.take<char>(last.N * es);
         H.gm.w2 = cv.take<char>(last.N * es);
+        H.gm.w3 = cv.take<char>(last.N * es);
         H.gm.h = cv.take<c128>(H.maxit + 2);
         H.gm.H = cv.take<c128>((size_t)(H.maxit + 2) * (H.maxit + 2));
-        H.gm.D = cv.take<c128>(2 * (size_t)(H.maxit + 2));
-        H.gm.C = cv.take<c128>(2 * (size_t)(H.maxit + 2));
+        H.gm.D = cv.take<c128>(3 * (size_t)(H.maxit + 4));
+        H.gm.C = cv.take<c128>(3 * (size_t)(H.maxit + 4));
         mmax = std::max(mmax, H.maxit + 2);
         p->host_H_cap = std::max(p->host_H_cap, (size_t)(H.maxit + 2) * (H.maxit + 2));
       }
@@ -1230,10 +1240,11 @@ static void plan(hm_problem* p, Carver& cv) {
       D.cslp.V = cv.take<char>((size_t)(D.cslp_maxit + 1) * D.N * es);
       D.cslp.w = cv.take<char>(D.N * es);
       D.cslp.w2 = cv.take<char>(D.N * es);
+      D.cslp.w3 = cv.take<char>(D.N * es);
       D.cslp.h = cv.take<c128>(D.cslp_maxit + 2);
       D.cslp.H = cv.take<c128>((size_t)(D.cslp_maxit + 2) * (D.cslp_maxit + 2));
-      D.cslp.D = cv.take<c128>(2 * (size_t)(D.cslp_maxit + 2));
-      D.cslp.C = cv.take<c128>(2 * (size_t)(D.cslp_maxit + 2));
+      D.cslp.D = cv.take<c128>(3 * (size_t)(D.cslp_maxit + 4));
+      D.cslp.C = cv.take<c128>(3 * (size_t)(D.cslp_maxit + 4));
       mmax = std::max(mmax, D.cslp_maxit + 2);
       p->host_H_cap = std::max(p->host_H_cap, (size_t)(D.cslp_maxit + 2) * (D.cslp_maxit + 2));
     }
@@ -1255,8 +1266,8 @@ static void plan(hm_problem* p, Carver& cv) {
     p->pin_v = cv.take<c64>(D1.N);
     p->pin_x = cv.take<c64>(D1.N);
   }
-  // two Arnoldi steps per sweep take 2 (m + 2) dots per reduction
-  p->rb.partials = cv.take<c128>((size_t)kMaxChunks * (2 * mmax + 4));
+  // three Arnoldi steps per sweep take 3 (m + 3) dots per reduction
+  p->rb.partials = cv.take<c128>((size_t)kMaxChunks * (3 * mmax + 9));
   p->rb.nchunks = 0;   // chosen per reduction from its length (rbuf)
   p->scal = cv.take<c128>(16);
   p->coef_cap = mmax + 2;
@@ -2007,9 +2018,9 @@ hm_status hm_set_small_krylov(hm_problem* p, int enable) {
   return HM_OK;
 }
 
-hm_status hm_set_krylov_pairs(hm_problem* p, int mode) {
-  if (!p || (mode != HM_PAIRS_OFF && mode != HM_PAIRS_ON)) return HM_ERR_ARG;
-  p->krylov_pairs = mode;
+hm_status hm_set_krylov_steps(hm_problem* p, int steps) {
+  if (!p || steps < 1 || steps > HM_KRYLOV_STEPS_MAX) return HM_ERR_ARG;
+  p->krylov_steps = steps;
   return HM_OK;
 }
 

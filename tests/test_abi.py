@@ -160,11 +160,12 @@ def test_csr_spmv_binding_rejects_x_of_the_wrong_length():
         hm.csr_spmv(rp, ci, va, torch.zeros(4, dtype=torch.complex128), ncols=6)
 
 
-def test_krylov_pairs_modes():
+def test_krylov_steps_setter():
     import paper_2412_04980_amd as hm
-    assert (hm.PAIRS_OFF, hm.PAIRS_ON) == (0, 1)
+    assert hm.KRYLOV_STEPS_MAX == 3
     # a null problem is rejected without touching the device
-    assert hm._lib.hm_set_krylov_pairs(None, hm.PAIRS_ON) == hm.HM_ERR_ARG
+    for steps in (1, hm.KRYLOV_STEPS_MAX):
+        assert hm._lib.hm_set_krylov_steps(None, steps) == hm.HM_ERR_ARG
 
 
 def test_set_basis_cache_rejects_bad_arguments_on_the_host():
