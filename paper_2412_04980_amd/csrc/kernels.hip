@@ -2619,12 +2619,40 @@ hipError_t launch_multidots(int S, const cx<T>* V, size_t ldv, int m, const cx<T
                             const cx<T>* y1, const cx<T>* y2, size_t n, RedBuf rb, c128* out,
                             hipStream_t s, const Batch& z, const CachePolicy& cp) {
   if (m <= 0 || S < 1 || S > 3) return hipErrorInvalidValue;
-  const size_t clen = multidot_chunk_len(n, m + G);
-  const int nch = (int)(((n + clen - 1) / clen + 7) & ~(size_t)7);
   const int ngroups = (m + GP - 1) / GP + (S + GP - 1) / GP;
+  const bool st = (double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis;
+  static int resident[2][4] = {};
+  int& res = resident[st ? 1 : 0][S];
+  if (res == 0) {
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const void* fn = nullptr;
+    if (S == 1) fn = st ? (const void*)k_multidots<T, true, 1> : (const void*)k_multidots<T, false, 1>;
+    else if (S == 2) fn = st ? (const void*)k_multidots<T, true, 2> : (const void*)k_multidots<T, false, 2>;
+    else fn = st ? (const void*)k_multidots<T, true, 3> : (const void*)k_multidots<T, false, 3>;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, 0);
+    if (e != hipSuccess) return e;
+    res = std::max(8, per_cu * ncu);
+  }
+  // chunks: whole rounds of the resident blocks (a partial last round leaves
+  // most of the device idle while it runs), as few rounds as keep the Y chunks
+  // of the blocks resident on one XCD within about 3 MB of its 4 MB L2 (every
+  // group of a chunk re-reads them).  On the 1150 x 364 coarsest level of the
+  // 4597 x 1453 layered problem 1.8 rounds became one (967 -> 918 ms per
+  // solve); the 4097^2 problem is unchanged.  The chunks do not depend on the
+  // number of batch members, so a member's sums are those of its solve alone.
+  const int slots = res;
+  const double ybytes = (double)S * sizeof(cx<T>);
+  const double nmin = (double)n * ybytes * slots / (8.0 * ngroups * 3.0e6);
+  const int rounds = std::max(1, (int)std::ceil(ngroups * nmin / slots));
+  int target = std::max(8, (int)((long long)rounds * slots / ngroups) / 8 * 8);
+  size_t clen = (n + target - 1) / target;
+  clen = (clen + 63) / 64 * 64;
+  while ((n + clen - 1) / clen > (size_t)kMaxChunks) clen += 64;
+  const int nch = (int)(((n + clen - 1) / clen + 7) & ~(size_t)7);
   const dim3 g = zgrid(ngroups * nch, z);
   const int recent = (int)(cp.recent / ((double)n * sizeof(cx<T>)));
-  const bool st = (double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis;
 #define HM_MD(SS)                                                                                 \
   if (st) k_multidots<T, true, SS><<<g, NT, 0, s>>>(V, ldv, m, y0, y1, y2, n, clen, rb.partials, \
                                                     nch, recent, z);                           \
