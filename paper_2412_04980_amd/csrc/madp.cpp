@@ -20,6 +20,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/helmdefl.h"
@@ -99,6 +100,11 @@ struct MGHier {
   c128* tmpB = nullptr;
   KrylovWS gm;                // coarsest GMRES otherwise
   int maxit = 0;
+  // mixed mode (FP32 levels 1-2): the coarsest GMRES in FP64, like the dense
+  // inverse, on cast copies of its right-hand side and solution
+  bool gm64 = false;
+  void* b64 = nullptr;
+  void* x64 = nullptr;
   // with a dense coarsest solve the whole cycle is a fixed kernel sequence on
   // fixed buffers: captured as a HIP graph (input = the level's r~ buffer), one
   // per set of batch members (bit mask) that runs it
@@ -750,6 +756,17 @@ static const cx<T>* mg_cycle(Ctx& c, const Act& a, DefLevel& D, int q, const cx<
       HM_CHECK(launch_dense_matvec<T>((const c128*)H.inv, (int)m.N, b, x, p->s, z));
       return x;
     }
+    if constexpr (std::is_same<T, float>::value) {
+      if (H.gm64) {
+        c128* b64 = (c128*)H.b64;
+        c128* x64 = (c128*)H.x64;
+        HM_CHECK(launch_convert<float, double>(b, b64, m.N, p->s, z));
+        gmres_cgs<double>(c, a, m.op64, mgk<double>(D, q), H.gm, H.maxit, p->cfg.tol_cslp, K_MGC,
+                          b64, x64);
+        HM_CHECK(launch_convert<double, float>(x64, x, m.N, p->s, z));
+        return x;
+      }
+    }
     gmres_cgs<T>(c, a, op, k, H.gm, H.maxit, p->cfg.tol_cslp, K_MGC, b, x);
     return x;
   }
@@ -1220,12 +1237,18 @@ static void plan(hm_problem* p, Carver& cv) {
         H.tmpB = cv.take<c128>(last.N * last.N);
       } else {
         H.maxit = krylov_maxit(last.N, c.maxit_coef);
+        H.gm64 = !D.dbl && c.precision == HM_MIXED_FP32;
+        const size_t ges = H.gm64 ? sizeof(c128) : es;
+        if (H.gm64) {
+          H.b64 = cv.take<char>(last.N * ges);
+          H.x64 = cv.take<char>(last.N * ges);
+        }
         H.gm.cap = H.maxit;
         H.gm.N = last.N;
-        H.gm.V = cv.take<char>((size_t)(H.maxit + 1) * last.N * es);
-        H.gm.w = cv.take<char>(last.N * es);
-        H.gm.w2 = cv.take<char>(last.N * es);
-        H.gm.w3 = cv.take<char>(last.N * es);
+        H.gm.V = cv.take<char>((size_t)(H.maxit + 1) * last.N * ges);
+        H.gm.w = cv.take<char>(last.N * ges);
+        H.gm.w2 = cv.take<char>(last.N * ges);
+        H.gm.w3 = cv.take<char>(last.N * ges);
         H.gm.h = cv.take<c128>(H.maxit + 2);
         H.gm.H = cv.take<c128>((size_t)(H.maxit + 2) * (H.maxit + 2));
         H.gm.D = cv.take<c128>(3 * (size_t)(H.maxit + 4));
