@@ -71,7 +71,9 @@ typedef enum { HM_BC_SOMMERFELD = 0, HM_BC_DIRICHLET = 1 } hm_bc;
  * HM_MIXED_FP32 keeps the coarsest problem (the solve on the deepest deflation
  * level, Sec. 4.1) in FP64; HM_MIXED_FP32_ALL runs it in FP32 as well.
  * Reductions accumulate in FP64 throughout, and the dense coarsest multigrid
- * inverse is applied in FP64 in every mode. */
+ * inverse is applied in FP64 in every mode.  In HM_MIXED_FP32 the coarsest
+ * multigrid level of levels 1-2, where it is too large for the dense inverse,
+ * is solved by FP64 GMRES on cast copies of its right-hand side and solution. */
 typedef enum {
   HM_FP64 = 0,          /* every step in complex128                                   */
   HM_MIXED_FP32 = 1,    /* preconditioner levels 1-2 in complex64 with FP32 arithmetic;
