@@ -2621,16 +2621,17 @@ hipError_t launch_multidots(int S, const cx<T>* V, size_t ldv, int m, const cx<T
   if (m <= 0 || S < 1 || S > 3) return hipErrorInvalidValue;
   const int ngroups = (m + GP - 1) / GP + (S + GP - 1) / GP;
   const bool st = (double)(m + 1) * (double)n * sizeof(cx<T>) > cp.basis;
-  static int resident[2][4] = {};
-  int& res = resident[st ? 1 : 0][S];
+  // resident blocks of the plain-load instance for both load forms, so the
+  // chunks (and the sums) do not depend on the load form
+  static int resident[4] = {};
+  int& res = resident[S];
   if (res == 0) {
     int dev = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const void* fn = nullptr;
-    if (S == 1) fn = st ? (const void*)k_multidots<T, true, 1> : (const void*)k_multidots<T, false, 1>;
-    else if (S == 2) fn = st ? (const void*)k_multidots<T, true, 2> : (const void*)k_multidots<T, false, 2>;
-    else fn = st ? (const void*)k_multidots<T, true, 3> : (const void*)k_multidots<T, false, 3>;
+    const void* fn = S == 1   ? (const void*)k_multidots<T, false, 1>
+                     : S == 2 ? (const void*)k_multidots<T, false, 2>
+                              : (const void*)k_multidots<T, false, 3>;
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, 0);
     if (e != hipSuccess) return e;
     res = std::max(8, per_cu * ncu);
